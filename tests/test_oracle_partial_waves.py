@@ -1,0 +1,60 @@
+"""Pins of the partial-wave reference (Section 4): library Bessel functions,
+the optical theorem, the Born limit and the hard-sphere limit."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import partial_waves as pw
+
+
+@pytest.mark.parametrize("x", [0.3, 2.0, 4.712, 7.3, 18.85, 40.0])
+def test_bessel_functions_match_library(x):
+    l = np.arange(31)
+    assert np.allclose(pw.sph_jn(30, x), special.spherical_jn(l, x), rtol=1e-11, atol=1e-300)
+    yy = special.spherical_yn(l[:20], x)
+    assert np.allclose(pw.sph_yn(19, x), yy, rtol=1e-11)
+    assert np.allclose(pw.sph_in(30, x), special.spherical_in(l, x), rtol=1e-11, atol=1e-300)
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0, -0.5, -1.0, 2.0])
+def test_optical_theorem(s):
+    k = 1.0
+    a = 4 * math.pi
+    V0 = s * k * k / 2
+    sigma = pw.total_cross_section(k, a, V0)
+    f0 = pw.amplitude(k, a, V0, 0.0)
+    assert 4 * math.pi / k * f0.imag == pytest.approx(sigma, rel=1e-12)
+
+
+def test_born_limit():
+    k, a = 2.0, 1.3
+    th = np.linspace(0.1, 3.0, 9)
+    for eps in (1e-3, 1e-4):
+        f = pw.amplitude(k, a, eps, th)
+        fb = pw.born_amplitude(k, a, eps, th)
+        assert np.abs(f - fb).max() < 30 * eps ** 2 + 1e-14
+
+
+def test_hard_sphere_limit():
+    k, a = 1.7, 1.1
+    # a barrier far above E: beta_l ~ q, so tan d_l -> j_l/y_l with an O(1/q)
+    # error; Richardson extrapolation over q and 2q removes the first order
+    ref = special.spherical_jn(np.arange(7), k * a) / special.spherical_yn(np.arange(7), k * a)
+    t = []
+    for qa in (100.0, 200.0):
+        q = qa / a
+        t.append(np.tan(pw.phase_shifts(k, a, k * k / 2 + q * q / 2, 6)))
+    err1 = np.abs(t[0] / ref - 1)
+    err_ex = np.abs((2 * t[1] - t[0]) / ref - 1)
+    assert err1.max() < 0.15
+    assert (err_ex < 0.1 * err1).all()
+
+
+def test_equal_energy_branch_is_continuous():
+    k, a = 1.3, 2.0
+    E = k * k / 2
+    d0 = pw.phase_shifts(k, a, E, 8)
+    for V0 in (E * (1 - 1e-9), E * (1 + 1e-9)):
+        assert np.allclose(np.tan(pw.phase_shifts(k, a, V0, 8)), np.tan(d0), rtol=1e-6, atol=1e-8)
