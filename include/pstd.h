@@ -1,0 +1,161 @@
+/*
+ * libpstd — C ABI of the MI355X PSTD quantum-scattering hot path.
+ *
+ * The library advances the Schroedinger wave function of a scattering problem
+ * on a 3D grid with the pseudo-spectral leapfrog of Eq. PSTDupdating
+ * (Section 2.5 of Chen, arXiv 2403.04053): per-axis spectral kinetic term,
+ * potential term, total-field/scattered-field plane-wave source (Section
+ * 2.2.2), masking absorber (Section 2.1, Eq. Gamma).  During a time window it
+ * accumulates the running DFT of psi and of its normal derivative on the six
+ * faces of a virtual box (Section 3.3, Eqs. psiphasor, dpsiphasor), and
+ * projects those phasors to distant points or to far-field directions with
+ * the semi-analytic surface integral of Section 3.2 (Eqs. bottomPsi_lm ...
+ * Psi).
+ *
+ * Conventions (every call):
+ *  - grid index (i, j, k) along (x, y, z) is the physical point
+ *    ((i - Nx/2) hx, (j - Ny/2) hy, (k - Nz/2) hz); 3D arrays are [k][j][i]
+ *    (x fastest), n_cells = Nx*Ny*Nz;
+ *  - complex64 = interleaved float (re, im); complex128 = interleaved double;
+ *  - a pointer named *_dev is device memory on the device current when the
+ *    solver was created; *_host is host memory.  The caller owns every pointer
+ *    it passes; the library keeps none after the call returns;
+ *  - every call that launches work enqueues it on the stream given at
+ *    creation (0 = the null stream) and returns without synchronising, except
+ *    where the description says it synchronises;
+ *  - one solver is used by one host thread at a time; solvers are independent;
+ *  - no call aborts: each returns a pstd_status, and pstd_last_error() gives
+ *    a message for the last failing call on that solver.
+ */
+#ifndef PSTD_H
+#define PSTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pstd_status {
+    PSTD_OK = 0,
+    PSTD_EINVAL = 1,       /* bad argument, size, index or geometry */
+    PSTD_EUNSTABLE = 2,    /* dt above the bound of Eq. PSTDstability */
+    PSTD_ENONFINITE = 3,   /* NaN/Inf in an input or in the wave function */
+    PSTD_ENOMEM = 4,       /* device allocation failed */
+    PSTD_EHIP = 5,         /* a HIP runtime call failed */
+    PSTD_ESTATE = 6,       /* call not valid in the solver's current state */
+    PSTD_EUNSUPPORTED = 7  /* grid length without a compiled FFT pass */
+} pstd_status;
+
+/*
+ * Problem description (physical units unless stated).  Section 2 defines the
+ * internal model: absorbing layer (Section 2.1), TF/SF taper (Eq. zeta_y),
+ * plane-wave incidence of wavenumber k0 along the direction of Eq. khat,
+ * virtual box (Section 3.1).
+ */
+typedef struct pstd_problem {
+    int32_t n[3];            /* FFT grid points per axis; even */
+    double  h[3];            /* grid spacing per axis */
+    double  hbar, mass;      /* > 0 */
+    double  k0;              /* central wavenumber of the incident wave, > 0 */
+    double  theta, phi;      /* incident direction, Eq. khat (radians) */
+    int32_t abc_cells[3];    /* absorbing-layer width per axis, cells */
+    double  abc_U0;          /* Eq. Poshcl-Teller height, units of E0/hbar */
+    double  abc_alpha;       /* Eq. Poshcl-Teller decay, per cell */
+    int32_t tfsf[3][4];      /* y0 < y1 <= y2 < y3 per axis, Eq. zeta_y */
+    double  v_max;           /* bound on |V| used for the step (energy) */
+    double  dt;              /* time step; 0 selects 0.9 of the critical one */
+    int32_t force_dt;        /* 1: accept dt above the bound */
+    double  ramp_periods;    /* switch-on length of the incident wave */
+    int64_t dft_begin;       /* surface-DFT window [dft_begin, dft_end) */
+    int64_t dft_end;
+    int32_t surf_lo[3];      /* box faces: grid indices per axis */
+    int32_t surf_hi[3];
+    int32_t eta_on_source;   /* 1: scale the source by eta as well */
+    int32_t reserved[7];
+} pstd_problem;
+
+typedef struct pstd_solver pstd_solver;  /* opaque; owns all its device memory */
+
+/* Fill *p with a small valid default problem.  Host only, no allocation. */
+pstd_status pstd_problem_init_defaults(pstd_problem* p);
+
+/* Critical step of Eq. PSTDstability for |V| <= vmax (energy units):
+ * dt_c = hbar / (hbar^2 pi^2 / 2m * sum_a 1/h_a^2 + vmax).  Host only. */
+pstd_status pstd_critical_dt(const pstd_problem* p, double vmax, double* dt_out_host);
+
+/* Reduced step dtau = E0 dt / hbar and phase-velocity factor eta =
+ * sin(dtau)/dtau (Eq. numdis2) the solver uses.  Host only. */
+pstd_status pstd_reduced_step(const pstd_problem* p, double* dtau_out_host, double* eta_out_host);
+
+/* Validate p, allocate the solver's device state on the current device and
+ * build its tables (FP64 on the host, rounded once).  psi^{-1} = psi^0 = 0,
+ * V = 0, step index 0.  hip_stream: a hipStream_t or 0.  Synchronises.
+ * EINVAL: odd or tiny n, taper indices out of order, a box face that is not
+ * wholly in the scattered-field region (zeta = 0 on the whole plane) or
+ * inside the absorber.  EUNSTABLE: dt above the bound and force_dt = 0.
+ * EUNSUPPORTED: an axis length with no compiled FFT pass. */
+pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** out);
+
+/* Copy the potential V (float32, energy units, [k][j][i]) into the solver as
+ * 2 dtau V / E0.  Synchronises.  EINVAL: n_cells mismatch.  ENONFINITE: a
+ * NaN/Inf value.  EUNSTABLE: max|V| > v_max (the step was sized for v_max).
+ * EINVAL also when V != 0 where the taper is below one ((zeta - 1) V = 0,
+ * Section 2.2.2). */
+pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cells);
+
+/* Replace (psi^{n-1}, psi^n) by two complex64 device arrays and set the step
+ * index to `step` (the next step computes psi^{step+1}).  Clears the surface
+ * DFT.  For restarts and tests. */
+pstd_status pstd_set_state(pstd_solver* s, const void* psi_prev_dev, const void* psi_cur_dev,
+                           int64_t n_cells, int64_t step);
+
+/* Advance n_steps leapfrog steps of Eq. PSTDupdating; accumulate the surface
+ * DFT for the steps inside [dft_begin, dft_end).  Asynchronous. */
+pstd_status pstd_run(pstd_solver* s, int64_t n_steps);
+
+/* Like pstd_run, and also times every pass kernel with HIP events on the
+ * solver's stream.  pass_ms_host[3] receives the summed milliseconds of the
+ * x, y and z passes.  Synchronises. */
+pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host);
+
+/* Number of steps taken (the current level is psi^step). */
+pstd_status pstd_step_index(const pstd_solver* s, int64_t* step_out_host);
+
+/* Copy psi^step (level 0) or psi^{step-1} (level 1) to a complex64 array. */
+pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n_cells);
+
+/* Number of complex128 values pstd_get_surface_phasors writes:
+ * 2 * (2 Ny Nz + 2 Nx Nz + 2 Nx Ny). */
+pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out_host);
+
+/* Normalised phasors of Eqs. scaledphsiphasor / scaleddpsiphasor, divided by
+ * the incident phasor at the coordinate origin (sum of the switch-on ramp
+ * over the window).  Layout: faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; per
+ * face the psi plane then the d(psi)/d(x_bar_normal) plane (reduced-unit
+ * derivative); x faces are [k][j], y faces [k][i], z faces [j][i].
+ * ESTATE if no step of the window has run. */
+pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n);
+
+/* Scattered wave Psi(r) at n_obs points (physical xyz, double[3] each) by the
+ * box integral of Eqs. bottomPsi_lm ... leftrightPsi_ln summed by Eq. Psi,
+ * with each sinc expanded to 8th order in its shift.  Output complex128,
+ * relative to a unit-amplitude incident wave.  Points must lie outside the
+ * box.  ESTATE before any window step. */
+pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_obs, double* psi_out_dev);
+
+/* Far-field amplitude f(r_hat) = lim r e^{-ikr} Psi (physical length units)
+ * for n_dir unit directions (double[3] each): the cell formula in the limit
+ * of Eq. FDTDfarfieldapprox.  Output complex128. */
+pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
+
+pstd_status pstd_destroy(pstd_solver* s);
+
+const char* pstd_status_string(pstd_status st);
+const char* pstd_last_error(const pstd_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSTD_H */

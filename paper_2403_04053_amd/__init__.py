@@ -1,0 +1,307 @@
+"""Python binding of libpstd (the C ABI in include/pstd.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Functions keep the C names; device buffers are passed as torch tensors (or raw
+integer addresses), streams as torch streams (or raw hipStream_t integers).
+Importing the package fails loudly when libpstd.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "PstdError", "pstd_problem", "problem_from", "lib",
+    "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
+    "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
+    "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
+    "pstd_far_field", "pstd_destroy", "pstd_status_string", "pstd_last_error", "Solver",
+    "EXPORTED",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpstd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_04053_amd.build`")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {0: "PSTD_OK", 1: "PSTD_EINVAL", 2: "PSTD_EUNSTABLE", 3: "PSTD_ENONFINITE",
+          4: "PSTD_ENOMEM", 5: "PSTD_EHIP", 6: "PSTD_ESTATE", 7: "PSTD_EUNSUPPORTED"}
+
+
+class PstdError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+class pstd_problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("h", ctypes.c_double * 3),
+        ("hbar", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("k0", ctypes.c_double),
+        ("theta", ctypes.c_double),
+        ("phi", ctypes.c_double),
+        ("abc_cells", ctypes.c_int32 * 3),
+        ("abc_U0", ctypes.c_double),
+        ("abc_alpha", ctypes.c_double),
+        ("tfsf", (ctypes.c_int32 * 4) * 3),
+        ("v_max", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("force_dt", ctypes.c_int32),
+        ("ramp_periods", ctypes.c_double),
+        ("dft_begin", ctypes.c_int64),
+        ("dft_end", ctypes.c_int64),
+        ("surf_lo", ctypes.c_int32 * 3),
+        ("surf_hi", ctypes.c_int32 * 3),
+        ("eta_on_source", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+def problem_from(obj) -> pstd_problem:
+    """Fill a pstd_problem from any object with the same attribute names
+    (tfsf as three 4-tuples; booleans for force_dt / eta_on_source)."""
+    p = pstd_problem()
+    for a in range(3):
+        p.n[a] = int(obj.n[a])
+        p.h[a] = float(obj.h[a])
+        p.abc_cells[a] = int(obj.abc_cells[a])
+        for q in range(4):
+            p.tfsf[a][q] = int(obj.tfsf[a][q])
+        p.surf_lo[a] = int(obj.surf_lo[a])
+        p.surf_hi[a] = int(obj.surf_hi[a])
+    for name in ("hbar", "mass", "k0", "theta", "phi", "abc_U0", "abc_alpha", "v_max", "dt", "ramp_periods"):
+        setattr(p, name, float(getattr(obj, name)))
+    p.force_dt = int(bool(getattr(obj, "force_dt", False)))
+    p.eta_on_source = int(bool(getattr(obj, "eta_on_source", False)))
+    p.dft_begin = int(obj.dft_begin)
+    p.dft_end = int(obj.dft_end)
+    return p
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_PP = ctypes.POINTER(pstd_problem)
+
+_SIGS = {
+    "pstd_problem_init_defaults": [_PP],
+    "pstd_critical_dt": [_PP, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+    "pstd_reduced_step": [_PP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "pstd_create": [_PP, _vp, ctypes.POINTER(_vp)],
+    "pstd_set_potential": [_vp, _vp, _i64],
+    "pstd_set_state": [_vp, _vp, _vp, _i64, _i64],
+    "pstd_run": [_vp, _i64],
+    "pstd_run_timed": [_vp, _i64, ctypes.POINTER(ctypes.c_double)],
+    "pstd_step_index": [_vp, ctypes.POINTER(_i64)],
+    "pstd_get_psi": [_vp, ctypes.c_int32, _vp, _i64],
+    "pstd_surface_size": [_vp, ctypes.POINTER(_i64)],
+    "pstd_get_surface_phasors": [_vp, _vp, _i64],
+    "pstd_project": [_vp, _vp, _i64, _vp],
+    "pstd_far_field": [_vp, _vp, _i64, _vp],
+    "pstd_destroy": [_vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+lib.pstd_status_string.argtypes = [ctypes.c_int]
+lib.pstd_status_string.restype = ctypes.c_char_p
+lib.pstd_last_error.argtypes = [_vp]
+lib.pstd_last_error.restype = ctypes.c_char_p
+
+# every symbol include/pstd.h declares
+EXPORTED = tuple(_SIGS) + ("pstd_status_string", "pstd_last_error")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _check(st, solver=None):
+    if st != 0:
+        msg = lib.pstd_last_error(solver).decode(errors="replace")
+        raise PstdError(st, msg)
+
+
+def pstd_status_string(st):
+    return lib.pstd_status_string(int(st)).decode()
+
+
+def pstd_last_error(solver=None):
+    return lib.pstd_last_error(solver).decode(errors="replace")
+
+
+def pstd_problem_init_defaults():
+    p = pstd_problem()
+    _check(lib.pstd_problem_init_defaults(ctypes.byref(p)))
+    return p
+
+
+def pstd_critical_dt(problem, vmax):
+    out = ctypes.c_double()
+    _check(lib.pstd_critical_dt(ctypes.byref(problem), float(vmax), ctypes.byref(out)))
+    return out.value
+
+
+def pstd_reduced_step(problem):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib.pstd_reduced_step(ctypes.byref(problem), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def pstd_create(problem, stream=None):
+    h = _vp()
+    _check(lib.pstd_create(ctypes.byref(problem), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def pstd_set_potential(solver, V_dev, n_cells):
+    _check(lib.pstd_set_potential(solver, _ptr(V_dev), int(n_cells)), solver)
+
+
+def pstd_set_state(solver, prev_dev, cur_dev, n_cells, step):
+    _check(lib.pstd_set_state(solver, _ptr(prev_dev), _ptr(cur_dev), int(n_cells), int(step)), solver)
+
+
+def pstd_run(solver, n_steps):
+    _check(lib.pstd_run(solver, int(n_steps)), solver)
+
+
+def pstd_run_timed(solver, n_steps):
+    out = (ctypes.c_double * 3)()
+    _check(lib.pstd_run_timed(solver, int(n_steps), out), solver)
+    return [out[0], out[1], out[2]]
+
+
+def pstd_step_index(solver):
+    out = _i64()
+    _check(lib.pstd_step_index(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
+def pstd_get_psi(solver, level, psi_dev, n_cells):
+    _check(lib.pstd_get_psi(solver, int(level), _ptr(psi_dev), int(n_cells)), solver)
+
+
+def pstd_surface_size(solver):
+    out = _i64()
+    _check(lib.pstd_surface_size(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
+def pstd_get_surface_phasors(solver, out_dev, n):
+    _check(lib.pstd_get_surface_phasors(solver, _ptr(out_dev), int(n)), solver)
+
+
+def pstd_project(solver, obs_dev, n_obs, out_dev):
+    _check(lib.pstd_project(solver, _ptr(obs_dev), int(n_obs), _ptr(out_dev)), solver)
+
+
+def pstd_far_field(solver, dir_dev, n_dir, out_dev):
+    _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
+
+
+def pstd_destroy(solver):
+    _check(lib.pstd_destroy(solver))
+
+
+class Solver:
+    """Owning wrapper around a pstd_solver handle; buffers are torch tensors."""
+
+    def __init__(self, problem, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.problem = problem if isinstance(problem, pstd_problem) else problem_from(problem)
+        self.n = tuple(self.problem.n[a] for a in range(3))
+        self.cells = self.n[0] * self.n[1] * self.n[2]
+        self.stream = stream
+        self.handle = pstd_create(self.problem, stream)
+
+    def close(self):
+        if self.handle:
+            pstd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    def set_potential(self, V):
+        t = self.torch.as_tensor(V, dtype=self.torch.float32, device=self.device).contiguous()
+        assert t.numel() == self.cells
+        pstd_set_potential(self.handle, t, self.cells)
+
+    def set_state(self, prev, cur, step):
+        c64 = self.torch.complex64
+        a = self.torch.as_tensor(prev, dtype=c64, device=self.device).contiguous()
+        b = self.torch.as_tensor(cur, dtype=c64, device=self.device).contiguous()
+        pstd_set_state(self.handle, a, b, self.cells, step)
+
+    def run(self, n_steps):
+        pstd_run(self.handle, n_steps)
+
+    def run_timed(self, n_steps):
+        return pstd_run_timed(self.handle, n_steps)
+
+    @property
+    def step(self):
+        return pstd_step_index(self.handle)
+
+    def psi(self, level=0):
+        out = self.torch.empty(self._shape(), dtype=self.torch.complex64, device=self.device)
+        pstd_get_psi(self.handle, level, out, self.cells)
+        return out
+
+    def phasors(self):
+        n = pstd_surface_size(self.handle)
+        out = self.torch.empty(n, dtype=self.torch.complex128, device=self.device)
+        pstd_get_surface_phasors(self.handle, out, n)
+        return out
+
+    def split_phasors(self, flat):
+        """flat phasor vector -> ([psi plane per face], [dpsi plane per face])"""
+        nx, ny, nz = self.n
+        shapes = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+        phi, dphi = [], []
+        off = 0
+        for s in shapes:
+            m = s[0] * s[1]
+            phi.append(flat[off:off + m].reshape(s))
+            dphi.append(flat[off + m:off + 2 * m].reshape(s))
+            off += 2 * m
+        return phi, dphi
+
+    def project(self, points):
+        pts = self.torch.as_tensor(points, dtype=self.torch.float64, device=self.device).contiguous()
+        out = self.torch.empty(pts.shape[0], dtype=self.torch.complex128, device=self.device)
+        pstd_project(self.handle, pts, pts.shape[0], out)
+        return out
+
+    def far_field(self, dirs):
+        d = self.torch.as_tensor(dirs, dtype=self.torch.float64, device=self.device).contiguous()
+        out = self.torch.empty(d.shape[0], dtype=self.torch.complex128, device=self.device)
+        pstd_far_field(self.handle, d, d.shape[0], out)
+        return out

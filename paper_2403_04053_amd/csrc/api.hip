@@ -1,0 +1,519 @@
+// Host side of libpstd: validation, FP64 table construction, device state and
+// the time-stepping loop.  See include/pstd.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pstd.h"
+#include "internal.hpp"
+#include "project.hpp"
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct pstd_solver {
+    pstd_problem prob{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double E0 = 0, dtau = 0, eta = 0, tau_r = 0;
+    double dxb[3] = {0, 0, 0};
+    double kh[3] = {0, 0, 0};
+    int64_t cells = 0;
+    int64_t step = 0;
+    float2* cur = nullptr;
+    float2* old = nullptr;
+    float2* L = nullptr;
+    float* v2 = nullptr;
+    void* tables = nullptr;
+    pstd::AxisTables ax[3]{};
+    double2* acc[3] = {nullptr, nullptr, nullptr};
+    int64_t points[3] = {0, 0, 0};
+    pstd::ProjectState* proj = nullptr;
+    std::string err;
+};
+
+namespace {
+
+pstd_status fail(pstd_solver* s, pstd_status st, const std::string& msg) {
+    if (s) s->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+pstd_status hip_fail(pstd_solver* s, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(s, e == hipErrorOutOfMemory ? PSTD_ENOMEM : PSTD_EHIP, m);
+}
+
+#define HIP_TRY(s, call)                                   \
+    do {                                                   \
+        hipError_t _e = (call);                            \
+        if (_e != hipSuccess) return hip_fail((s), _e, #call); \
+    } while (0)
+
+double xi(double r) { return r - 2.0 / (3.0 * kPi) * std::sin(2 * kPi * r) + 1.0 / (12.0 * kPi) * std::sin(4 * kPi * r); }
+double dxi(double r) { return 1.0 - 4.0 / 3.0 * std::cos(2 * kPi * r) + 1.0 / 3.0 * std::cos(4 * kPi * r); }
+double d2xi(double r) { return 8.0 * kPi / 3.0 * std::sin(2 * kPi * r) - 4.0 * kPi / 3.0 * std::sin(4 * kPi * r); }
+
+double ramp_of(double tau, double tau_r) {
+    if (tau_r <= 0) return 1.0;
+    double r = tau / tau_r;
+    if (r < 0) r = 0;
+    if (r > 1) r = 1;
+    return xi(r);
+}
+
+double kbar_of(int m, int N, double dxb) {
+    const int mp = m < N / 2 ? m : m - N;
+    return 2.0 * kPi * mp / (N * dxb);
+}
+
+pstd_status reduced(const pstd_problem* p, double* E0, double* dxb, double* dtau, double* eta, double* dtau_crit) {
+    *E0 = p->hbar * p->hbar * p->k0 * p->k0 / (2.0 * p->mass);
+    double s = 0;
+    for (int a = 0; a < 3; ++a) {
+        dxb[a] = p->k0 * p->h[a];
+        s += 1.0 / (dxb[a] * dxb[a]);
+    }
+    *dtau_crit = 1.0 / (kPi * kPi * s + p->v_max / *E0);
+    *dtau = p->dt > 0 ? *E0 * p->dt / p->hbar : 0.9 * *dtau_crit;
+    *eta = std::sin(*dtau) / *dtau;
+    return PSTD_OK;
+}
+
+pstd_status validate(const pstd_problem* p) {
+    if (!p) return fail(nullptr, PSTD_EINVAL, "null problem");
+    if (!(p->hbar > 0 && p->mass > 0 && p->k0 > 0)) return fail(nullptr, PSTD_EINVAL, "hbar, mass and k0 must be positive");
+    if (!(p->v_max >= 0)) return fail(nullptr, PSTD_EINVAL, "v_max must be >= 0");
+    if (!(p->dt >= 0)) return fail(nullptr, PSTD_EINVAL, "dt must be >= 0");
+    for (int a = 0; a < 3; ++a) {
+        const int N = p->n[a];
+        if (N < 8 || (N & 1)) return fail(nullptr, PSTD_EINVAL, "grid lengths must be even and >= 8");
+        if (!(p->h[a] > 0)) return fail(nullptr, PSTD_EINVAL, "grid spacing must be positive");
+        if (!pstd::pass_supported(N)) return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for axis length " + std::to_string(N));
+        const int* y = p->tfsf[a];
+        if (!(0 <= y[0] && y[0] < y[1] && y[1] <= y[2] && y[2] < y[3] && y[3] <= N - 1))
+            return fail(nullptr, PSTD_EINVAL, "taper indices must satisfy 0 <= y0 < y1 <= y2 < y3 <= N-1");
+        if (p->abc_cells[a] < 0 || 2 * p->abc_cells[a] > N) return fail(nullptr, PSTD_EINVAL, "absorber wider than the grid");
+        const int lo = p->surf_lo[a], hi = p->surf_hi[a];
+        if (!(0 <= lo && lo < hi && hi <= N - 1)) return fail(nullptr, PSTD_EINVAL, "box faces out of range");
+        if (!(lo <= y[0] && hi >= y[3]))
+            return fail(nullptr, PSTD_EINVAL, "box faces must lie wholly in the scattered-field region (face <= y0, >= y3)");
+        if (lo < p->abc_cells[a] || N - 1 - hi < p->abc_cells[a])
+            return fail(nullptr, PSTD_EINVAL, "box faces must lie outside the absorbing layer");
+    }
+    if (p->dft_begin < 0 || p->dft_end < p->dft_begin) return fail(nullptr, PSTD_EINVAL, "bad DFT window");
+    return PSTD_OK;
+}
+
+template <class T>
+pstd_status upload(pstd_solver* s, T* dst, const std::vector<T>& src) {
+    HIP_TRY(s, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PSTD_OK;
+}
+
+pstd_status build_tables(pstd_solver* s) {
+    const pstd_problem& p = s->prob;
+    // layout per axis: kk[N] f, gam[N] f, tw[N] f2, zt[N] f2, dz[N] f2, dlo[N] f2, dhi[N] f2
+    size_t bytes = 0;
+    for (int a = 0; a < 3; ++a) bytes += (size_t)p.n[a] * (2 * sizeof(float) + 5 * sizeof(float2)) + 256;
+    HIP_TRY(s, hipMalloc(&s->tables, bytes));
+    char* cur = (char*)s->tables;
+    for (int a = 0; a < 3; ++a) {
+        const int N = p.n[a];
+        const double dxb = s->dxb[a];
+        std::vector<float> kk(N), gam(N);
+        std::vector<float2> tw(N), zt(N), dz(N), dlo(N), dhi(N);
+        for (int m = 0; m < N; ++m) {
+            const double k = kbar_of(m, N, dxb);
+            kk[m] = (float)(2.0 * s->eta * s->dtau * k * k / N);
+            tw[m] = make_float2((float)std::cos(2 * kPi * m / N), (float)-std::sin(2 * kPi * m / N));
+        }
+        for (int i = 0; i < N; ++i) {
+            const int d = std::min(i, N - 1 - i);
+            double g = 0.0;
+            if (d < p.abc_cells[a]) {
+                const double c = std::cosh(p.abc_alpha * d);
+                g = p.abc_U0 / (c * c);
+            }
+            gam[i] = (float)std::exp(-g * s->dtau);
+            // taper factor and its derivatives (Eq. zeta_y with Eq. xi)
+            const int* y = p.tfsf[a];
+            double z = 0, z1 = 0, z2 = 0;
+            if (i > y[0] && i < y[3]) {
+                if (i >= y[1] && i <= y[2]) {
+                    z = 1.0;
+                } else if (i < y[1]) {
+                    const double w = (y[1] - y[0]) * dxb, r = double(i - y[0]) / (y[1] - y[0]);
+                    z = xi(r);
+                    z1 = dxi(r) / w;
+                    z2 = d2xi(r) / (w * w);
+                } else {
+                    const double w = (y[3] - y[2]) * dxb, r = double(i - y[2]) / (y[3] - y[2]);
+                    z = 1.0 - xi(r);
+                    z1 = -dxi(r) / w;
+                    z2 = -d2xi(r) / (w * w);
+                }
+            }
+            const double x = (i - N / 2) * dxb;
+            const double ph = s->kh[a] * x;
+            const double er = std::cos(ph), ei = std::sin(ph);
+            zt[i] = make_float2((float)(z * er), (float)(z * ei));
+            // (z2 + 2 i kh z1) e^{i ph}
+            const double ar = z2, ai = 2.0 * s->kh[a] * z1;
+            dz[i] = make_float2((float)(ar * er - ai * ei), (float)(ar * ei + ai * er));
+        }
+        // spectral-derivative rows: d(e) = (1/N) sum_m i kbar_m exp(2 pi i m (i0 - e)/N)
+        for (int side = 0; side < 2; ++side) {
+            const int i0 = side == 0 ? p.surf_lo[a] : p.surf_hi[a];
+            std::vector<float2>& row = side == 0 ? dlo : dhi;
+            for (int e = 0; e < N; ++e) {
+                double re = 0, im = 0;
+                for (int m = 0; m < N; ++m) {
+                    const double k = kbar_of(m, N, dxb);
+                    const double ang = 2 * kPi * (double)(((int64_t)m * (i0 - e)) % N) / N;
+                    // i k e^{i ang}
+                    re += -k * std::sin(ang);
+                    im += k * std::cos(ang);
+                }
+                row[e] = make_float2((float)(re / N), (float)(im / N));
+            }
+        }
+        auto place = [&](auto& vec) {
+            using T = typename std::decay_t<decltype(vec)>::value_type;
+            T* ptr = (T*)cur;
+            cur += ((vec.size() * sizeof(T) + 15) / 16) * 16;
+            return ptr;
+        };
+        float* d_kk = place(kk);
+        float* d_gam = place(gam);
+        float2* d_tw = place(tw);
+        float2* d_zt = place(zt);
+        float2* d_dz = place(dz);
+        float2* d_dlo = place(dlo);
+        float2* d_dhi = place(dhi);
+        pstd_status st;
+        if ((st = upload(s, d_kk, kk)) || (st = upload(s, d_gam, gam)) || (st = upload(s, d_tw, tw)) ||
+            (st = upload(s, d_zt, zt)) || (st = upload(s, d_dz, dz)) || (st = upload(s, d_dlo, dlo)) ||
+            (st = upload(s, d_dhi, dhi)))
+            return st;
+        s->ax[a] = pstd::AxisTables{d_kk, d_tw, d_gam, d_zt, d_dz, d_dlo, d_dhi};
+    }
+    return PSTD_OK;
+}
+
+double incident_phasor(const pstd_solver* s) {
+    const int64_t end = std::min<int64_t>(s->prob.dft_end, s->step);
+    double acc = 0;
+    for (int64_t n = s->prob.dft_begin; n < end; ++n) acc += ramp_of(n * s->dtau, s->tau_r);
+    return acc;
+}
+
+pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
+    const int64_t n = s->step;
+    const double tau = n * s->dtau;
+    const double R = ramp_of(tau, s->tau_r);
+    const double f = 2.0 * s->dtau * R * (s->prob.eta_on_source ? s->eta : 1.0);
+    pstd::PassArgs a{};
+    a.psi = s->cur;
+    a.L = s->L;
+    a.psi_old = s->old;
+    a.v2 = s->v2;
+    a.nx = s->prob.n[0];
+    a.ny = s->prob.n[1];
+    a.nz = s->prob.n[2];
+    for (int i = 0; i < 3; ++i) a.ax[i] = s->ax[i];
+    a.sigma = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
+    a.dft_on = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
+    a.w = make_double2(std::cos(tau), std::sin(tau));
+    for (int axis = 0; axis < 3; ++axis) {
+        a.plane_lo = s->prob.surf_lo[axis];
+        a.plane_hi = s->prob.surf_hi[axis];
+        a.acc = s->acc[axis];
+        a.points = s->points[axis];
+        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], s->stream));
+        hipError_t e = pstd::launch_pass(axis, a, s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "pass launch");
+        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], s->stream));
+    }
+    std::swap(s->cur, s->old);
+    s->step = n + 1;
+    return PSTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pstd_status pstd_problem_init_defaults(pstd_problem* p) {
+    if (!p) return PSTD_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    const double h = 0.1, k0 = kPi / (4 * h);
+    for (int a = 0; a < 3; ++a) {
+        p->n[a] = 48;
+        p->h[a] = h;
+        p->abc_cells[a] = 8;
+        p->tfsf[a][0] = 12;
+        p->tfsf[a][1] = 18;
+        p->tfsf[a][2] = 30;
+        p->tfsf[a][3] = 36;
+        p->surf_lo[a] = 10;
+        p->surf_hi[a] = 38;
+    }
+    p->hbar = 1.0;
+    p->mass = 1.0;
+    p->k0 = k0;
+    p->abc_U0 = 10.0;
+    p->abc_alpha = 0.5;
+    p->v_max = 0.5 * k0 * k0 / 2;
+    p->ramp_periods = 4.0;
+    return PSTD_OK;
+}
+
+pstd_status pstd_critical_dt(const pstd_problem* p, double vmax, double* dt_out) {
+    if (!p || !dt_out || !(p->hbar > 0 && p->mass > 0) || !(vmax >= 0)) return PSTD_EINVAL;
+    double lam = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(p->h[a] > 0)) return PSTD_EINVAL;
+        lam += 1.0 / (p->h[a] * p->h[a]);
+    }
+    lam *= p->hbar * p->hbar * kPi * kPi / (2.0 * p->mass);
+    *dt_out = p->hbar / (lam + vmax);
+    return PSTD_OK;
+}
+
+pstd_status pstd_reduced_step(const pstd_problem* p, double* dtau_out, double* eta_out) {
+    if (!p || !dtau_out || !eta_out) return PSTD_EINVAL;
+    pstd_status st = validate(p);
+    if (st) return st;
+    double E0, dxb[3], dtau, eta, crit;
+    reduced(p, &E0, dxb, &dtau, &eta, &crit);
+    *dtau_out = dtau;
+    *eta_out = eta;
+    return PSTD_OK;
+}
+
+pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** out) {
+    if (!out) return PSTD_EINVAL;
+    *out = nullptr;
+    pstd_status st = validate(p);
+    if (st) return st;
+    pstd_solver* s = new pstd_solver();
+    s->prob = *p;
+    s->stream = (hipStream_t)hip_stream;
+    hipGetDevice(&s->device);
+    double crit;
+    reduced(p, &s->E0, s->dxb, &s->dtau, &s->eta, &crit);
+    if (s->dtau > crit * (1 + 1e-12) && !p->force_dt) {
+        delete s;
+        return fail(nullptr, PSTD_EUNSTABLE, "dt exceeds the bound of Eq. PSTDstability");
+    }
+    const double th = p->theta, ph = p->phi;
+    s->kh[0] = std::sin(th) * std::cos(ph);
+    s->kh[1] = std::sin(th) * std::sin(ph);
+    s->kh[2] = std::cos(th);
+    s->tau_r = 2 * kPi * p->ramp_periods;
+    s->cells = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    s->points[0] = (int64_t)p->n[1] * p->n[2];
+    s->points[1] = (int64_t)p->n[0] * p->n[2];
+    s->points[2] = (int64_t)p->n[0] * p->n[1];
+    auto cleanup = [&](pstd_status e) {
+        std::string m = s->err;
+        pstd_destroy(s);
+        g_create_error = m;
+        return e;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&s->cur, s->cells * sizeof(float2))) || (e = hipMalloc(&s->old, s->cells * sizeof(float2))) ||
+        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))))
+        return cleanup(hip_fail(s, e, "hipMalloc state"));
+    for (int a = 0; a < 3; ++a)
+        if ((e = hipMalloc(&s->acc[a], 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMalloc acc"));
+    if ((st = build_tables(s))) return cleanup(st);
+    if ((e = hipMemsetAsync(s->cur, 0, s->cells * sizeof(float2), s->stream)) ||
+        (e = hipMemsetAsync(s->old, 0, s->cells * sizeof(float2), s->stream)) ||
+        (e = hipMemsetAsync(s->v2, 0, s->cells * sizeof(float), s->stream)))
+        return cleanup(hip_fail(s, e, "hipMemset"));
+    for (int a = 0; a < 3; ++a)
+        if ((e = hipMemsetAsync(s->acc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream)))
+            return cleanup(hip_fail(s, e, "hipMemset acc"));
+    if ((e = hipStreamSynchronize(s->stream))) return cleanup(hip_fail(s, e, "sync"));
+    *out = s;
+    return PSTD_OK;
+}
+
+pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cells) {
+    if (!s || !V_dev) return PSTD_EINVAL;
+    if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
+    std::vector<float> V(n_cells);
+    HIP_TRY(s, hipMemcpyAsync(V.data(), V_dev, n_cells * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const pstd_problem& p = s->prob;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    std::vector<float> v2(n_cells);
+    const double scale = 2.0 * s->dtau / s->E0;
+    double vmax = 0;
+    for (int k = 0; k < nz; ++k) {
+        const bool ck = k >= p.tfsf[2][1] && k <= p.tfsf[2][2];
+        for (int j = 0; j < ny; ++j) {
+            const bool cj = j >= p.tfsf[1][1] && j <= p.tfsf[1][2];
+            for (int i = 0; i < nx; ++i) {
+                const int64_t id = i + (int64_t)nx * (j + (int64_t)ny * k);
+                const double v = V[id];
+                if (!std::isfinite(v)) return fail(s, PSTD_ENONFINITE, "non-finite potential value");
+                const bool ci = i >= p.tfsf[0][1] && i <= p.tfsf[0][2];
+                if (v != 0.0 && !(ci && cj && ck))
+                    return fail(s, PSTD_EINVAL, "potential must vanish where the taper is below one");
+                vmax = std::max(vmax, std::fabs(v));
+                v2[id] = (float)(scale * v);
+            }
+        }
+    }
+    if (vmax > p.v_max * (1 + 1e-6) && !p.force_dt)
+        return fail(s, PSTD_EUNSTABLE, "max |V| exceeds v_max used to size the step");
+    HIP_TRY(s, hipMemcpy(s->v2, v2.data(), n_cells * sizeof(float), hipMemcpyHostToDevice));
+    return PSTD_OK;
+}
+
+pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, int64_t n_cells, int64_t step) {
+    if (!s || !prev || !cur || step < 0) return PSTD_EINVAL;
+    if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
+    HIP_TRY(s, hipMemcpyAsync(s->old, prev, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->cur, cur, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
+    for (int a = 0; a < 3; ++a)
+        HIP_TRY(s, hipMemsetAsync(s->acc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream));
+    s->step = step;
+    return PSTD_OK;
+}
+
+pstd_status pstd_run(pstd_solver* s, int64_t n_steps) {
+    if (!s || n_steps < 0) return PSTD_EINVAL;
+    for (int64_t i = 0; i < n_steps; ++i) {
+        pstd_status st = step_once(s, nullptr);
+        if (st) return st;
+    }
+    return PSTD_OK;
+}
+
+pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
+    if (!s || n_steps < 0 || !pass_ms) return PSTD_EINVAL;
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) HIP_TRY(s, hipEventCreate(&ev[i]));
+    double sum[3] = {0, 0, 0};
+    pstd_status st = PSTD_OK;
+    for (int64_t i = 0; i < n_steps && !st; ++i) {
+        st = step_once(s, ev);
+        if (st) break;
+        hipError_t e = hipEventSynchronize(ev[5]);
+        if (e) {
+            st = hip_fail(s, e, "event sync");
+            break;
+        }
+        for (int a = 0; a < 3; ++a) {
+            float ms = 0;
+            hipEventElapsedTime(&ms, ev[2 * a], ev[2 * a + 1]);
+            sum[a] += ms;
+        }
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    for (int a = 0; a < 3; ++a) pass_ms[a] = sum[a];
+    return st;
+}
+
+pstd_status pstd_step_index(const pstd_solver* s, int64_t* out) {
+    if (!s || !out) return PSTD_EINVAL;
+    *out = s->step;
+    return PSTD_OK;
+}
+
+pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n_cells) {
+    if (!s || !psi_dev || (level != 0 && level != 1)) return PSTD_EINVAL;
+    if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
+    HIP_TRY(s, hipMemcpyAsync(psi_dev, level == 0 ? s->cur : s->old, n_cells * sizeof(float2),
+                              hipMemcpyDeviceToDevice, s->stream));
+    return PSTD_OK;
+}
+
+pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out) {
+    if (!s || !n_out) return PSTD_EINVAL;
+    *n_out = 4 * (s->points[0] + s->points[1] + s->points[2]);
+    return PSTD_OK;
+}
+
+pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+    if (!s || !out_dev) return PSTD_EINVAL;
+    int64_t need;
+    pstd_surface_size(s, &need);
+    if (n != need) return fail(s, PSTD_EINVAL, "output size must equal pstd_surface_size");
+    const double inc = incident_phasor(s);
+    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    hipError_t e = pstd::finalize_phasors(s->acc, s->points, 1.0 / inc, (double2*)out_dev, s->stream);
+    if (e) return hip_fail(s, e, "finalize_phasors");
+    return PSTD_OK;
+}
+
+pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
+    if (!s || !obs_dev || !out_dev || n_obs < 0) return PSTD_EINVAL;
+    const double inc = incident_phasor(s);
+    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    std::string msg;
+    hipError_t e = pstd::project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / inc,
+                                        (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
+    if (e) return msg.empty() ? hip_fail(s, e, "project") : fail(s, PSTD_EINVAL, msg);
+    return PSTD_OK;
+}
+
+pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
+    if (!s || !dir_dev || !out_dev || n_dir < 0) return PSTD_EINVAL;
+    const double inc = incident_phasor(s);
+    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    std::string msg;
+    hipError_t e = pstd::far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / inc,
+                                   (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
+    if (e) return msg.empty() ? hip_fail(s, e, "far_field") : fail(s, PSTD_EINVAL, msg);
+    return PSTD_OK;
+}
+
+pstd_status pstd_destroy(pstd_solver* s) {
+    if (!s) return PSTD_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(s->cur);
+    (void)hipFree(s->old);
+    (void)hipFree(s->L);
+    (void)hipFree(s->v2);
+    (void)hipFree(s->tables);
+    for (int a = 0; a < 3; ++a) (void)hipFree(s->acc[a]);
+    pstd::project_free(s->proj);
+    delete s;
+    return PSTD_OK;
+}
+
+const char* pstd_status_string(pstd_status st) {
+    switch (st) {
+        case PSTD_OK: return "PSTD_OK";
+        case PSTD_EINVAL: return "PSTD_EINVAL";
+        case PSTD_EUNSTABLE: return "PSTD_EUNSTABLE";
+        case PSTD_ENONFINITE: return "PSTD_ENONFINITE";
+        case PSTD_ENOMEM: return "PSTD_ENOMEM";
+        case PSTD_EHIP: return "PSTD_EHIP";
+        case PSTD_ESTATE: return "PSTD_ESTATE";
+        case PSTD_EUNSUPPORTED: return "PSTD_EUNSUPPORTED";
+    }
+    return "PSTD_UNKNOWN";
+}
+
+const char* pstd_last_error(const pstd_solver* s) {
+    return s ? s->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal interface between the host API and the device passes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pstd {
+
+// Per-axis constant tables (device pointers), built in FP64 on the host and
+// rounded once.
+struct AxisTables {
+    const float* kk;     // 2 eta dtau kbar_m^2 / N  (FFT index order)
+    const float2* tw;    // exp(-2 pi i j / N), j = 0..N-1
+    const float* gam;    // exp(-gamma(d) dtau), Eq. Gamma factor
+    const float2* zt;    // zeta(i) exp(i khat_a x_a(i))
+    const float2* dz;    // (zeta''(i) + 2 i khat_a zeta'(i)) exp(i khat_a x_a(i))
+    const float2* dlo;   // spectral-derivative row for the low plane
+    const float2* dhi;   // spectral-derivative row for the high plane
+};
+
+struct PassArgs {
+    const float2* psi;   // psi^n
+    float2* L;           // kinetic accumulator (scaled by 2 eta dtau)
+    float2* psi_old;     // psi^{n-1} in, psi^{n+1} out (z pass)
+    const float* v2;     // 2 dtau V / E0
+    int nx, ny, nz;
+    AxisTables ax[3];
+    float2 sigma;        // 2 dtau R(tau_n) exp(-i tau_n) [* eta]
+    int dft_on;
+    double2 w;           // exp(i tau_n)
+    int plane_lo, plane_hi;  // plane indices along this pass's axis
+    double2* acc;        // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]
+    int64_t points;      // points of one plane of this axis
+};
+
+// FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
+struct PassShape {
+    int N, N1, N2, P, threads;
+};
+
+bool pass_supported(int N);
+PassShape pass_shape(int N);
+// Launch the pass along `axis` (0, 1, 2) for the axis length args.{nx,ny,nz}[axis]
+hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream);
+
+}  // namespace pstd

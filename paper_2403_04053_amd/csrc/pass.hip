@@ -1,0 +1,276 @@
+// Pencil passes of the PSTD step (Eq. PSTDupdating, Section 2.5).
+//
+// A pass along axis a computes F_a^-1[kbar_a^2 F_a psi^n] for every pencil
+// along a.  Each pencil of length N = N1 N2 is handled by N2 threads in stage
+// A (N1-point DFTs over stride-N2 elements, held in VGPRs) and by N1 threads
+// in stage B (N2-point DFTs), with one padded LDS exchange between the two
+// stages and one back.  The forward transform leaves the spectrum in stage-B
+// order k1 + N1 k2, where it is scaled by the kbar^2 table; the inverse runs
+// the same stages backwards, so no digit-reversal pass is needed and the
+// result returns to the registers it was loaded into.
+//
+// Loads and stores are coalesced without an LDS transpose: the x pass gives
+// consecutive lanes consecutive elements of a row; the y and z passes give
+// consecutive lanes consecutive x of a tile of P pencils.
+//
+// Epilogues: x pass writes L; y pass adds to L; z pass adds its term and
+// applies the leapfrog update with potential, TF/SF source and absorber,
+// writing psi^{n+1} over psi^{n-1}.  Inside the DFT window each pass also
+// accumulates, in FP64 with Neumaier compensation, the DFT of psi and of its
+// spectral normal derivative on the two planes normal to its axis
+// (Eqs. psiphasor, dpsiphasor).
+#include "dft.hpp"
+#include "internal.hpp"
+
+namespace pstd {
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+template <int N, int N1, int N2, int P, int AXIS>
+__global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs a) {
+    constexpr int ROW = N2 + 1;                 // padded exchange row
+    constexpr int STRIDE = (N1 * ROW) | 1;      // odd pencil stride (float2)
+    __shared__ float2 ex[P * STRIDE];
+    __shared__ float2 red[P * N2 * 4];
+
+    const int t = threadIdx.x;
+    const bool activeA = t < P * N2;
+    const int pA = AXIS == 0 ? t / N2 : t % P;
+    const int n2 = AXIS == 0 ? t % N2 : t / P;
+    const AxisTables& T = a.ax[AXIS];
+
+    // pencil geometry: element e of pencil pA lives at base + e * estride
+    int64_t base = 0, estride = 1;
+    bool valid;
+    int px = 0, py = 0;  // (x, y) of the pencil for the z-pass update
+    if constexpr (AXIS == 0) {
+        const int64_t row = (int64_t)blockIdx.x * P + pA;
+        valid = activeA && row < (int64_t)a.ny * a.nz;
+        base = row * a.nx;
+        estride = 1;
+    } else if constexpr (AXIS == 1) {
+        const int x = blockIdx.x * P + pA;
+        valid = activeA && x < a.nx;
+        base = x + (int64_t)a.nx * a.ny * blockIdx.y;
+        estride = a.nx;
+    } else {
+        px = blockIdx.x * P + pA;
+        py = blockIdx.y;
+        valid = activeA && px < a.nx;
+        base = px + (int64_t)a.nx * py;
+        estride = (int64_t)a.nx * a.ny;
+    }
+
+    float2 v[N1];
+    float2 keep[AXIS == 2 ? N1 : 1];
+    unroll<N1>([&](auto i) {
+        constexpr int n1 = decltype(i)::value;
+        v[n1] = valid ? a.psi[base + (int64_t)(n2 + N2 * n1) * estride] : make_float2(0.f, 0.f);
+        if constexpr (AXIS == 2) keep[n1] = v[n1];
+    });
+
+    if (a.dft_on && activeA) {
+        float2 lo = make_float2(0.f, 0.f), hi = lo, dlo = lo, dhi = lo;
+        unroll<N1>([&](auto i) {
+            constexpr int n1 = decltype(i)::value;
+            const int e = n2 + N2 * n1;
+            if (e == a.plane_lo) lo = v[n1];
+            if (e == a.plane_hi) hi = v[n1];
+            const float2 cl = T.dlo[e], ch = T.dhi[e];
+            dlo = cadd(dlo, cmul(cl, v[n1]));
+            dhi = cadd(dhi, cmul(ch, v[n1]));
+        });
+        float2* r = &red[(pA * N2 + n2) * 4];
+        r[0] = lo;
+        r[1] = hi;
+        r[2] = dlo;
+        r[3] = dhi;
+    }
+
+    // ---- forward: stage A (N1-point DFTs), twiddle, exchange ----
+    dft<N1, -1>(v);
+    if (activeA) {
+        unroll<N1>([&](auto i) {
+            constexpr int k1 = decltype(i)::value;
+            float2 x = v[k1];
+            if constexpr (k1 != 0) x = cmul(x, T.tw[n2 * k1]);
+            ex[pA * STRIDE + k1 * ROW + n2] = x;
+        });
+    }
+    __syncthreads();
+
+    // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
+    if (t < P * N1) {
+        const int pB = AXIS == 0 ? t / N1 : t % P;
+        const int k1 = AXIS == 0 ? t % N1 : t / P;
+        float2 u[N2];
+        unroll<N2>([&](auto i) { u[decltype(i)::value] = ex[pB * STRIDE + k1 * ROW + decltype(i)::value]; });
+        dft<N2, -1>(u);
+        unroll<N2>([&](auto i) {
+            constexpr int k2 = decltype(i)::value;
+            u[k2] = cscale(u[k2], T.kk[k1 + N1 * k2]);
+        });
+        dft<N2, 1>(u);
+        unroll<N2>([&](auto i) {
+            constexpr int nn = decltype(i)::value;
+            float2 x = u[nn];
+            if constexpr (nn != 0) x = cmulc(x, T.tw[nn * k1]);
+            ex[pB * STRIDE + k1 * ROW + nn] = x;
+        });
+    }
+    __syncthreads();
+
+    // ---- inverse: stage A ----
+    if (activeA) {
+        unroll<N1>([&](auto i) { v[decltype(i)::value] = ex[pA * STRIDE + decltype(i)::value * ROW + n2]; });
+    }
+    dft<N1, 1>(v);
+
+    // ---- epilogue ----
+    if (valid) {
+        if constexpr (AXIS == 0) {
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                a.L[base + n2 + N2 * n1] = v[n1];
+            });
+        } else if constexpr (AXIS == 1) {
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                const int64_t ad = base + (int64_t)(n2 + N2 * n1) * estride;
+                a.L[ad] = cadd(a.L[ad], v[n1]);
+            });
+        } else {
+            const float2 Zx = a.ax[0].zt[px], Dx = a.ax[0].dz[px];
+            const float2 Zy = a.ax[1].zt[py], Dy = a.ax[1].dz[py];
+            const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
+            const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
+            const float gxy = a.ax[0].gam[px] * a.ax[1].gam[py];
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                const int e = n2 + N2 * n1;
+                const int64_t ad = base + (int64_t)e * estride;
+                const float2 Lt = cadd(a.L[ad], v[n1]);
+                const float2 po = a.psi_old[ad];
+                const float vv = a.v2[ad];
+                const float2 s = cadd(cmul(SA, T.zt[e]), cmul(SB, T.dz[e]));
+                float2 q = cadd(Lt, cscale(keep[n1], vv));
+                q = cadd(q, cmul(a.sigma, s));
+                const float g = gxy * T.gam[e];
+                // psi^{n+1} = Gamma (psi^{n-1} - i q)
+                a.psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+            });
+        }
+    }
+
+    // ---- surface DFT: reduce the per-thread partials, accumulate in FP64 ----
+    if (a.dft_on && t < P * 4) {
+        const int p = t >> 2;
+        const int q = t & 3;
+        int64_t pt = -1;
+        if constexpr (AXIS == 0) {
+            const int64_t row = (int64_t)blockIdx.x * P + p;
+            if (row < (int64_t)a.ny * a.nz) pt = row;
+        } else {
+            const int x = blockIdx.x * P + p;
+            if (x < a.nx) pt = x + (int64_t)a.nx * blockIdx.y;
+        }
+        if (pt >= 0) {
+            float2 s = make_float2(0.f, 0.f);
+            for (int m = 0; m < N2; ++m) s = cadd(s, red[(p * N2 + m) * 4 + q]);
+            const double re = (double)s.x, im = (double)s.y;
+            const double zr = a.w.x * re - a.w.y * im;
+            const double zi = a.w.x * im + a.w.y * re;
+            const int side = q & 1;
+            const int field = (q >> 1) * 2;
+            double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
+            double2* C = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
+            double2 sv = *S, cv = *C;
+            neumaier(sv.x, cv.x, zr);
+            neumaier(sv.y, cv.y, zi);
+            *S = sv;
+            *C = cv;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// supported lengths
+// ---------------------------------------------------------------------------
+
+template <int N, int N1, int N2, int P>
+struct Shape {
+    static constexpr int threads = P * (N1 > N2 ? N1 : N2);
+};
+
+#define PSTD_SHAPES(X)      \
+    X(8, 2, 4, 64)          \
+    X(12, 3, 4, 64)         \
+    X(16, 4, 4, 64)         \
+    X(20, 4, 5, 32)         \
+    X(24, 4, 6, 32)         \
+    X(32, 4, 8, 32)         \
+    X(40, 5, 8, 32)         \
+    X(48, 6, 8, 32)         \
+    X(64, 8, 8, 32)         \
+    X(96, 8, 12, 16)        \
+    X(100, 10, 10, 16)      \
+    X(108, 9, 12, 16)       \
+    X(120, 10, 12, 16)      \
+    X(128, 8, 16, 16)       \
+    X(144, 12, 12, 16)      \
+    X(150, 10, 15, 16)      \
+    X(160, 10, 16, 16)      \
+    X(162, 9, 18, 16)       \
+    X(180, 12, 15, 16)      \
+    X(192, 12, 16, 16)      \
+    X(256, 16, 16, 16)      \
+    X(288, 16, 18, 16)
+
+bool pass_supported(int N) {
+#define PSTD_CASE(n, a, b, p) \
+    if (N == n) return true;
+    PSTD_SHAPES(PSTD_CASE)
+#undef PSTD_CASE
+    return false;
+}
+
+PassShape pass_shape(int N) {
+#define PSTD_CASE(n, a, b, p) \
+    if (N == n) return PassShape{n, a, b, p, Shape<n, a, b, p>::threads};
+    PSTD_SHAPES(PSTD_CASE)
+#undef PSTD_CASE
+    return PassShape{0, 0, 0, 0, 0};
+}
+
+template <int N, int N1, int N2, int P>
+static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t stream) {
+    const int threads = Shape<N, N1, N2, P>::threads;
+    if (axis == 0) {
+        const int64_t rows = (int64_t)args.ny * args.nz;
+        dim3 grid((unsigned)((rows + P - 1) / P));
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0>), grid, dim3(threads), 0, stream, args);
+    } else if (axis == 1) {
+        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)args.nz);
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1>), grid, dim3(threads), 0, stream, args);
+    } else {
+        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)args.ny);
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2>), grid, dim3(threads), 0, stream, args);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream) {
+    const int N = axis == 0 ? args.nx : axis == 1 ? args.ny : args.nz;
+#define PSTD_CASE(n, a, b, p) \
+    if (N == n) return launch_shape<n, a, b, p>(axis, args, stream);
+    PSTD_SHAPES(PSTD_CASE)
+#undef PSTD_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pstd

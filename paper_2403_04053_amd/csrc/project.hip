@@ -1,0 +1,542 @@
+// Near-to-distant-field projection over the virtual box (Section 3.2).
+//
+// All sums are FP64.  The phasors of each face plane are first brought to
+// their 2D spectrum (the coefficients of the trigonometric interpolant of
+// Eq. AnBottomPsi).  Then:
+//
+//  * far field: the cell formula of Eqs. bottomPsi_lm ... leftrightPsi_ln in
+//    the limit of Eq. FDTDfarfieldapprox.  For a direction r_hat every cell
+//    term factors into an in-plane b-part and c-part, so a face contributes
+//    g_c(r_hat)^T [F_dpsi + i r_hat_a F_psi] g_b(r_hat): one complex GEMM
+//    [directions x Nb] x [Nb x 2Nc] per face and a fused row-wise dot;
+//  * Fresnel points: each sinc of the cell formula is expanded to 8th order
+//    in its shift alpha = k d R_hat / 2, so the spectral double sum of a cell
+//    becomes sum_pq alpha_b^p alpha_c^q Q_pq(cell); the Q tables are two
+//    batched GEMMs per face and field, and the per-point work is a Horner
+//    evaluation per cell with the exact distance R and exp(ikR)/R.
+//
+// Reduced units throughout (k = 1); the far-field amplitude is divided by k0
+// at the end to return physical length units.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "project.hpp"
+
+namespace pstd {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kOrder = 8;            // sinc expansion order
+constexpr int kTerms = kOrder + 1;
+
+__host__ __device__ inline int face_axis_b(int a) { return a == 0 ? 1 : 0; }
+__host__ __device__ inline int face_axis_c(int a) { return a == 2 ? 1 : 2; }
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double dsinc(double x) { return fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : sin(x) / x; }
+
+// ---------------------------------------------------------------------------
+// phasor finalisation
+// ---------------------------------------------------------------------------
+
+__global__ void finalize_kernel(const double2* __restrict__ acc, int side, int64_t points, double scale,
+                                double2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= points) return;
+    const double2* base = acc + (int64_t)side * 4 * points;
+    const double2 s0 = base[i], c0 = base[points + i], s1 = base[2 * points + i], c1 = base[3 * points + i];
+    out[i] = make_double2((s0.x + c0.x) * scale, (s0.y + c0.y) * scale);
+    out[points + i] = make_double2((s1.x + c1.x) * scale, (s1.y + c1.y) * scale);
+}
+
+// ---------------------------------------------------------------------------
+// naive separable 2D DFT of a [Nc][Nb] plane (FP64, forward)
+// ---------------------------------------------------------------------------
+
+__global__ void dft_rows_kernel(const double2* __restrict__ x, double2* __restrict__ y, int Nb, int Nc,
+                                const double2* __restrict__ twb) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)Nb * Nc) return;
+    const int bp = (int)(id % Nb), c = (int)(id / Nb);
+    double2 s = make_double2(0, 0);
+    for (int b = 0; b < Nb; ++b) s = zadd(s, zmul(x[(int64_t)c * Nb + b], twb[(int)(((int64_t)b * bp) % Nb)]));
+    y[id] = s;
+}
+
+__global__ void dft_cols_kernel(const double2* __restrict__ y, double2* __restrict__ z, int Nb, int Nc,
+                                const double2* __restrict__ twc) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)Nb * Nc) return;
+    const int bp = (int)(id % Nb), cp = (int)(id / Nb);
+    double2 s = make_double2(0, 0);
+    for (int c = 0; c < Nc; ++c) s = zadd(s, zmul(y[(int64_t)c * Nb + bp], twc[(int)(((int64_t)c * cp) % Nc)]));
+    z[id] = s;
+}
+
+// ---------------------------------------------------------------------------
+// batched complex GEMM, row-major: C[i][j] (+)= sum_k A[i][k] B[k][j]
+// ---------------------------------------------------------------------------
+
+constexpr int GBM = 32, GBN = 32, GBK = 16;
+
+__global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const double2* __restrict__ A, int64_t lda,
+                                                    int64_t sA, const double2* __restrict__ B, int64_t ldb, int64_t sB,
+                                                    double2* __restrict__ C, int64_t ldc, int64_t sC) {
+    __shared__ double2 As[GBM][GBK + 1];
+    __shared__ double2 Bs[GBK][GBN + 1];
+    const int bz = blockIdx.z;
+    A += bz * sA;
+    B += bz * sB;
+    C += bz * sC;
+    const int i0 = blockIdx.y * GBM, j0 = blockIdx.x * GBN;
+    const int t = threadIdx.x;
+    const int ti = (t / 16) * 2, tj = (t % 16) * 2;
+    double2 acc[2][2] = {{make_double2(0, 0), make_double2(0, 0)}, {make_double2(0, 0), make_double2(0, 0)}};
+    for (int k0 = 0; k0 < K; k0 += GBK) {
+        for (int e = t; e < GBM * GBK; e += 256) {
+            const int r = e / GBK, c = e % GBK;
+            const int gi = i0 + r, gk = k0 + c;
+            As[r][c] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : make_double2(0, 0);
+        }
+        for (int e = t; e < GBK * GBN; e += 256) {
+            const int r = e / GBN, c = e % GBN;
+            const int gk = k0 + r, gj = j0 + c;
+            Bs[r][c] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : make_double2(0, 0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GBK; ++kk) {
+            const double2 a0 = As[ti][kk], a1 = As[ti + 1][kk];
+            const double2 b0 = Bs[kk][tj], b1 = Bs[kk][tj + 1];
+            acc[0][0] = zadd(acc[0][0], zmul(a0, b0));
+            acc[0][1] = zadd(acc[0][1], zmul(a0, b1));
+            acc[1][0] = zadd(acc[1][0], zmul(a1, b0));
+            acc[1][1] = zadd(acc[1][1], zmul(a1, b1));
+        }
+        __syncthreads();
+    }
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            const int gi = i0 + ti + u, gj = j0 + tj + v;
+            if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[u][v];
+        }
+}
+
+hipError_t zgemm(int M, int N, int K, const double2* A, int64_t lda, int64_t sA, const double2* B, int64_t ldb,
+                 int64_t sB, double2* C, int64_t ldc, int64_t sC, int batch, hipStream_t stream) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch);
+    hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, stream, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// far field
+// ---------------------------------------------------------------------------
+
+// g(b') = (-1)^b' sinc(pi b'/N - d r/2) sum_{l=lo}^{hi-1} exp(i (2 pi b'/(N d) - r) x_l),
+// x_l = (l - N/2 + 1/2) d: the closed form of the geometric sum is used.
+__global__ void farfield_factor_kernel(const double3* __restrict__ dirs, int64_t nd, int comp, int N, double d,
+                                       int lo, int hi, double2* __restrict__ G) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nd * N) return;
+    const int m = (int)(id % N);
+    const int64_t di = id / N;
+    const double3 rh = dirs[di];
+    const double r = comp == 0 ? rh.x : comp == 1 ? rh.y : rh.z;
+    const int bp = m < N / 2 ? m : m - N;
+    const double beta = 2.0 * kPi * bp / (N * d) - r;
+    const int M = hi - lo;
+    const double theta = beta * d / 2.0;
+    const double mag = (double)M * dsinc(M * theta) / dsinc(theta) * dsinc(kPi * bp / N - d * r / 2.0) *
+                       ((bp & 1) ? -1.0 : 1.0);
+    const double ph = beta * d * (lo - N / 2 + 0.5 * M);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    G[id] = make_double2(mag * cs, mag * sn);
+}
+
+// Mt[b'][j] = F_dpsi[j][b'] (j < Nc), F_psi[j - Nc][b'] (j >= Nc)
+__global__ void stack_transpose_kernel(const double2* __restrict__ Fp, const double2* __restrict__ Fd, int Nb, int Nc,
+                                       double2* __restrict__ Mt) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)Nb * 2 * Nc) return;
+    const int j = (int)(id % (2 * Nc));
+    const int bp = (int)(id / (2 * Nc));
+    Mt[id] = j < Nc ? Fd[(int64_t)j * Nb + bp] : Fp[(int64_t)(j - Nc) * Nb + bp];
+}
+
+// f[d] += pref exp(-i r_a x_a) sum_c' Gc[d][c'] (T[d][c'] + i r_a T[d][Nc + c'])
+__global__ void farfield_dot_kernel(const double3* __restrict__ dirs, int64_t nd, int comp_a, double xa, double pref,
+                                    const double2* __restrict__ Gc, const double2* __restrict__ T, int Nc,
+                                    double2* __restrict__ f) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= nd) return;
+    const double3 rh = dirs[d];
+    const double ra = comp_a == 0 ? rh.x : comp_a == 1 ? rh.y : rh.z;
+    double2 s = make_double2(0, 0);
+    const double2* t = T + d * 2 * Nc;
+    const double2* g = Gc + d * Nc;
+    for (int c = 0; c < Nc; ++c) {
+        const double2 a = t[c], b = t[Nc + c];
+        // a + i ra b
+        const double2 m = make_double2(a.x - ra * b.y, a.y + ra * b.x);
+        s = zadd(s, zmul(g[c], m));
+    }
+    double sn, cs;
+    sincos(-ra * xa, &sn, &cs);
+    const double2 r = zmul(s, make_double2(pref * cs, pref * sn));
+    f[d] = zadd(f[d], r);
+}
+
+// ---------------------------------------------------------------------------
+// Fresnel points
+// ---------------------------------------------------------------------------
+
+constexpr int kNearThreads = 128;
+constexpr int kCellChunk = 8;
+
+struct FaceGeo {
+    int a, b, c;
+    int lo_b, lo_c, L, M;     // cell ranges
+    double db, dc, xa;        // reduced spacings, face coordinate
+    double xb0, xc0;          // first cell-centre coordinates
+    double pref;
+};
+
+// Q layout: [cell][field(0 psi, 1 dpsi)][p][q]
+__global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __restrict__ obs, int64_t n_obs, double k0,
+                                                            FaceGeo g, const double2* __restrict__ Q,
+                                                            double2* __restrict__ out) {
+    __shared__ double2 sq[kCellChunk * 2 * kTerms * kTerms];
+    const int64_t pi = (int64_t)blockIdx.x * kNearThreads + threadIdx.x;
+    const bool live = pi < n_obs;
+    double r[3] = {0, 0, 0};
+    if (live) {
+        const double3 o = obs[pi];
+        r[0] = o.x * k0;
+        r[1] = o.y * k0;
+        r[2] = o.z * k0;
+    }
+    const double Ra = r[g.a] - g.xa;
+    double2 acc = make_double2(0, 0);
+    const int64_t ncell = (int64_t)g.L * g.M;
+    constexpr int per_cell = 2 * kTerms * kTerms;
+    for (int64_t c0 = 0; c0 < ncell; c0 += kCellChunk) {
+        const int nc = (int)min<int64_t>(kCellChunk, ncell - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc * per_cell; e += kNearThreads) sq[e] = Q[c0 * per_cell + e];
+        __syncthreads();
+        if (!live) continue;
+        for (int ci = 0; ci < nc; ++ci) {
+            const int64_t cell = c0 + ci;
+            const int m = (int)(cell / g.L), l = (int)(cell % g.L);
+            const double Rb = r[g.b] - (g.xb0 + l * g.db);
+            const double Rc = r[g.c] - (g.xc0 + m * g.dc);
+            const double R2 = Ra * Ra + Rb * Rb + Rc * Rc;
+            const double Rn = sqrt(R2);
+            const double inv = 1.0 / Rn;
+            const double ab = g.db * Rb * inv * 0.5, ac = g.dc * Rc * inv * 0.5;
+            const double2* q = &sq[ci * per_cell];
+            double2 S[2];
+            for (int fld = 0; fld < 2; ++fld) {
+                double2 outer = make_double2(0, 0);
+                for (int p = kOrder; p >= 0; --p) {
+                    double2 inner = make_double2(0, 0);
+                    const double2* row = q + (fld * kTerms + p) * kTerms;
+                    for (int qq = kOrder; qq >= 0; --qq) {
+                        inner.x = inner.x * ac + row[qq].x;
+                        inner.y = inner.y * ac + row[qq].y;
+                    }
+                    outer.x = outer.x * ab + inner.x;
+                    outer.y = outer.y * ab + inner.y;
+                }
+                S[fld] = outer;
+            }
+            // e^{iR}/R (S_dpsi + (i - 1/R) (R_a/R) S_psi)
+            const double ra = Ra * inv;
+            const double2 coef = make_double2(-inv * ra, ra);
+            const double2 inner = zadd(S[1], zmul(coef, S[0]));
+            double sn, cs;
+            sincos(Rn, &sn, &cs);
+            acc = zadd(acc, zmul(make_double2(cs * inv, sn * inv), inner));
+        }
+    }
+    if (live) out[pi] = zadd(out[pi], make_double2(acc.x * g.pref, acc.y * g.pref));
+}
+
+// Q[p][q][m][l] (GEMM output) -> [cell][field][p][q]
+__global__ void reorder_q_kernel(const double2* __restrict__ Qg, int fld, int64_t ncell, double2* __restrict__ Q) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ncell * kTerms * kTerms) return;
+    const int64_t cell = id % ncell;
+    const int pq = (int)(id / ncell);
+    Q[(cell * 2 + fld) * kTerms * kTerms + pq] = Qg[(int64_t)pq * ncell + cell];
+}
+
+// sinc(x - alpha) = sum_p s_p(x) alpha^p, s_p = (-1)^p sinc^(p)(x)/p!
+void sinc_taylor(double x, double* s) {
+    for (int p = 0; p <= kOrder; ++p) {
+        double acc = 0.0;
+        for (int j = 0; j < 40; ++j) {
+            if (2 * j < p) continue;
+            // (-1)^j (2j)! / ((2j-p)! (2j+1)!) x^(2j-p)
+            double c = (j & 1) ? -1.0 : 1.0;
+            for (int t = 2 * j - p + 1; t <= 2 * j; ++t) c *= t;
+            for (int t = 2; t <= 2 * j + 1; ++t) c /= t;
+            acc += c * std::pow(x, 2 * j - p);
+        }
+        double fact = 1.0;
+        for (int t = 2; t <= p; ++t) fact *= t;
+        s[p] = ((p & 1) ? -1.0 : 1.0) * acc / fact;
+    }
+}
+
+}  // namespace
+
+struct ProjectState {
+    double2* phasors = nullptr;   // [face][2][plane]
+    double2* spectra = nullptr;   // [face][2][plane]
+    double2* work = nullptr;      // scratch
+    size_t work_bytes = 0;
+    double2* tw = nullptr;        // per distinct length: twiddles (3 axes)
+    int64_t face_off[7] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t total = 0;
+};
+
+namespace {
+
+template <class T>
+hipError_t ensure(T** ptr, size_t* have, size_t need) {
+    if (*have >= need) return hipSuccess;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc((void**)ptr, need);
+    if (e == hipSuccess) *have = need;
+    return e;
+}
+
+#define TRY(x)                                \
+    do {                                      \
+        hipError_t _e = (x);                  \
+        if (_e != hipSuccess) return _e;      \
+    } while (0)
+
+hipError_t prepare(ProjectState** pst, const pstd_problem& p, double2* const acc[3], const int64_t points[3],
+                   double scale, hipStream_t stream) {
+    if (!*pst) {
+        ProjectState* s = new ProjectState();
+        int64_t off = 0;
+        for (int f = 0; f < 6; ++f) {
+            s->face_off[f] = off;
+            off += 2 * points[f / 2];
+        }
+        s->face_off[6] = off;
+        s->total = off;
+        hipError_t e;
+        if ((e = hipMalloc(&s->phasors, off * sizeof(double2))) || (e = hipMalloc(&s->spectra, off * sizeof(double2))) ||
+            (e = hipMalloc(&s->tw, (size_t)(p.n[0] + p.n[1] + p.n[2]) * sizeof(double2)))) {
+            project_free(s);
+            return e;
+        }
+        std::vector<double2> tw;
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < p.n[a]; ++j)
+                tw.push_back(make_double2(std::cos(2 * kPi * j / p.n[a]), -std::sin(2 * kPi * j / p.n[a])));
+        if ((e = hipMemcpy(s->tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice))) {
+            project_free(s);
+            return e;
+        }
+        *pst = s;
+    }
+    ProjectState* s = *pst;
+    TRY(finalize_phasors(acc, points, scale, s->phasors, stream));
+    // 2D spectra of every plane
+    size_t need = 0;
+    for (int f = 0; f < 6; ++f) need = std::max(need, (size_t)points[f / 2] * sizeof(double2));
+    TRY(ensure(&s->work, &s->work_bytes, need));
+    const double2* twa[3] = {s->tw, s->tw + p.n[0], s->tw + p.n[0] + p.n[1]};
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2, b = face_axis_b(a), c = face_axis_c(a);
+        const int Nb = p.n[b], Nc = p.n[c];
+        const int64_t np = (int64_t)Nb * Nc;
+        for (int fld = 0; fld < 2; ++fld) {
+            const double2* x = s->phasors + s->face_off[f] + fld * np;
+            double2* z = s->spectra + s->face_off[f] + fld * np;
+            const unsigned blocks = (unsigned)((np + 255) / 256);
+            hipLaunchKernelGGL(dft_rows_kernel, dim3(blocks), dim3(256), 0, stream, x, s->work, Nb, Nc, twa[b]);
+            hipLaunchKernelGGL(dft_cols_kernel, dim3(blocks), dim3(256), 0, stream, s->work, z, Nb, Nc, twa[c]);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t finalize_phasors(double2* const acc[3], const int64_t points[3], double scale, double2* out,
+                            hipStream_t stream) {
+    int64_t off = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2;
+        const int64_t P = points[a];
+        hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, acc[a], f % 2, P,
+                           scale, out + off);
+        off += 2 * P;
+    }
+    return hipGetLastError();
+}
+
+hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                     const int64_t points[3], double scale, const double3* dirs, int64_t n_dir, double2* out,
+                     hipStream_t stream, std::string* msg) {
+    TRY(prepare(pst, p, acc, points, scale, stream));
+    ProjectState* s = *pst;
+    TRY(hipMemsetAsync(out, 0, n_dir * sizeof(double2), stream));
+    const int64_t chunk = 8192;
+    for (int64_t d0 = 0; d0 < n_dir; d0 += chunk) {
+        const int64_t nd = std::min(chunk, n_dir - d0);
+        for (int f = 0; f < 6; ++f) {
+            const int a = f / 2, side = f % 2, b = face_axis_b(a), c = face_axis_c(a);
+            const int Nb = p.n[b], Nc = p.n[c];
+            const int idx = side == 0 ? p.surf_lo[a] : p.surf_hi[a];
+            const double xa = (idx - p.n[a] / 2) * dxb[a];
+            const double pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc) / p.k0;
+            // scratch: Gb [nd][Nb], Gc [nd][Nc], Mt [Nb][2Nc], T [nd][2Nc]
+            const size_t need = ((size_t)nd * Nb + (size_t)nd * Nc + (size_t)Nb * 2 * Nc + (size_t)nd * 2 * Nc) *
+                                sizeof(double2);
+            TRY(ensure(&s->work, &s->work_bytes, need));
+            double2* Gb = s->work;
+            double2* Gc = Gb + nd * Nb;
+            double2* Mt = Gc + nd * Nc;
+            double2* T = Mt + (int64_t)Nb * 2 * Nc;
+            const double2* Fp = s->spectra + s->face_off[f];
+            const double2* Fd = Fp + (int64_t)Nb * Nc;
+            hipLaunchKernelGGL(farfield_factor_kernel, dim3((unsigned)((nd * Nb + 255) / 256)), dim3(256), 0, stream,
+                               dirs + d0, nd, b, Nb, dxb[b], p.surf_lo[b], p.surf_hi[b], Gb);
+            hipLaunchKernelGGL(farfield_factor_kernel, dim3((unsigned)((nd * Nc + 255) / 256)), dim3(256), 0, stream,
+                               dirs + d0, nd, c, Nc, dxb[c], p.surf_lo[c], p.surf_hi[c], Gc);
+            hipLaunchKernelGGL(stack_transpose_kernel, dim3((unsigned)(((int64_t)Nb * 2 * Nc + 255) / 256)), dim3(256),
+                               0, stream, Fp, Fd, Nb, Nc, Mt);
+            TRY(zgemm((int)nd, 2 * Nc, Nb, Gb, Nb, 0, Mt, 2 * Nc, 0, T, 2 * Nc, 0, 1, stream));
+            hipLaunchKernelGGL(farfield_dot_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, stream,
+                               dirs + d0, nd, a, xa, pref, Gc, T, Nc, out + d0);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t project_points(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                          const int64_t points[3], double scale, const double3* obs, int64_t n_obs, double2* out,
+                          hipStream_t stream, std::string* msg) {
+    // the cell formula holds outside the box only
+    {
+        std::vector<double3> h(n_obs);
+        TRY(hipMemcpyAsync(h.data(), obs, n_obs * sizeof(double3), hipMemcpyDeviceToHost, stream));
+        TRY(hipStreamSynchronize(stream));
+        for (int64_t i = 0; i < n_obs; ++i) {
+            const double r[3] = {h[i].x * p.k0, h[i].y * p.k0, h[i].z * p.k0};
+            bool inside = true;
+            for (int a = 0; a < 3; ++a) {
+                const double lo = (p.surf_lo[a] - p.n[a] / 2) * dxb[a], hi = (p.surf_hi[a] - p.n[a] / 2) * dxb[a];
+                if (!(r[a] > lo && r[a] < hi)) inside = false;
+                if (!std::isfinite(r[a])) inside = true;
+            }
+            if (inside) {
+                *msg = "observation point inside the box or not finite";
+                return hipErrorInvalidValue;
+            }
+        }
+    }
+    TRY(prepare(pst, p, acc, points, scale, stream));
+    ProjectState* s = *pst;
+    TRY(hipMemsetAsync(out, 0, n_obs * sizeof(double2), stream));
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2, side = f % 2, b = face_axis_b(a), c = face_axis_c(a);
+        const int Nb = p.n[b], Nc = p.n[c];
+        const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
+        const int64_t ncell = (int64_t)L * M;
+        // expansion tables U_p^T[b'][l] (batched over p) and V_q[m][c'] (batched over q)
+        std::vector<double2> Ut((size_t)kTerms * Nb * L), V((size_t)kTerms * M * Nc);
+        auto fill = [&](int ax, int lo, int cells, int N, bool transpose, std::vector<double2>& dst) {
+            const double d = dxb[ax], Lp = N * d;
+            double sp[kTerms];
+            for (int m = 0; m < N; ++m) {
+                const int bp = m < N / 2 ? m : m - N;
+                sinc_taylor(kPi * bp / N, sp);
+                for (int l = 0; l < cells; ++l) {
+                    const double xc = (lo + l - N / 2 + 0.5) * d;
+                    const double ph = 2 * kPi * bp * xc / Lp;
+                    const double sg = (bp & 1) ? -1.0 : 1.0;
+                    for (int q = 0; q < kTerms; ++q) {
+                        const double2 v = make_double2(sg * sp[q] * std::cos(ph), sg * sp[q] * std::sin(ph));
+                        if (transpose) dst[((size_t)q * N + m) * cells + l] = v;   // [p][b'][l]
+                        else dst[((size_t)q * cells + l) * N + m] = v;             // [q][m][c']
+                    }
+                }
+            }
+        };
+        fill(b, p.surf_lo[b], L, Nb, true, Ut);
+        fill(c, p.surf_lo[c], M, Nc, false, V);
+        // scratch: Ut, V, W [p][Nc][L], Qg [p][q][M][L], Q [cell][2][p][q]
+        const size_t nUt = Ut.size(), nV = V.size(), nW = (size_t)kTerms * Nc * L,
+                     nQg = (size_t)kTerms * kTerms * ncell, nQ = (size_t)2 * kTerms * kTerms * ncell;
+        TRY(ensure(&s->work, &s->work_bytes, (nUt + nV + nW + nQg + nQ) * sizeof(double2)));
+        double2* dUt = s->work;
+        double2* dV = dUt + nUt;
+        double2* dW = dV + nV;
+        double2* dQg = dW + nW;
+        double2* dQ = dQg + nQg;
+        TRY(hipMemcpyAsync(dUt, Ut.data(), nUt * sizeof(double2), hipMemcpyHostToDevice, stream));
+        TRY(hipMemcpyAsync(dV, V.data(), nV * sizeof(double2), hipMemcpyHostToDevice, stream));
+        for (int fld = 0; fld < 2; ++fld) {
+            const double2* F = s->spectra + s->face_off[f] + (int64_t)fld * Nb * Nc;
+            // W_p = F [Nc x Nb] * Ut_p [Nb x L]
+            TRY(zgemm(Nc, L, Nb, F, Nb, 0, dUt, L, (int64_t)Nb * L, dW, L, (int64_t)Nc * L, kTerms, stream));
+            // Q_pq = V_q [M x Nc] * W_p [Nc x L]
+            for (int pp = 0; pp < kTerms; ++pp)
+                TRY(zgemm(M, L, Nc, dV, Nc, (int64_t)M * Nc, dW + (size_t)pp * Nc * L, L, 0,
+                          dQg + (size_t)pp * kTerms * ncell, L, ncell, kTerms, stream));
+            const int64_t tot = ncell * kTerms * kTerms;
+            hipLaunchKernelGGL(reorder_q_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, dQg, fld,
+                               ncell, dQ);
+        }
+        FaceGeo g;
+        g.a = a;
+        g.b = b;
+        g.c = c;
+        g.lo_b = p.surf_lo[b];
+        g.lo_c = p.surf_lo[c];
+        g.L = L;
+        g.M = M;
+        g.db = dxb[b];
+        g.dc = dxb[c];
+        g.xa = ((side == 0 ? p.surf_lo[a] : p.surf_hi[a]) - p.n[a] / 2) * dxb[a];
+        g.xb0 = (p.surf_lo[b] - Nb / 2 + 0.5) * dxb[b];
+        g.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
+        g.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
+        hipLaunchKernelGGL(near_kernel, dim3((unsigned)((n_obs + kNearThreads - 1) / kNearThreads)),
+                           dim3(kNearThreads), 0, stream, obs, n_obs, p.k0, g, dQ, out);
+        // the scratch is reused by the next face: wait for this face's kernels
+        TRY(hipStreamSynchronize(stream));
+    }
+    return hipGetLastError();
+}
+
+void project_free(ProjectState* s) {
+    if (!s) return;
+    (void)hipFree(s->phasors);
+    (void)hipFree(s->spectra);
+    (void)hipFree(s->work);
+    (void)hipFree(s->tw);
+    delete s;
+}
+
+}  // namespace pstd

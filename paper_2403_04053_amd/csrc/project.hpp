@@ -1,0 +1,29 @@
+// Near-to-distant-field projection (Section 3.2) on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/pstd.h"
+
+namespace pstd {
+
+struct ProjectState;  // cached spectra and expansion tables
+
+// out[face][psi|dpsi][plane] = (sum + comp) * scale  (complex128)
+hipError_t finalize_phasors(double2* const acc[3], const int64_t points[3], double scale, double2* out,
+                            hipStream_t stream);
+
+hipError_t project_points(ProjectState** st, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                          const int64_t points[3], double scale, const double3* obs, int64_t n_obs, double2* out,
+                          hipStream_t stream, std::string* msg);
+
+hipError_t far_field(ProjectState** st, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                     const int64_t points[3], double scale, const double3* dirs, int64_t n_dir, double2* out,
+                     hipStream_t stream, std::string* msg);
+
+void project_free(ProjectState* st);
+
+}  // namespace pstd

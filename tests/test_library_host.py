@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/pstd.h declares, and its host arithmetic and validation
+agree with the oracle and the paper."""
+import math
+import os
+import re
+
+import pytest
+
+import synth
+from oracle import pstd as opstd
+
+lib_mod = pytest.importorskip("paper_2403_04053_amd")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pstd.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:pstd_status|const char\*)\s+(pstd_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib_mod.lib, n), n
+    assert set(names) == set(lib_mod.EXPORTED)
+
+
+def test_status_strings():
+    for code, name in lib_mod.STATUS.items():
+        assert lib_mod.pstd_status_string(code) == name
+
+
+@pytest.mark.parametrize("cfg", [synth.cfg1, lambda: synth.tiny(n=(24, 20, 32), P=3, transition=2)])
+def test_reduced_step_matches_oracle(cfg):
+    prob = cfg()[0]
+    p = lib_mod.problem_from(prob)
+    dtau, eta = lib_mod.pstd_reduced_step(p)
+    assert dtau == pytest.approx(opstd.dtau_of(prob), rel=1e-14)
+    assert eta == pytest.approx(opstd.eta_of(opstd.dtau_of(prob)), rel=1e-14)
+    assert lib_mod.pstd_critical_dt(p, prob.v_max) == pytest.approx(opstd.critical_dt(prob, prob.v_max), rel=1e-14)
+
+
+def test_defaults_are_valid_plain_method_geometry():
+    p = lib_mod.pstd_problem_init_defaults()
+    assert list(p.n) == [48, 48, 48]
+    dtau, eta = lib_mod.pstd_reduced_step(p)
+    # 0.9 of Eq. dtau_stability at dxb = pi/4, |V|max = E0/2
+    assert dtau == pytest.approx(0.9 / (3 * 16 + 0.5), rel=1e-12)
+
+
+def _expect(status_name, prob):
+    with pytest.raises(lib_mod.PstdError) as e:
+        lib_mod.pstd_create(lib_mod.problem_from(prob))
+    assert e.value.name == status_name
+
+
+def test_create_rejects_bad_geometry_before_touching_the_device():
+    prob, _ = synth.cfg1()
+    _expect("PSTD_EINVAL", prob.replace(n=(47, 48, 48)))
+    _expect("PSTD_EINVAL", prob.replace(surf_lo=(13, 10, 10)))       # face inside the taper
+    _expect("PSTD_EINVAL", prob.replace(surf_hi=(38, 35, 38)))
+    _expect("PSTD_EINVAL", prob.replace(surf_lo=(5, 10, 10)))        # inside the absorber
+    _expect("PSTD_EINVAL", prob.replace(tfsf=((12, 11, 30, 36),) * 3))
+    _expect("PSTD_EINVAL", prob.replace(k0=0.0))
+    _expect("PSTD_EUNSUPPORTED", prob.replace(n=(50, 48, 48), tfsf=((12, 18, 30, 36),) * 3))
+
+
+def test_create_rejects_unstable_step():
+    """The plain-method workload's literal dt = 0.1 dx^2 is above the bound of
+    Eq. PSTDstability and is refused unless forced."""
+    prob, _ = synth.cfg1()
+    _expect("PSTD_EUNSTABLE", prob.replace(dt=0.1 * 0.1 ** 2))
+    ok = lib_mod.problem_from(prob.replace(dt=0.99 * opstd.critical_dt(prob, prob.v_max)))
+    assert lib_mod.pstd_reduced_step(ok)[0] > 0
