@@ -33,6 +33,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--n", type=int, default=160, help="FFT grid length per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run a plain FP32 copy kernel over this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -43,6 +45,15 @@ def main():
 
     import paper_2403_04053_amd as P
     import synth
+
+    if args.copy_mb:
+        # reads and writes exactly copy_mb MiB: the scale for FETCH_SIZE / WRITE_SIZE
+        a = torch.ones(args.copy_mb * 2 ** 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     prob, V = synth.cfg2(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window

@@ -130,8 +130,8 @@ pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n
 pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out_host);
 
 /* Normalised phasors of Eqs. scaledphsiphasor / scaleddpsiphasor, divided by
- * the incident phasor at the coordinate origin (sum of the switch-on ramp
- * over the window).  Layout: faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; per
+ * the incident phasor at the coordinate origin (the switch-on ramp summed
+ * over the window steps that have run since creation or pstd_set_state).  Layout: faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; per
  * face the psi plane then the d(psi)/d(x_bar_normal) plane (reduced-unit
  * derivative); x faces are [k][j], y faces [k][i], z faces [j][i].
  * ESTATE if no step of the window has run. */

@@ -29,6 +29,7 @@ struct pstd_solver {
     double kh[3] = {0, 0, 0};
     int64_t cells = 0;
     int64_t step = 0;
+    double inc_sum = 0;   // incident phasor at the origin over the window steps run so far
     float2* cur = nullptr;
     float2* old = nullptr;
     float2* L = nullptr;
@@ -211,12 +212,9 @@ pstd_status build_tables(pstd_solver* s) {
     return PSTD_OK;
 }
 
-double incident_phasor(const pstd_solver* s) {
-    const int64_t end = std::min<int64_t>(s->prob.dft_end, s->step);
-    double acc = 0;
-    for (int64_t n = s->prob.dft_begin; n < end; ++n) acc += ramp_of(n * s->dtau, s->tau_r);
-    return acc;
-}
+// Eq. incpsiphasor at the origin: psi_inc(0, tau_n) exp(i tau_n) = R(tau_n), summed
+// over the window steps that have run
+double incident_phasor(const pstd_solver* s) { return s->inc_sum; }
 
 pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
     const int64_t n = s->step;
@@ -234,6 +232,7 @@ pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
     for (int i = 0; i < 3; ++i) a.ax[i] = s->ax[i];
     a.sigma = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
     a.dft_on = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
+    if (a.dft_on) s->inc_sum += R;
     a.w = make_double2(std::cos(tau), std::sin(tau));
     for (int axis = 0; axis < 3; ++axis) {
         a.plane_lo = s->prob.surf_lo[axis];
@@ -310,7 +309,7 @@ pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** o
     pstd_solver* s = new pstd_solver();
     s->prob = *p;
     s->stream = (hipStream_t)hip_stream;
-    hipGetDevice(&s->device);
+    (void)hipGetDevice(&s->device);
     double crit;
     reduced(p, &s->E0, s->dxb, &s->dtau, &s->eta, &crit);
     if (s->dtau > crit * (1 + 1e-12) && !p->force_dt) {
@@ -392,6 +391,7 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
     for (int a = 0; a < 3; ++a)
         HIP_TRY(s, hipMemsetAsync(s->acc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream));
     s->step = step;
+    s->inc_sum = 0;
     return PSTD_OK;
 }
 
@@ -420,7 +420,7 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
         }
         for (int a = 0; a < 3; ++a) {
             float ms = 0;
-            hipEventElapsedTime(&ms, ev[2 * a], ev[2 * a + 1]);
+            (void)hipEventElapsedTime(&ms, ev[2 * a], ev[2 * a + 1]);
             sum[a] += ms;
         }
     }
