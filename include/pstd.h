@@ -72,7 +72,15 @@ typedef struct pstd_problem {
     int32_t surf_lo[3];      /* box faces: grid indices per axis */
     int32_t surf_hi[3];
     int32_t eta_on_source;   /* 1: scale the source by eta as well */
-    int32_t reserved[7];
+    /* Overlapping subdomains with local Fourier basis (Section 2.6): along
+     * every axis with sub_core[a] > 0 the kinetic term is taken on local
+     * arrays of sub_core[a] + 2 sub_halo points (halo weighted by Eq. weight
+     * with sub_taper tapered points) and only core points are updated.
+     * n[a] must be a multiple of sub_core[a]; sub_halo >= sub_taper + 5. */
+    int32_t sub_core[3];
+    int32_t sub_halo;
+    int32_t sub_taper;
+    int32_t reserved[2];
 } pstd_problem;
 
 typedef struct pstd_solver pstd_solver;  /* opaque; owns all its device memory */
@@ -94,7 +102,8 @@ pstd_status pstd_reduced_step(const pstd_problem* p, double* dtau_out_host, doub
  * EINVAL: odd or tiny n, taper indices out of order, a box face that is not
  * wholly in the scattered-field region (zeta = 0 on the whole plane) or
  * inside the absorber.  EUNSTABLE: dt above the bound and force_dt = 0.
- * EUNSUPPORTED: an axis length with no compiled FFT pass. */
+ * EUNSUPPORTED: an axis length (or local subdomain length) with no compiled
+ * FFT pass. */
 pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** out);
 
 /* Copy the potential V (float32, energy units, [k][j][i]) into the solver as

@@ -137,3 +137,35 @@ def step(model, blocks, psi_prev, psi_cur, n):
     rhs = psi_prev - 2j * model.eta * dt * kinetic(model, blocks, psi_cur) - 2j * dt * model.v * psi_cur \
         - 2j * dt * S
     return model.Gamma * rhs
+
+
+def step_at(model, blocks, psi_prev, psi_cur, n, points):
+    """psi^{n+1} of the subdomain scheme at selected points.  A point lies in
+    the core of exactly one block; there the weights of the two transverse
+    axes are 1, so each axis term needs only the weighted local pencil
+    along that axis."""
+    from .pstd import step_at as global_step_at  # source, potential and mask terms
+    out = []
+    dt = model.dtau
+    h = blocks.halo
+    for (i, j, k) in points:
+        pos = (i, j, k)
+        kin = 0.0 + 0.0j
+        for a in range(3):
+            b = pos[a] // blocks.core[a]
+            idx = blocks.window(a, b)
+            ok = (idx >= 0) & (idx < blocks.n[a])
+            pen = np.zeros(blocks.nloc[a], np.complex128)
+            full = (psi_cur[k, j, :], psi_cur[k, :, i], psi_cur[:, j, i])[a]
+            pen[ok] = full[idx[ok]]
+            pen = pen * blocks.w[a]
+            kb2 = kbar(blocks.nloc[a], model.dxb[a]) ** 2
+            kin += _fft.ifft(kb2 * _fft.fft(pen))[pos[a] - b * blocks.core[a] + h]
+        ref_global = global_step_at(model, psi_prev, psi_cur, n, [pos])[0]
+        # replace the global kinetic term of the same formula by the local one
+        glob_kin = 0.0 + 0.0j
+        for a in range(3):
+            full = (psi_cur[k, j, :], psi_cur[k, :, i], psi_cur[:, j, i])[a]
+            glob_kin += _fft.ifft(model.kb2[a] * _fft.fft(full))[pos[a]]
+        out.append(ref_global - model.Gamma[k, j, i] * 2j * model.eta * dt * (kin - glob_kin))
+    return np.array(out)

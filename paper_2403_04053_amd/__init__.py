@@ -59,7 +59,10 @@ class pstd_problem(ctypes.Structure):
         ("surf_lo", ctypes.c_int32 * 3),
         ("surf_hi", ctypes.c_int32 * 3),
         ("eta_on_source", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("sub_core", ctypes.c_int32 * 3),
+        ("sub_halo", ctypes.c_int32),
+        ("sub_taper", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -81,6 +84,12 @@ def problem_from(obj) -> pstd_problem:
     p.eta_on_source = int(bool(getattr(obj, "eta_on_source", False)))
     p.dft_begin = int(obj.dft_begin)
     p.dft_end = int(obj.dft_end)
+    sub = getattr(obj, "sub_core", None)
+    if sub:
+        for a in range(3):
+            p.sub_core[a] = int(sub[a])
+        p.sub_halo = int(obj.sub_halo)
+        p.sub_taper = int(obj.sub_taper)
     return p
 
 

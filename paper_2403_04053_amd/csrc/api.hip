@@ -36,6 +36,7 @@ struct pstd_solver {
     float* v2 = nullptr;
     void* tables = nullptr;
     pstd::AxisTables ax[3]{};
+    const float* wloc[3] = {nullptr, nullptr, nullptr};
     double2* acc[3] = {nullptr, nullptr, nullptr};
     int64_t points[3] = {0, 0, 0};
     pstd::ProjectState* proj = nullptr;
@@ -100,7 +101,18 @@ pstd_status validate(const pstd_problem* p) {
         const int N = p->n[a];
         if (N < 8 || (N & 1)) return fail(nullptr, PSTD_EINVAL, "grid lengths must be even and >= 8");
         if (!(p->h[a] > 0)) return fail(nullptr, PSTD_EINVAL, "grid spacing must be positive");
-        if (!pstd::pass_supported(N)) return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for axis length " + std::to_string(N));
+        if (p->sub_core[a] > 0) {
+            const int C = p->sub_core[a], nloc = C + 2 * p->sub_halo;
+            if (N % C) return fail(nullptr, PSTD_EINVAL, "sub_core must divide the grid length");
+            if (p->sub_taper < 0 || p->sub_halo < p->sub_taper + 5)
+                return fail(nullptr, PSTD_EINVAL, "sub_halo must be at least sub_taper + 5 (Section 2.6)");
+            if (!pstd::seg_supported(nloc))
+                return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for local length " + std::to_string(nloc));
+        } else if (p->sub_core[a] < 0) {
+            return fail(nullptr, PSTD_EINVAL, "sub_core must be >= 0");
+        } else if (!pstd::pass_supported(N)) {
+            return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for axis length " + std::to_string(N));
+        }
         const int* y = p->tfsf[a];
         if (!(0 <= y[0] && y[0] < y[1] && y[1] <= y[2] && y[2] < y[3] && y[3] <= N - 1))
             return fail(nullptr, PSTD_EINVAL, "taper indices must satisfy 0 <= y0 < y1 <= y2 < y3 <= N-1");
@@ -122,22 +134,52 @@ pstd_status upload(pstd_solver* s, T* dst, const std::vector<T>& src) {
     return PSTD_OK;
 }
 
+// local spectral length of axis a (the subdomain length in the segmented mode)
+int local_len(const pstd_problem& p, int a) {
+    return p.sub_core[a] > 0 ? p.sub_core[a] + 2 * p.sub_halo : p.n[a];
+}
+
+// plane index of side `side` along axis a as (segment, position in the local array)
+void plane_local(const pstd_problem& p, int a, int side, int* seg, int* pos) {
+    const int i0 = side == 0 ? p.surf_lo[a] : p.surf_hi[a];
+    if (p.sub_core[a] > 0) {
+        *seg = i0 / p.sub_core[a];
+        *pos = i0 - *seg * p.sub_core[a] + p.sub_halo;
+    } else {
+        *seg = 0;
+        *pos = i0;
+    }
+}
+
 pstd_status build_tables(pstd_solver* s) {
     const pstd_problem& p = s->prob;
-    // layout per axis: kk[N] f, gam[N] f, tw[N] f2, zt[N] f2, dz[N] f2, dlo[N] f2, dhi[N] f2
+    // per axis: kk[Nl] f, wloc[Nl] f, tw[Nl] f2, dlo[Nl] f2, dhi[Nl] f2 (local length Nl),
+    //           gam[N] f, zt[N] f2, dz[N] f2 (global length N)
     size_t bytes = 0;
-    for (int a = 0; a < 3; ++a) bytes += (size_t)p.n[a] * (2 * sizeof(float) + 5 * sizeof(float2)) + 256;
+    for (int a = 0; a < 3; ++a)
+        bytes += (size_t)local_len(p, a) * (2 * sizeof(float) + 3 * sizeof(float2)) +
+                 (size_t)p.n[a] * (sizeof(float) + 2 * sizeof(float2)) + 16 * 8;
     HIP_TRY(s, hipMalloc(&s->tables, bytes));
     char* cur = (char*)s->tables;
     for (int a = 0; a < 3; ++a) {
         const int N = p.n[a];
+        const int Nl = local_len(p, a);
         const double dxb = s->dxb[a];
-        std::vector<float> kk(N), gam(N);
-        std::vector<float2> tw(N), zt(N), dz(N), dlo(N), dhi(N);
-        for (int m = 0; m < N; ++m) {
-            const double k = kbar_of(m, N, dxb);
-            kk[m] = (float)(2.0 * s->eta * s->dtau * k * k / N);
-            tw[m] = make_float2((float)std::cos(2 * kPi * m / N), (float)-std::sin(2 * kPi * m / N));
+        std::vector<float> kk(Nl), wl(Nl, 1.0f), gam(N);
+        std::vector<float2> tw(Nl), zt(N), dz(N), dlo(Nl), dhi(Nl);
+        for (int m = 0; m < Nl; ++m) {
+            const double k = kbar_of(m, Nl, dxb);
+            kk[m] = (float)(2.0 * s->eta * s->dtau * k * k / Nl);
+            tw[m] = make_float2((float)std::cos(2 * kPi * m / Nl), (float)-std::sin(2 * kPi * m / Nl));
+        }
+        if (p.sub_core[a] > 0) {
+            // halo weights, distal to proximal (Eq. weight): 0, xi(l/(n_t+1)) for l = 1..n_t, then 1
+            const int H = p.sub_halo, nt = p.sub_taper;
+            for (int l = 0; l < H; ++l) {
+                const double w = l == 0 ? 0.0 : (l <= nt ? xi(double(l) / (nt + 1)) : 1.0);
+                wl[l] = (float)w;
+                wl[Nl - 1 - l] = (float)w;
+            }
         }
         for (int i = 0; i < N; ++i) {
             const int d = std::min(i, N - 1 - i);
@@ -173,20 +215,21 @@ pstd_status build_tables(pstd_solver* s) {
             const double ar = z2, ai = 2.0 * s->kh[a] * z1;
             dz[i] = make_float2((float)(ar * er - ai * ei), (float)(ar * ei + ai * er));
         }
-        // spectral-derivative rows: d(e) = (1/N) sum_m i kbar_m exp(2 pi i m (i0 - e)/N)
+        // spectral-derivative rows: d(e) = (1/Nl) sum_m i kbar_m exp(2 pi i m (i0 - e)/Nl)
         for (int side = 0; side < 2; ++side) {
-            const int i0 = side == 0 ? p.surf_lo[a] : p.surf_hi[a];
+            int seg, i0;
+            plane_local(p, a, side, &seg, &i0);
             std::vector<float2>& row = side == 0 ? dlo : dhi;
-            for (int e = 0; e < N; ++e) {
+            for (int e = 0; e < Nl; ++e) {
                 double re = 0, im = 0;
-                for (int m = 0; m < N; ++m) {
-                    const double k = kbar_of(m, N, dxb);
-                    const double ang = 2 * kPi * (double)(((int64_t)m * (i0 - e)) % N) / N;
+                for (int m = 0; m < Nl; ++m) {
+                    const double k = kbar_of(m, Nl, dxb);
+                    const double ang = 2 * kPi * (double)(((int64_t)m * (i0 - e)) % Nl) / Nl;
                     // i k e^{i ang}
                     re += -k * std::sin(ang);
                     im += k * std::cos(ang);
                 }
-                row[e] = make_float2((float)(re / N), (float)(im / N));
+                row[e] = make_float2((float)(re / Nl), (float)(im / Nl));
             }
         }
         auto place = [&](auto& vec) {
@@ -196,6 +239,7 @@ pstd_status build_tables(pstd_solver* s) {
             return ptr;
         };
         float* d_kk = place(kk);
+        float* d_wl = place(wl);
         float* d_gam = place(gam);
         float2* d_tw = place(tw);
         float2* d_zt = place(zt);
@@ -203,11 +247,12 @@ pstd_status build_tables(pstd_solver* s) {
         float2* d_dlo = place(dlo);
         float2* d_dhi = place(dhi);
         pstd_status st;
-        if ((st = upload(s, d_kk, kk)) || (st = upload(s, d_gam, gam)) || (st = upload(s, d_tw, tw)) ||
-            (st = upload(s, d_zt, zt)) || (st = upload(s, d_dz, dz)) || (st = upload(s, d_dlo, dlo)) ||
-            (st = upload(s, d_dhi, dhi)))
+        if ((st = upload(s, d_kk, kk)) || (st = upload(s, d_wl, wl)) || (st = upload(s, d_gam, gam)) ||
+            (st = upload(s, d_tw, tw)) || (st = upload(s, d_zt, zt)) || (st = upload(s, d_dz, dz)) ||
+            (st = upload(s, d_dlo, dlo)) || (st = upload(s, d_dhi, dhi)))
             return st;
         s->ax[a] = pstd::AxisTables{d_kk, d_tw, d_gam, d_zt, d_dz, d_dlo, d_dhi};
+        s->wloc[a] = d_wl;
     }
     return PSTD_OK;
 }
@@ -235,12 +280,19 @@ pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
     if (a.dft_on) s->inc_sum += R;
     a.w = make_double2(std::cos(tau), std::sin(tau));
     for (int axis = 0; axis < 3; ++axis) {
-        a.plane_lo = s->prob.surf_lo[axis];
-        a.plane_hi = s->prob.surf_hi[axis];
+        const pstd_problem& p = s->prob;
+        plane_local(p, axis, 0, &a.seg_plane[0], &a.plane_lo);
+        plane_local(p, axis, 1, &a.seg_plane[1], &a.plane_hi);
         a.acc = s->acc[axis];
         a.points = s->points[axis];
+        const bool seg = p.sub_core[axis] > 0;
+        a.seg_core = seg ? p.sub_core[axis] : 0;
+        a.seg_halo = seg ? p.sub_halo : 0;
+        a.nseg = seg ? p.n[axis] / p.sub_core[axis] : 1;
+        a.wloc = s->wloc[axis];
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], s->stream));
-        hipError_t e = pstd::launch_pass(axis, a, s->stream);
+        hipError_t e = seg ? pstd::launch_pass_seg(axis, local_len(p, axis), a, s->stream)
+                           : pstd::launch_pass(axis, a, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], s->stream));
     }

@@ -32,6 +32,10 @@ struct PassArgs {
     int plane_lo, plane_hi;  // plane indices along this pass's axis
     double2* acc;        // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]
     int64_t points;      // points of one plane of this axis
+    // overlapping-subdomain mode along this pass's axis (Section 2.6)
+    int seg_core, seg_halo, nseg;
+    const float* wloc;   // local halo weights, length core + 2 halo
+    int seg_plane[2];    // segment holding the low / high plane (plane_lo/hi are local then)
 };
 
 // FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
@@ -43,5 +47,8 @@ bool pass_supported(int N);
 PassShape pass_shape(int N);
 // Launch the pass along `axis` (0, 1, 2) for the axis length args.{nx,ny,nz}[axis]
 hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream);
+// Segmented pass: local pencils of length nloc = seg_core + 2 seg_halo
+bool seg_supported(int nloc);
+hipError_t launch_pass_seg(int axis, int nloc, const PassArgs& args, hipStream_t stream);
 
 }  // namespace pstd

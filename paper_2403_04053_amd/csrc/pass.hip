@@ -31,7 +31,7 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
     s = t;
 }
 
-template <int N, int N1, int N2, int P, int AXIS>
+template <int N, int N1, int N2, int P, int AXIS, bool SEG>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs a) {
     constexpr int ROW = N2 + 1;                 // padded exchange row
     constexpr int STRIDE = (N1 * ROW) | 1;      // odd pencil stride (float2)
@@ -43,35 +43,53 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     const int pA = AXIS == 0 ? t / N2 : t % P;
     const int n2 = AXIS == 0 ? t % N2 : t / P;
     const AxisTables& T = a.ax[AXIS];
+    // segmented pencils (overlapping subdomains): element e of segment `seg`
+    // is global index seg * C - H + e, weighted by wloc[e]; plain pencils have
+    // one segment with C = N, H = 0
+    const int C = SEG ? a.seg_core : N;
+    const int H = SEG ? a.seg_halo : 0;
+    const int nseg = SEG ? a.nseg : 1;
+    const int Ng = AXIS == 0 ? a.nx : AXIS == 1 ? a.ny : a.nz;
 
     // pencil geometry: element e of pencil pA lives at base + e * estride
     int64_t base = 0, estride = 1;
     bool valid;
+    int seg = 0;
     int px = 0, py = 0;  // (x, y) of the pencil for the z-pass update
     if constexpr (AXIS == 0) {
-        const int64_t row = (int64_t)blockIdx.x * P + pA;
-        valid = activeA && row < (int64_t)a.ny * a.nz;
-        base = row * a.nx;
+        const int64_t q = (int64_t)blockIdx.x * P + pA;
+        const int64_t row = q / nseg;
+        seg = (int)(q % nseg);
+        valid = activeA && q < (int64_t)a.ny * a.nz * nseg;
+        base = row * a.nx + (seg * C - H);
         estride = 1;
     } else if constexpr (AXIS == 1) {
         const int x = blockIdx.x * P + pA;
+        const int z = blockIdx.y / nseg;
+        seg = blockIdx.y % nseg;
         valid = activeA && x < a.nx;
-        base = x + (int64_t)a.nx * a.ny * blockIdx.y;
         estride = a.nx;
+        base = x + (int64_t)a.nx * a.ny * z + (int64_t)(seg * C - H) * estride;
     } else {
         px = blockIdx.x * P + pA;
-        py = blockIdx.y;
+        py = blockIdx.y / nseg;
+        seg = blockIdx.y % nseg;
         valid = activeA && px < a.nx;
-        base = px + (int64_t)a.nx * py;
         estride = (int64_t)a.nx * a.ny;
+        base = px + (int64_t)a.nx * py + (int64_t)(seg * C - H) * estride;
     }
+    const int g0 = seg * C - H;  // global index of element 0
 
     float2 v[N1];
     float2 keep[AXIS == 2 ? N1 : 1];
     unroll<N1>([&](auto i) {
         constexpr int n1 = decltype(i)::value;
-        v[n1] = valid ? a.psi[base + (int64_t)(n2 + N2 * n1) * estride] : make_float2(0.f, 0.f);
-        if constexpr (AXIS == 2) keep[n1] = v[n1];
+        const int e = n2 + N2 * n1;
+        const bool in = valid && (!SEG || (g0 + e >= 0 && g0 + e < Ng));
+        float2 x = in ? a.psi[base + (int64_t)e * estride] : make_float2(0.f, 0.f);
+        if constexpr (AXIS == 2) keep[n1] = x;
+        if constexpr (SEG) x = cscale(x, a.wloc[e]);
+        v[n1] = x;
     });
 
     if (a.dft_on && activeA) {
@@ -131,18 +149,22 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     }
     dft<N1, 1>(v);
 
-    // ---- epilogue ----
+    // ---- epilogue (only core elements are written) ----
     if (valid) {
         if constexpr (AXIS == 0) {
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
-                a.L[base + n2 + N2 * n1] = v[n1];
+                const int e = n2 + N2 * n1;
+                if (!SEG || (e >= H && e < H + C)) a.L[base + e] = v[n1];
             });
         } else if constexpr (AXIS == 1) {
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
-                const int64_t ad = base + (int64_t)(n2 + N2 * n1) * estride;
-                a.L[ad] = cadd(a.L[ad], v[n1]);
+                const int e = n2 + N2 * n1;
+                if (!SEG || (e >= H && e < H + C)) {
+                    const int64_t ad = base + (int64_t)e * estride;
+                    a.L[ad] = cadd(a.L[ad], v[n1]);
+                }
             });
         } else {
             const float2 Zx = a.ax[0].zt[px], Dx = a.ax[0].dz[px];
@@ -153,16 +175,19 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
-                const int64_t ad = base + (int64_t)e * estride;
-                const float2 Lt = cadd(a.L[ad], v[n1]);
-                const float2 po = a.psi_old[ad];
-                const float vv = a.v2[ad];
-                const float2 s = cadd(cmul(SA, T.zt[e]), cmul(SB, T.dz[e]));
-                float2 q = cadd(Lt, cscale(keep[n1], vv));
-                q = cadd(q, cmul(a.sigma, s));
-                const float g = gxy * T.gam[e];
-                // psi^{n+1} = Gamma (psi^{n-1} - i q)
-                a.psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                if (!SEG || (e >= H && e < H + C)) {
+                    const int z = g0 + e;
+                    const int64_t ad = base + (int64_t)e * estride;
+                    const float2 Lt = cadd(a.L[ad], v[n1]);
+                    const float2 po = a.psi_old[ad];
+                    const float vv = a.v2[ad];
+                    const float2 s = cadd(cmul(SA, T.zt[z]), cmul(SB, T.dz[z]));
+                    float2 q = cadd(Lt, cscale(keep[n1], vv));
+                    q = cadd(q, cmul(a.sigma, s));
+                    const float g = gxy * T.gam[z];
+                    // psi^{n+1} = Gamma (psi^{n-1} - i q)
+                    a.psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                }
             });
         }
     }
@@ -171,13 +196,14 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     if (a.dft_on && t < P * 4) {
         const int p = t >> 2;
         const int q = t & 3;
+        const int side = q & 1;
         int64_t pt = -1;
         if constexpr (AXIS == 0) {
-            const int64_t row = (int64_t)blockIdx.x * P + p;
-            if (row < (int64_t)a.ny * a.nz) pt = row;
+            const int64_t qq = (int64_t)blockIdx.x * P + p;
+            if (qq < (int64_t)a.ny * a.nz * nseg && (int)(qq % nseg) == a.seg_plane[side]) pt = qq / nseg;
         } else {
             const int x = blockIdx.x * P + p;
-            if (x < a.nx) pt = x + (int64_t)a.nx * blockIdx.y;
+            if (x < a.nx && (int)(blockIdx.y % nseg) == a.seg_plane[side]) pt = x + (int64_t)a.nx * (blockIdx.y / nseg);
         }
         if (pt >= 0) {
             float2 s = make_float2(0.f, 0.f);
@@ -185,15 +211,14 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
             const double re = (double)s.x, im = (double)s.y;
             const double zr = a.w.x * re - a.w.y * im;
             const double zi = a.w.x * im + a.w.y * re;
-            const int side = q & 1;
             const int field = (q >> 1) * 2;
             double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
-            double2* C = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
-            double2 sv = *S, cv = *C;
+            double2* Cc = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
+            double2 sv = *S, cv = *Cc;
             neumaier(sv.x, cv.x, zr);
             neumaier(sv.y, cv.y, zi);
             *S = sv;
-            *C = cv;
+            *Cc = cv;
         }
     }
 }
@@ -231,6 +256,14 @@ struct Shape {
     X(256, 16, 16, 16)      \
     X(288, 16, 18, 16)
 
+// local lengths of the overlapping-subdomain mode
+#define PSTD_SEG_SHAPES(X) \
+    X(32, 4, 8, 32)        \
+    X(48, 6, 8, 32)        \
+    X(64, 8, 8, 32)        \
+    X(96, 8, 12, 16)       \
+    X(128, 8, 16, 16)
+
 bool pass_supported(int N) {
 #define PSTD_CASE(n, a, b, p) \
     if (N == n) return true;
@@ -247,19 +280,20 @@ PassShape pass_shape(int N) {
     return PassShape{0, 0, 0, 0, 0};
 }
 
-template <int N, int N1, int N2, int P>
+template <int N, int N1, int N2, int P, bool SEG>
 static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t stream) {
     const int threads = Shape<N, N1, N2, P>::threads;
+    const int nseg = SEG ? args.nseg : 1;
     if (axis == 0) {
-        const int64_t rows = (int64_t)args.ny * args.nz;
-        dim3 grid((unsigned)((rows + P - 1) / P));
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0>), grid, dim3(threads), 0, stream, args);
+        const int64_t pencils = (int64_t)args.ny * args.nz * nseg;
+        dim3 grid((unsigned)((pencils + P - 1) / P));
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), grid, dim3(threads), 0, stream, args);
     } else if (axis == 1) {
-        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)args.nz);
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1>), grid, dim3(threads), 0, stream, args);
+        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)(args.nz * nseg));
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), grid, dim3(threads), 0, stream, args);
     } else {
-        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)args.ny);
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2>), grid, dim3(threads), 0, stream, args);
+        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)(args.ny * nseg));
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), grid, dim3(threads), 0, stream, args);
     }
     return hipGetLastError();
 }
@@ -267,8 +301,24 @@ static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t strea
 hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream) {
     const int N = axis == 0 ? args.nx : axis == 1 ? args.ny : args.nz;
 #define PSTD_CASE(n, a, b, p) \
-    if (N == n) return launch_shape<n, a, b, p>(axis, args, stream);
+    if (N == n) return launch_shape<n, a, b, p, false>(axis, args, stream);
     PSTD_SHAPES(PSTD_CASE)
+#undef PSTD_CASE
+    return hipErrorInvalidValue;
+}
+
+bool seg_supported(int N) {
+#define PSTD_CASE(n, a, b, p) \
+    if (N == n) return true;
+    PSTD_SEG_SHAPES(PSTD_CASE)
+#undef PSTD_CASE
+    return false;
+}
+
+hipError_t launch_pass_seg(int axis, int nloc, const PassArgs& args, hipStream_t stream) {
+#define PSTD_CASE(n, a, b, p) \
+    if (nloc == n) return launch_shape<n, a, b, p, true>(axis, args, stream);
+    PSTD_SEG_SHAPES(PSTD_CASE)
 #undef PSTD_CASE
     return hipErrorInvalidValue;
 }

@@ -57,6 +57,9 @@ class Problem:
     surf_lo: tuple = (10, 10, 10)
     surf_hi: tuple = (38, 38, 38)
     eta_on_source: bool = False
+    sub_core: tuple = ()
+    sub_halo: int = 0
+    sub_taper: int = 0
 
     def replace(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)
@@ -227,7 +230,8 @@ def cfg3_global(n_fft=288, seed=3):
     prob = Problem(n=n, h=(h, h, h), k0=k0, abc_cells=(P,) * 3, abc_alpha=alpha,
                    abc_U0=paper_u0(alpha, k0 * h, P), tfsf=(tf,) * 3,
                    v_max=float(np.abs(V).max()), n_steps=1000, dft_begin=0, dft_end=0,
-                   surf_lo=(20,) * 3, surf_hi=(n_fft - 20,) * 3)
+                   surf_lo=(20,) * 3, surf_hi=(n_fft - 20,) * 3,
+                   sub_core=(48, 48, 48), sub_halo=8, sub_taper=3)
     return prob, V
 
 

@@ -74,3 +74,12 @@ def test_create_rejects_unstable_step():
     _expect("PSTD_EUNSTABLE", prob.replace(dt=0.1 * 0.1 ** 2))
     ok = lib_mod.problem_from(prob.replace(dt=0.99 * opstd.critical_dt(prob, prob.v_max)))
     assert lib_mod.pstd_reduced_step(ok)[0] > 0
+
+
+def test_subdomain_validation():
+    prob, _ = synth.cfg3_global()
+    p = lib_mod.problem_from(prob)
+    assert list(p.sub_core) == [48, 48, 48] and p.sub_halo == 8 and p.sub_taper == 3
+    _expect("PSTD_EINVAL", prob.replace(sub_taper=4))                       # halo < taper + 5
+    _expect("PSTD_EINVAL", prob.replace(sub_core=(50, 48, 48)))            # does not tile 288
+    _expect("PSTD_EUNSUPPORTED", prob.replace(sub_core=(72, 48, 48)))      # local length 88
