@@ -63,6 +63,7 @@ def main():
     s = P.Solver(prob, stream=stream)
     s.set_potential(V)
     cells = prob.cells
+    tiles = s.autotune(reps=5)
 
     s.run(args.warmup)
     torch.cuda.synchronize()
@@ -115,6 +116,7 @@ def main():
             "traffic": None,
             "bytes_per_cell": PASS_BYTES[dom],
             "pass_ms": {k: round(v, 5) for k, v in avg.items()},
+            "tiles": {k: list(tiles[i]) for i, k in enumerate("xyz")},
             "step_frac_28B": round(STEP_BYTES * cells / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         },
         "wall_s": round(wall, 4),

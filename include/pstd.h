@@ -128,6 +128,16 @@ pstd_status pstd_run(pstd_solver* s, int64_t n_steps);
  * x, y and z passes.  Synchronises. */
 pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host);
 
+/* Pick, for each axis pass, the fastest compiled tile shape (FFT factor
+ * order N1 x N2 and pencils per workgroup) by timing `reps` launches of every
+ * candidate on scratch buffers of the solver's size; the solver's state is
+ * not touched.  Synchronises.  ENOMEM if the scratch cannot be allocated. */
+pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
+
+/* Tile shape used by the pass along axis (0, 1, 2): info_host[4] =
+ * {N, N1, N2, pencils per workgroup}.  Host only. */
+pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host);
+
 /* Number of steps taken (the current level is psi^step). */
 pstd_status pstd_step_index(const pstd_solver* s, int64_t* step_out_host);
 

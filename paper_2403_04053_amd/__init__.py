@@ -15,14 +15,14 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_destroy", "pstd_status_string", "pstd_last_error", "Solver",
+    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_status_string", "pstd_last_error", "Solver",
     "EXPORTED",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpstd.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_04053_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2403_04053_amd/build.py`")
 
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -113,6 +113,8 @@ _SIGS = {
     "pstd_project": [_vp, _vp, _i64, _vp],
     "pstd_far_field": [_vp, _vp, _i64, _vp],
     "pstd_destroy": [_vp],
+    "pstd_autotune": [_vp, ctypes.c_int32],
+    "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -227,6 +229,16 @@ def pstd_far_field(solver, dir_dev, n_dir, out_dev):
     _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
 
 
+def pstd_autotune(solver, reps=5):
+    _check(lib.pstd_autotune(solver, int(reps)), solver)
+
+
+def pstd_tile_info(solver, axis):
+    out = (ctypes.c_int32 * 4)()
+    _check(lib.pstd_tile_info(solver, int(axis), out), solver)
+    return tuple(out)
+
+
 def pstd_destroy(solver):
     _check(lib.pstd_destroy(solver))
 
@@ -271,6 +283,13 @@ class Solver:
 
     def run(self, n_steps):
         pstd_run(self.handle, n_steps)
+
+    def autotune(self, reps=5):
+        pstd_autotune(self.handle, reps)
+        return [pstd_tile_info(self.handle, a) for a in range(3)]
+
+    def tiles(self):
+        return [pstd_tile_info(self.handle, a) for a in range(3)]
 
     def run_timed(self, n_steps):
         return pstd_run_timed(self.handle, n_steps)

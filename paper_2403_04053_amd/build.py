@@ -1,6 +1,6 @@
 """Build libpstd.so (HIP for gfx950) in the package directory.
 
-    python -m paper_2403_04053_amd.build
+    python paper_2403_04053_amd/build.py
 """
 from __future__ import annotations
 

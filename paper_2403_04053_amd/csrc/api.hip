@@ -39,6 +39,7 @@ struct pstd_solver {
     const float* wloc[3] = {nullptr, nullptr, nullptr};
     double2* acc[3] = {nullptr, nullptr, nullptr};
     int64_t points[3] = {0, 0, 0};
+    int variant[3] = {0, 0, 0};   // tile shape of each axis pass
     pstd::ProjectState* proj = nullptr;
     std::string err;
 };
@@ -106,11 +107,12 @@ pstd_status validate(const pstd_problem* p) {
             if (N % C) return fail(nullptr, PSTD_EINVAL, "sub_core must divide the grid length");
             if (p->sub_taper < 0 || p->sub_halo < p->sub_taper + 5)
                 return fail(nullptr, PSTD_EINVAL, "sub_halo must be at least sub_taper + 5 (Section 2.6)");
-            if (!pstd::seg_supported(nloc))
+            int v;
+            if (pstd::pass_variants(nloc, true, &v, 1) == 0)
                 return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for local length " + std::to_string(nloc));
         } else if (p->sub_core[a] < 0) {
             return fail(nullptr, PSTD_EINVAL, "sub_core must be >= 0");
-        } else if (!pstd::pass_supported(N)) {
+        } else if (int v; pstd::pass_variants(N, false, &v, 1) == 0) {
             return fail(nullptr, PSTD_EUNSUPPORTED, "no FFT pass compiled for axis length " + std::to_string(N));
         }
         const int* y = p->tfsf[a];
@@ -261,12 +263,21 @@ pstd_status build_tables(pstd_solver* s) {
 // over the window steps that have run
 double incident_phasor(const pstd_solver* s) { return s->inc_sum; }
 
-pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
-    const int64_t n = s->step;
-    const double tau = n * s->dtau;
-    const double R = ramp_of(tau, s->tau_r);
-    const double f = 2.0 * s->dtau * R * (s->prob.eta_on_source ? s->eta : 1.0);
-    pstd::PassArgs a{};
+// fields of the pass arguments that depend on the axis
+void axis_args(const pstd_solver* s, int axis, pstd::PassArgs& a) {
+    const pstd_problem& p = s->prob;
+    plane_local(p, axis, 0, &a.seg_plane[0], &a.plane_lo);
+    plane_local(p, axis, 1, &a.seg_plane[1], &a.plane_hi);
+    a.acc = s->acc[axis];
+    a.points = s->points[axis];
+    const bool seg = p.sub_core[axis] > 0;
+    a.seg_core = seg ? p.sub_core[axis] : 0;
+    a.seg_halo = seg ? p.sub_halo : 0;
+    a.nseg = seg ? p.n[axis] / p.sub_core[axis] : 1;
+    a.wloc = s->wloc[axis];
+}
+
+void common_args(const pstd_solver* s, pstd::PassArgs& a) {
     a.psi = s->cur;
     a.L = s->L;
     a.psi_old = s->old;
@@ -275,24 +286,24 @@ pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
     a.ny = s->prob.n[1];
     a.nz = s->prob.n[2];
     for (int i = 0; i < 3; ++i) a.ax[i] = s->ax[i];
+}
+
+pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
+    const int64_t n = s->step;
+    const double tau = n * s->dtau;
+    const double R = ramp_of(tau, s->tau_r);
+    const double f = 2.0 * s->dtau * R * (s->prob.eta_on_source ? s->eta : 1.0);
+    pstd::PassArgs a{};
+    common_args(s, a);
     a.sigma = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
     a.dft_on = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
     if (a.dft_on) s->inc_sum += R;
     a.w = make_double2(std::cos(tau), std::sin(tau));
     for (int axis = 0; axis < 3; ++axis) {
-        const pstd_problem& p = s->prob;
-        plane_local(p, axis, 0, &a.seg_plane[0], &a.plane_lo);
-        plane_local(p, axis, 1, &a.seg_plane[1], &a.plane_hi);
-        a.acc = s->acc[axis];
-        a.points = s->points[axis];
-        const bool seg = p.sub_core[axis] > 0;
-        a.seg_core = seg ? p.sub_core[axis] : 0;
-        a.seg_halo = seg ? p.sub_halo : 0;
-        a.nseg = seg ? p.n[axis] / p.sub_core[axis] : 1;
-        a.wloc = s->wloc[axis];
+        axis_args(s, axis, a);
+        const bool seg = s->prob.sub_core[axis] > 0;
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], s->stream));
-        hipError_t e = seg ? pstd::launch_pass_seg(axis, local_len(p, axis), a, s->stream)
-                           : pstd::launch_pass(axis, a, s->stream);
+        hipError_t e = pstd::launch_variant(s->variant[axis], seg, axis, a, s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], s->stream));
     }
@@ -389,6 +400,7 @@ pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** o
         return cleanup(hip_fail(s, e, "hipMalloc state"));
     for (int a = 0; a < 3; ++a)
         if ((e = hipMalloc(&s->acc[a], 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMalloc acc"));
+    for (int a = 0; a < 3; ++a) pstd::pass_variants(local_len(*p, a), p->sub_core[a] > 0, &s->variant[a], 1);
     if ((st = build_tables(s))) return cleanup(st);
     if ((e = hipMemsetAsync(s->cur, 0, s->cells * sizeof(float2), s->stream)) ||
         (e = hipMemsetAsync(s->old, 0, s->cells * sizeof(float2), s->stream)) ||
@@ -479,6 +491,87 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
     for (int a = 0; a < 3; ++a) pass_ms[a] = sum[a];
     return st;
+}
+
+pstd_status pstd_autotune(pstd_solver* s, int32_t reps) {
+    if (!s || reps < 1) return PSTD_EINVAL;
+    // time every compiled tile shape of each axis on scratch state (the
+    // solver's own state is left untouched) and keep the fastest
+    float2 *tcur = nullptr, *told = nullptr, *tL = nullptr;
+    double2* tacc[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pstd_status st = PSTD_OK;
+    auto release = [&]() {
+        (void)hipFree(tcur);
+        (void)hipFree(told);
+        (void)hipFree(tL);
+        for (int a = 0; a < 3; ++a) (void)hipFree(tacc[a]);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&tcur, s->cells * sizeof(float2))) || (e = hipMalloc(&told, s->cells * sizeof(float2))) ||
+        (e = hipMalloc(&tL, s->cells * sizeof(float2))) || (e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+        release();
+        return hip_fail(s, e, "autotune scratch");
+    }
+    for (int a = 0; a < 3 && !e; ++a) e = hipMalloc(&tacc[a], 8 * s->points[a] * sizeof(double2));
+    if (!e) e = hipMemsetAsync(tcur, 0, s->cells * sizeof(float2), s->stream);
+    if (!e) e = hipMemsetAsync(told, 0, s->cells * sizeof(float2), s->stream);
+    for (int a = 0; a < 3 && !e; ++a) e = hipMemsetAsync(tacc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream);
+    if (e) {
+        release();
+        return hip_fail(s, e, "autotune scratch");
+    }
+    pstd::PassArgs args{};
+    common_args(s, args);
+    args.psi = tcur;
+    args.psi_old = told;
+    args.L = tL;
+    args.dft_on = 1;
+    args.w = make_double2(1.0, 0.0);
+    args.sigma = make_float2(0.f, 0.f);
+    for (int axis = 0; axis < 3 && !st; ++axis) {
+        const bool seg = s->prob.sub_core[axis] > 0;
+        int ids[16];
+        const int nv = std::min(16, pstd::pass_variants(local_len(s->prob, axis), seg, ids, 16));
+        if (nv <= 1) continue;
+        axis_args(s, axis, args);
+        args.acc = tacc[axis];
+        float best = 1e30f;
+        for (int k = 0; k < nv && !st; ++k) {
+            if ((e = pstd::launch_variant(ids[k], seg, axis, args, s->stream)) ||
+                (e = hipEventRecord(e0, s->stream))) {
+                st = hip_fail(s, e, "autotune launch");
+                break;
+            }
+            for (int r = 0; r < reps && !e; ++r) e = pstd::launch_variant(ids[k], seg, axis, args, s->stream);
+            float ms = 0;
+            if (!e) e = hipEventRecord(e1, s->stream);
+            if (!e) e = hipEventSynchronize(e1);
+            if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e) {
+                st = hip_fail(s, e, "autotune timing");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                s->variant[axis] = ids[k];
+            }
+        }
+    }
+    release();
+    return st;
+}
+
+pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host) {
+    if (!s || !info_host || axis < 0 || axis > 2) return PSTD_EINVAL;
+    const pstd::PassShape sh = pstd::variant_shape(s->variant[axis]);
+    info_host[0] = sh.N;
+    info_host[1] = sh.N1;
+    info_host[2] = sh.N2;
+    info_host[3] = sh.P;
+    return PSTD_OK;
 }
 
 pstd_status pstd_step_index(const pstd_solver* s, int64_t* out) {

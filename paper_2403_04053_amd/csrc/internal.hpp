@@ -43,12 +43,11 @@ struct PassShape {
     int N, N1, N2, P, threads;
 };
 
-bool pass_supported(int N);
-PassShape pass_shape(int N);
-// Launch the pass along `axis` (0, 1, 2) for the axis length args.{nx,ny,nz}[axis]
-hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream);
-// Segmented pass: local pencils of length nloc = seg_core + 2 seg_halo
-bool seg_supported(int nloc);
-hipError_t launch_pass_seg(int axis, int nloc, const PassArgs& args, hipStream_t stream);
+// Compiled tile-shape variants for local length N (segmented: with a
+// subdomain instance).  Writes up to cap variant ids, returns the count.
+int pass_variants(int N, bool segmented, int* out, int cap);
+PassShape variant_shape(int v);
+// Launch variant v for the pass along `axis` (0, 1, 2)
+hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs& args, hipStream_t stream);
 
 }  // namespace pstd

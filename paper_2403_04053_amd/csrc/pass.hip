@@ -11,7 +11,9 @@
 //
 // Loads and stores are coalesced without an LDS transpose: the x pass gives
 // consecutive lanes consecutive elements of a row; the y and z passes give
-// consecutive lanes consecutive x of a tile of P pencils.
+// consecutive lanes consecutive x of a tile of P pencils.  The per-axis
+// tables (twiddles, kbar^2, derivative rows) are staged in LDS once per
+// workgroup.
 //
 // Epilogues: x pass writes L; y pass adds to L; z pass adds its term and
 // applies the leapfrog update with potential, TF/SF source and absorber,
@@ -19,6 +21,11 @@
 // accumulates, in FP64 with Neumaier compensation, the DFT of psi and of its
 // spectral normal derivative on the two planes normal to its axis
 // (Eqs. psiphasor, dpsiphasor).
+//
+// Segmented mode (overlapping subdomains, Section 2.6): a pencil is split
+// into segments of C core points; each segment is transformed as a local
+// array of N = C + 2H points read from the global array with the halo
+// weights, and only its core points are written.
 #include "dft.hpp"
 #include "internal.hpp"
 
@@ -33,19 +40,34 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 
 template <int N, int N1, int N2, int P, int AXIS, bool SEG>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs a) {
+    constexpr int NT = P * (N1 > N2 ? N1 : N2);
     constexpr int ROW = N2 + 1;                 // padded exchange row
-    constexpr int STRIDE = (N1 * ROW) | 1;      // odd pencil stride (float2)
+    // odd pencil stride (float2); also holds the four DFT partials per thread
+    constexpr int STRIDE = (N1 * ROW > 4 * N2 ? N1 * ROW : 4 * N2) | 1;
     __shared__ float2 ex[P * STRIDE];
-    __shared__ float2 red[P * N2 * 4];
+    __shared__ float2 s_tw[N];
+    __shared__ float s_kk[N];
+    __shared__ float2 s_dl[N], s_dh[N];
 
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
     const int pA = AXIS == 0 ? t / N2 : t % P;
     const int n2 = AXIS == 0 ? t % N2 : t / P;
     const AxisTables& T = a.ax[AXIS];
-    // segmented pencils (overlapping subdomains): element e of segment `seg`
-    // is global index seg * C - H + e, weighted by wloc[e]; plain pencils have
-    // one segment with C = N, H = 0
+    const bool surf = a.dft_on != 0;
+
+    // tables to LDS (issued before the field loads)
+    for (int i = t; i < N; i += NT) {
+        s_tw[i] = T.tw[i];
+        s_kk[i] = T.kk[i];
+        if (surf) {
+            s_dl[i] = T.dlo[i];
+            s_dh[i] = T.dhi[i];
+        }
+    }
+
+    // segmented pencils: element e of segment `seg` is global index
+    // seg * C - H + e, weighted by wloc[e]; plain pencils: C = N, H = 0
     const int C = SEG ? a.seg_core : N;
     const int H = SEG ? a.seg_halo : 0;
     const int nseg = SEG ? a.nseg : 1;
@@ -91,23 +113,26 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         if constexpr (SEG) x = cscale(x, a.wloc[e]);
         v[n1] = x;
     });
+    // plane values: read directly by the thread that owns the element
+    // (planes lie in a core, where the halo weight is 1)
+    float2 plo = make_float2(0.f, 0.f), phi = plo;
+    if (surf && valid) {
+        if (n2 == a.plane_lo % N2 && seg == a.seg_plane[0]) plo = a.psi[base + (int64_t)a.plane_lo * estride];
+        if (n2 == a.plane_hi % N2 && seg == a.seg_plane[1]) phi = a.psi[base + (int64_t)a.plane_hi * estride];
+    }
+    __syncthreads();
 
-    if (a.dft_on && activeA) {
-        float2 lo = make_float2(0.f, 0.f), hi = lo, dlo = lo, dhi = lo;
+    // spectral normal derivative on the two planes: partial dot products
+    float2 dlo = make_float2(0.f, 0.f), dhi = dlo;
+    if (surf) {
         unroll<N1>([&](auto i) {
             constexpr int n1 = decltype(i)::value;
             const int e = n2 + N2 * n1;
-            if (e == a.plane_lo) lo = v[n1];
-            if (e == a.plane_hi) hi = v[n1];
-            const float2 cl = T.dlo[e], ch = T.dhi[e];
-            dlo = cadd(dlo, cmul(cl, v[n1]));
-            dhi = cadd(dhi, cmul(ch, v[n1]));
+            if (e < N) {
+                dlo = cadd(dlo, cmul(s_dl[e], v[n1]));
+                dhi = cadd(dhi, cmul(s_dh[e], v[n1]));
+            }
         });
-        float2* r = &red[(pA * N2 + n2) * 4];
-        r[0] = lo;
-        r[1] = hi;
-        r[2] = dlo;
-        r[3] = dhi;
     }
 
     // ---- forward: stage A (N1-point DFTs), twiddle, exchange ----
@@ -116,7 +141,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         unroll<N1>([&](auto i) {
             constexpr int k1 = decltype(i)::value;
             float2 x = v[k1];
-            if constexpr (k1 != 0) x = cmul(x, T.tw[n2 * k1]);
+            if constexpr (k1 != 0) x = cmul(x, s_tw[n2 * k1]);
             ex[pA * STRIDE + k1 * ROW + n2] = x;
         });
     }
@@ -131,13 +156,13 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         dft<N2, -1>(u);
         unroll<N2>([&](auto i) {
             constexpr int k2 = decltype(i)::value;
-            u[k2] = cscale(u[k2], T.kk[k1 + N1 * k2]);
+            u[k2] = cscale(u[k2], s_kk[k1 + N1 * k2]);
         });
         dft<N2, 1>(u);
         unroll<N2>([&](auto i) {
             constexpr int nn = decltype(i)::value;
             float2 x = u[nn];
-            if constexpr (nn != 0) x = cmulc(x, T.tw[nn * k1]);
+            if constexpr (nn != 0) x = cmulc(x, s_tw[nn * k1]);
             ex[pB * STRIDE + k1 * ROW + nn] = x;
         });
     }
@@ -193,96 +218,89 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     }
 
     // ---- surface DFT: reduce the per-thread partials, accumulate in FP64 ----
-    if (a.dft_on && t < P * 4) {
-        const int p = t >> 2;
-        const int q = t & 3;
-        const int side = q & 1;
-        int64_t pt = -1;
-        if constexpr (AXIS == 0) {
-            const int64_t qq = (int64_t)blockIdx.x * P + p;
-            if (qq < (int64_t)a.ny * a.nz * nseg && (int)(qq % nseg) == a.seg_plane[side]) pt = qq / nseg;
-        } else {
-            const int x = blockIdx.x * P + p;
-            if (x < a.nx && (int)(blockIdx.y % nseg) == a.seg_plane[side]) pt = x + (int64_t)a.nx * (blockIdx.y / nseg);
+    if (surf) {
+        __syncthreads();  // every thread has read its exchange slots
+        if (activeA) {
+            float2* r = &ex[pA * STRIDE + n2 * 4];
+            r[0] = plo;
+            r[1] = phi;
+            r[2] = dlo;
+            r[3] = dhi;
         }
-        if (pt >= 0) {
-            float2 s = make_float2(0.f, 0.f);
-            for (int m = 0; m < N2; ++m) s = cadd(s, red[(p * N2 + m) * 4 + q]);
-            const double re = (double)s.x, im = (double)s.y;
-            const double zr = a.w.x * re - a.w.y * im;
-            const double zi = a.w.x * im + a.w.y * re;
-            const int field = (q >> 1) * 2;
-            double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
-            double2* Cc = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
-            double2 sv = *S, cv = *Cc;
-            neumaier(sv.x, cv.x, zr);
-            neumaier(sv.y, cv.y, zi);
-            *S = sv;
-            *Cc = cv;
+        __syncthreads();
+        if (t < P * 4) {
+            const int p = t >> 2;
+            const int q = t & 3;
+            const int side = q & 1;
+            int64_t pt = -1;
+            if constexpr (AXIS == 0) {
+                const int64_t qq = (int64_t)blockIdx.x * P + p;
+                if (qq < (int64_t)a.ny * a.nz * nseg && (int)(qq % nseg) == a.seg_plane[side]) pt = qq / nseg;
+            } else {
+                const int x = blockIdx.x * P + p;
+                if (x < a.nx && (int)(blockIdx.y % nseg) == a.seg_plane[side])
+                    pt = x + (int64_t)a.nx * (blockIdx.y / nseg);
+            }
+            if (pt >= 0) {
+                float2 s = make_float2(0.f, 0.f);
+                for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
+                const double re = (double)s.x, im = (double)s.y;
+                const double zr = a.w.x * re - a.w.y * im;
+                const double zi = a.w.x * im + a.w.y * re;
+                const int field = (q >> 1) * 2;
+                double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
+                double2* Cc = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
+                double2 sv = *S, cv = *Cc;
+                neumaier(sv.x, cv.x, zr);
+                neumaier(sv.y, cv.y, zi);
+                *S = sv;
+                *Cc = cv;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// supported lengths
+// compiled tile shapes: (N, N1, N2, P, with a segmented instance)
 // ---------------------------------------------------------------------------
 
-template <int N, int N1, int N2, int P>
-struct Shape {
-    static constexpr int threads = P * (N1 > N2 ? N1 : N2);
-};
+#define PSTD_VARIANTS(X)        \
+    X(8, 2, 4, 64, 0)           \
+    X(12, 3, 4, 64, 0)          \
+    X(16, 4, 4, 64, 0)          \
+    X(20, 4, 5, 32, 0)          \
+    X(24, 4, 6, 32, 0)          \
+    X(32, 4, 8, 32, 1)          \
+    X(40, 5, 8, 32, 0)          \
+    X(48, 6, 8, 32, 1)          \
+    X(48, 8, 6, 32, 0)          \
+    X(64, 8, 8, 32, 1)          \
+    X(64, 8, 8, 16, 1)          \
+    X(80, 8, 10, 16, 0)         \
+    X(96, 8, 12, 16, 1)         \
+    X(100, 10, 10, 16, 0)       \
+    X(108, 9, 12, 16, 0)        \
+    X(120, 10, 12, 16, 0)       \
+    X(128, 8, 16, 16, 1)        \
+    X(128, 16, 8, 16, 0)        \
+    X(128, 8, 16, 32, 0)        \
+    X(144, 12, 12, 16, 0)       \
+    X(150, 10, 15, 16, 0)       \
+    X(160, 10, 16, 16, 0)       \
+    X(160, 16, 10, 16, 0)       \
+    X(160, 10, 16, 32, 0)       \
+    X(160, 10, 16, 8, 0)        \
+    X(162, 9, 18, 16, 0)        \
+    X(180, 12, 15, 16, 0)       \
+    X(192, 12, 16, 16, 0)       \
+    X(256, 16, 16, 16, 0)       \
+    X(288, 16, 18, 16, 0)
 
-#define PSTD_SHAPES(X)      \
-    X(8, 2, 4, 64)          \
-    X(12, 3, 4, 64)         \
-    X(16, 4, 4, 64)         \
-    X(20, 4, 5, 32)         \
-    X(24, 4, 6, 32)         \
-    X(32, 4, 8, 32)         \
-    X(40, 5, 8, 32)         \
-    X(48, 6, 8, 32)         \
-    X(64, 8, 8, 32)         \
-    X(96, 8, 12, 16)        \
-    X(100, 10, 10, 16)      \
-    X(108, 9, 12, 16)       \
-    X(120, 10, 12, 16)      \
-    X(128, 8, 16, 16)       \
-    X(144, 12, 12, 16)      \
-    X(150, 10, 15, 16)      \
-    X(160, 10, 16, 16)      \
-    X(162, 9, 18, 16)       \
-    X(180, 12, 15, 16)      \
-    X(192, 12, 16, 16)      \
-    X(256, 16, 16, 16)      \
-    X(288, 16, 18, 16)
-
-// local lengths of the overlapping-subdomain mode
-#define PSTD_SEG_SHAPES(X) \
-    X(32, 4, 8, 32)        \
-    X(48, 6, 8, 32)        \
-    X(64, 8, 8, 32)        \
-    X(96, 8, 12, 16)       \
-    X(128, 8, 16, 16)
-
-bool pass_supported(int N) {
-#define PSTD_CASE(n, a, b, p) \
-    if (N == n) return true;
-    PSTD_SHAPES(PSTD_CASE)
-#undef PSTD_CASE
-    return false;
-}
-
-PassShape pass_shape(int N) {
-#define PSTD_CASE(n, a, b, p) \
-    if (N == n) return PassShape{n, a, b, p, Shape<n, a, b, p>::threads};
-    PSTD_SHAPES(PSTD_CASE)
-#undef PSTD_CASE
-    return PassShape{0, 0, 0, 0, 0};
-}
+using LaunchFn = hipError_t (*)(int axis, const PassArgs& args, hipStream_t stream);
 
 template <int N, int N1, int N2, int P, bool SEG>
 static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t stream) {
-    const int threads = Shape<N, N1, N2, P>::threads;
+    constexpr int threads = P * (N1 > N2 ? N1 : N2);
     const int nseg = SEG ? args.nseg : 1;
     if (axis == 0) {
         const int64_t pencils = (int64_t)args.ny * args.nz * nseg;
@@ -298,29 +316,48 @@ static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t strea
     return hipGetLastError();
 }
 
-hipError_t launch_pass(int axis, const PassArgs& args, hipStream_t stream) {
-    const int N = axis == 0 ? args.nx : axis == 1 ? args.ny : args.nz;
-#define PSTD_CASE(n, a, b, p) \
-    if (N == n) return launch_shape<n, a, b, p, false>(axis, args, stream);
-    PSTD_SHAPES(PSTD_CASE)
-#undef PSTD_CASE
-    return hipErrorInvalidValue;
+namespace {
+
+struct VariantEntry {
+    PassShape shape;
+    LaunchFn plain;
+    LaunchFn seg;  // null when the shape has no segmented instance
+};
+
+template <int N, int N1, int N2, int P, int S>
+constexpr LaunchFn seg_fn() {
+    if constexpr (S != 0) return &launch_shape<N, N1, N2, P, true>;
+    else return nullptr;
 }
 
-bool seg_supported(int N) {
-#define PSTD_CASE(n, a, b, p) \
-    if (N == n) return true;
-    PSTD_SEG_SHAPES(PSTD_CASE)
-#undef PSTD_CASE
-    return false;
+const VariantEntry kVariants[] = {
+#define PSTD_ENTRY(n, a, b, p, s) \
+    {PassShape{n, a, b, p, p * (a > b ? a : b)}, &launch_shape<n, a, b, p, false>, seg_fn<n, a, b, p, s>()},
+    PSTD_VARIANTS(PSTD_ENTRY)
+#undef PSTD_ENTRY
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+}  // namespace
+
+int pass_variants(int N, bool segmented, int* out, int cap) {
+    int k = 0;
+    for (int i = 0; i < kNumVariants; ++i) {
+        if (kVariants[i].shape.N != N) continue;
+        if (segmented && !kVariants[i].seg) continue;
+        if (k < cap) out[k] = i;
+        ++k;
+    }
+    return k;
 }
 
-hipError_t launch_pass_seg(int axis, int nloc, const PassArgs& args, hipStream_t stream) {
-#define PSTD_CASE(n, a, b, p) \
-    if (nloc == n) return launch_shape<n, a, b, p, true>(axis, args, stream);
-    PSTD_SEG_SHAPES(PSTD_CASE)
-#undef PSTD_CASE
-    return hipErrorInvalidValue;
+PassShape variant_shape(int v) { return kVariants[v].shape; }
+
+hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs& args, hipStream_t stream) {
+    if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
+    LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
+    if (!f) return hipErrorInvalidValue;
+    return f(axis, args, stream);
 }
 
 }  // namespace pstd
