@@ -170,6 +170,36 @@ pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir,
 
 pstd_status pstd_destroy(pstd_solver* s);
 
+/*
+ * Batched solves.  `count` independent problems (own grids, directions,
+ * energies, potentials, steps) advanced together: per axis the instances are
+ * grouped by FFT tile shape and each group is one launch; step groups are
+ * replayed from a HIP graph.  Every instance has the single-solver state and
+ * tables.
+ */
+typedef struct pstd_batch pstd_batch;  /* opaque; owns its instances */
+
+/* Create `count` instances from problems[0..count) on the current device.
+ * Synchronises.  Errors as pstd_create; the message names the instance. */
+pstd_status pstd_batch_create(const pstd_problem* problems, int32_t count, void* hip_stream, pstd_batch** out);
+pstd_status pstd_batch_size(const pstd_batch* b, int32_t* count_out_host);
+/* Borrowed handle of instance idx, for pstd_get_psi, pstd_get_surface_phasors,
+ * pstd_project, pstd_far_field, pstd_step_index, pstd_tile_info.  Owned by
+ * the batch: never pass it to pstd_destroy; pstd_run on it returns ESTATE
+ * (pstd_set_state works and takes effect at the next pstd_batch_run). */
+pstd_status pstd_batch_solver(pstd_batch* b, int32_t idx, pstd_solver** out);
+/* pstd_set_potential for instance idx. */
+pstd_status pstd_batch_set_potential(pstd_batch* b, int32_t idx, const float* V_dev, int64_t n_cells);
+/* Tile autotuning: the largest instance of each distinct pass length is
+ * tuned (as pstd_autotune) and its choice shared.  Synchronises. */
+pstd_status pstd_batch_autotune(pstd_batch* b, int32_t reps);
+/* Advance instance i by n_steps_host[i] steps (0 allowed); instances that
+ * reach their count stop while the others continue.  Asynchronous after the
+ * counters are set. */
+pstd_status pstd_batch_run(pstd_batch* b, const int64_t* n_steps_host);
+pstd_status pstd_batch_destroy(pstd_batch* b);
+const char* pstd_batch_last_error(const pstd_batch* b);
+
 const char* pstd_status_string(pstd_status st);
 const char* pstd_last_error(const pstd_solver* s);
 

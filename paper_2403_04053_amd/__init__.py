@@ -15,7 +15,9 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_status_string", "pstd_last_error", "Solver",
+    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_batch_create",
+    "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
+    "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
     "EXPORTED",
 ]
 
@@ -115,6 +117,13 @@ _SIGS = {
     "pstd_destroy": [_vp],
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "pstd_batch_create": [ctypes.c_void_p, ctypes.c_int32, _vp, ctypes.POINTER(_vp)],
+    "pstd_batch_size": [_vp, ctypes.POINTER(ctypes.c_int32)],
+    "pstd_batch_solver": [_vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+    "pstd_batch_set_potential": [_vp, ctypes.c_int32, _vp, _i64],
+    "pstd_batch_autotune": [_vp, ctypes.c_int32],
+    "pstd_batch_run": [_vp, ctypes.POINTER(_i64)],
+    "pstd_batch_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -124,9 +133,11 @@ lib.pstd_status_string.argtypes = [ctypes.c_int]
 lib.pstd_status_string.restype = ctypes.c_char_p
 lib.pstd_last_error.argtypes = [_vp]
 lib.pstd_last_error.restype = ctypes.c_char_p
+lib.pstd_batch_last_error.argtypes = [_vp]
+lib.pstd_batch_last_error.restype = ctypes.c_char_p
 
 # every symbol include/pstd.h declares
-EXPORTED = tuple(_SIGS) + ("pstd_status_string", "pstd_last_error")
+EXPORTED = tuple(_SIGS) + ("pstd_status_string", "pstd_last_error", "pstd_batch_last_error")
 
 
 def _ptr(x):
@@ -243,6 +254,51 @@ def pstd_destroy(solver):
     _check(lib.pstd_destroy(solver))
 
 
+def _bcheck(st, batch=None):
+    if st != 0:
+        raise PstdError(st, lib.pstd_batch_last_error(batch).decode(errors="replace"))
+
+
+def pstd_batch_create(problems, stream=None):
+    arr = (pstd_problem * len(problems))(*problems)
+    h = _vp()
+    _bcheck(lib.pstd_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(problems), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def pstd_batch_size(batch):
+    out = ctypes.c_int32()
+    _bcheck(lib.pstd_batch_size(batch, ctypes.byref(out)), batch)
+    return out.value
+
+
+def pstd_batch_solver(batch, idx):
+    h = _vp()
+    _bcheck(lib.pstd_batch_solver(batch, int(idx), ctypes.byref(h)), batch)
+    return h.value
+
+
+def pstd_batch_set_potential(batch, idx, V_dev, n_cells):
+    _bcheck(lib.pstd_batch_set_potential(batch, int(idx), _ptr(V_dev), int(n_cells)), batch)
+
+
+def pstd_batch_autotune(batch, reps=5):
+    _bcheck(lib.pstd_batch_autotune(batch, int(reps)), batch)
+
+
+def pstd_batch_run(batch, n_steps):
+    arr = (_i64 * len(n_steps))(*[int(v) for v in n_steps])
+    _bcheck(lib.pstd_batch_run(batch, arr), batch)
+
+
+def pstd_batch_destroy(batch):
+    _bcheck(lib.pstd_batch_destroy(batch))
+
+
+def pstd_batch_last_error(batch=None):
+    return lib.pstd_batch_last_error(batch).decode(errors="replace")
+
+
 class Solver:
     """Owning wrapper around a pstd_solver handle; buffers are torch tensors."""
 
@@ -333,3 +389,58 @@ class Solver:
         out = self.torch.empty(d.shape[0], dtype=self.torch.complex128, device=self.device)
         pstd_far_field(self.handle, d, d.shape[0], out)
         return out
+
+
+class _BorrowedSolver(Solver):
+    """View of one batch instance (not destroyed by Python)."""
+
+    def __init__(self, batch, idx, problem):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda")
+        self.problem = problem
+        self.n = tuple(problem.n[a] for a in range(3))
+        self.cells = self.n[0] * self.n[1] * self.n[2]
+        self.stream = batch.stream
+        self.handle = pstd_batch_solver(batch.handle, idx)
+        self._batch = batch
+
+    def close(self):
+        self.handle = None
+
+
+class Batch:
+    """Owning wrapper around a pstd_batch handle."""
+
+    def __init__(self, problems, stream=None):
+        self.problems = [p if isinstance(p, pstd_problem) else problem_from(p) for p in problems]
+        self.stream = stream
+        self.handle = pstd_batch_create(self.problems, stream)
+        self.count = len(self.problems)
+
+    def close(self):
+        if self.handle:
+            pstd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def instance(self, idx):
+        return _BorrowedSolver(self, idx, self.problems[idx])
+
+    def set_potential(self, idx, V):
+        import torch
+        t = torch.as_tensor(V, dtype=torch.float32, device="cuda").contiguous()
+        pstd_batch_set_potential(self.handle, idx, t, t.numel())
+
+    def autotune(self, reps=5):
+        pstd_batch_autotune(self.handle, reps)
+
+    def run(self, n_steps):
+        if isinstance(n_steps, int):
+            n_steps = [n_steps] * self.count
+        pstd_batch_run(self.handle, n_steps)

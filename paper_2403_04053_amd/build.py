@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpstd.so")
-SOURCES = ["pass.hip", "project.hip", "api.hip"]
+SOURCES = ["pass.hip", "project.hip", "api.hip", "batch.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -21,7 +21,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     objs = []
     procs = []
     for src in SOURCES:

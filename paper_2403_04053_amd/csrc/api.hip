@@ -1,50 +1,24 @@
-// Host side of libpstd: validation, FP64 table construction, device state and
-// the time-stepping loop.  See include/pstd.h for the contract.
+// Host side of libpstd: validation, FP64 table construction, device state,
+// the time-stepping loop (graph-replayed step groups) and the tile autotuner.
+// See include/pstd.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
-#include "../../include/pstd.h"
-#include "internal.hpp"
-#include "project.hpp"
+#include "solver.hpp"
 
 namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kGraphSteps = 16;  // steps per replayed graph
 
 thread_local std::string g_create_error;
-
-}  // namespace
-
-struct pstd_solver {
-    pstd_problem prob{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-    double E0 = 0, dtau = 0, eta = 0, tau_r = 0;
-    double dxb[3] = {0, 0, 0};
-    double kh[3] = {0, 0, 0};
-    int64_t cells = 0;
-    int64_t step = 0;
-    double inc_sum = 0;   // incident phasor at the origin over the window steps run so far
-    float2* cur = nullptr;
-    float2* old = nullptr;
-    float2* L = nullptr;
-    float* v2 = nullptr;
-    void* tables = nullptr;
-    pstd::AxisTables ax[3]{};
-    const float* wloc[3] = {nullptr, nullptr, nullptr};
-    double2* acc[3] = {nullptr, nullptr, nullptr};
-    int64_t points[3] = {0, 0, 0};
-    int variant[3] = {0, 0, 0};   // tile shape of each axis pass
-    pstd::ProjectState* proj = nullptr;
-    std::string err;
-};
-
-namespace {
 
 pstd_status fail(pstd_solver* s, pstd_status st, const std::string& msg) {
     if (s) s->err = msg;
@@ -57,9 +31,9 @@ pstd_status hip_fail(pstd_solver* s, hipError_t e, const char* what) {
     return fail(s, e == hipErrorOutOfMemory ? PSTD_ENOMEM : PSTD_EHIP, m);
 }
 
-#define HIP_TRY(s, call)                                   \
-    do {                                                   \
-        hipError_t _e = (call);                            \
+#define HIP_TRY(s, call)                                       \
+    do {                                                       \
+        hipError_t _e = (call);                                \
         if (_e != hipSuccess) return hip_fail((s), _e, #call); \
     } while (0)
 
@@ -259,13 +233,85 @@ pstd_status build_tables(pstd_solver* s) {
     return PSTD_OK;
 }
 
-// Eq. incpsiphasor at the origin: psi_inc(0, tau_n) exp(i tau_n) = R(tau_n), summed
-// over the window steps that have run
-double incident_phasor(const pstd_solver* s) { return s->inc_sum; }
 
-// fields of the pass arguments that depend on the axis
-void axis_args(const pstd_solver* s, int axis, pstd::PassArgs& a) {
+// ---------------------------------------------------------------------------
+// per-step tables and descriptors
+// ---------------------------------------------------------------------------
+
+pstd_status upload_descs(pstd_solver* s) {
+    pstd::PassArgs a[3];
+    int off[6];
+    for (int axis = 0; axis < 3; ++axis) {
+        pstd::solver_args(s, axis, a[axis]);
+        off[2 * axis] = 0;
+        off[2 * axis + 1] = a[axis].tiles;
+    }
+    HIP_TRY(s, hipMemcpy(s->desc, a, sizeof(a), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(s->off, off, sizeof(off), hipMemcpyHostToDevice));
+    return PSTD_OK;
+}
+
+// launch one step (three passes and the counter advance) on `stream`
+pstd_status launch_step(pstd_solver* s, hipStream_t stream, hipEvent_t* ev) {
+    for (int axis = 0; axis < 3; ++axis) {
+        pstd::PassArgs a;
+        pstd::solver_args(s, axis, a);
+        const bool seg = s->prob.sub_core[axis] > 0;
+        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], stream));
+        hipError_t e = pstd::launch_variant(s->variant[axis], seg, axis, s->desc + axis, s->off + 2 * axis, 1,
+                                            a.tiles, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "pass launch");
+        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
+    }
+    hipError_t e = pstd::launch_advance(s->ctr, 1, stream);
+    if (e != hipSuccess) return hip_fail(s, e, "advance launch");
+    return PSTD_OK;
+}
+
+pstd_status build_graph(pstd_solver* s) {
+    if (s->graph) return PSTD_OK;
+    if (!s->cap_stream) HIP_TRY(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    pstd_status st = PSTD_OK;
+    for (int i = 0; i < kGraphSteps && !st; ++i) st = launch_step(s, s->cap_stream, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "graph capture");
+    e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        s->graph = nullptr;
+        return hip_fail(s, e, "graph instantiate");
+    }
+    return PSTD_OK;
+}
+
+}  // namespace
+
+namespace pstd {
+
+pstd_status solver_fail(pstd_solver* s, pstd_status st, const std::string& msg) { return fail(s, st, msg); }
+pstd_status solver_hip_fail(pstd_solver* s, hipError_t e, const char* what) { return hip_fail(s, e, what); }
+
+void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
+    a = PassArgs{};
     const pstd_problem& p = s->prob;
+    a.buf[0] = s->buf[0];
+    a.buf[1] = s->buf[1];
+    a.L = s->L;
+    a.v2 = s->v2;
+    a.nx = p.n[0];
+    a.ny = p.n[1];
+    a.nz = p.n[2];
+    for (int i = 0; i < 3; ++i) a.ax[i] = s->ax[i];
+    a.ctr = s->ctr;
+    a.sigma_tab = s->sigma_tab;
+    a.w_tab = s->w_tab;
+    a.dft_tab = s->dft_tab;
     plane_local(p, axis, 0, &a.seg_plane[0], &a.plane_lo);
     plane_local(p, axis, 1, &a.seg_plane[1], &a.plane_hi);
     a.acc = s->acc[axis];
@@ -275,44 +321,202 @@ void axis_args(const pstd_solver* s, int axis, pstd::PassArgs& a) {
     a.seg_halo = seg ? p.sub_halo : 0;
     a.nseg = seg ? p.n[axis] / p.sub_core[axis] : 1;
     a.wloc = s->wloc[axis];
+    variant_tiles(s->variant[axis], axis, a);
 }
 
-void common_args(const pstd_solver* s, pstd::PassArgs& a) {
-    a.psi = s->cur;
-    a.L = s->L;
-    a.psi_old = s->old;
-    a.v2 = s->v2;
-    a.nx = s->prob.n[0];
-    a.ny = s->prob.n[1];
-    a.nz = s->prob.n[2];
-    for (int i = 0; i < 3; ++i) a.ax[i] = s->ax[i];
-}
-
-pstd_status step_once(pstd_solver* s, hipEvent_t* ev) {
-    const int64_t n = s->step;
-    const double tau = n * s->dtau;
-    const double R = ramp_of(tau, s->tau_r);
-    const double f = 2.0 * s->dtau * R * (s->prob.eta_on_source ? s->eta : 1.0);
-    pstd::PassArgs a{};
-    common_args(s, a);
-    a.sigma = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
-    a.dft_on = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
-    if (a.dft_on) s->inc_sum += R;
-    a.w = make_double2(std::cos(tau), std::sin(tau));
-    for (int axis = 0; axis < 3; ++axis) {
-        axis_args(s, axis, a);
-        const bool seg = s->prob.sub_core[axis] > 0;
-        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], s->stream));
-        hipError_t e = pstd::launch_variant(s->variant[axis], seg, axis, a, s->stream);
-        if (e != hipSuccess) return hip_fail(s, e, "pass launch");
-        if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], s->stream));
+pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
+    if (n_end <= s->tab_cap) return PSTD_OK;
+    int64_t cap = std::max<int64_t>(n_end, 2 * s->tab_cap);
+    cap = std::max<int64_t>(cap, 1024);
+    std::vector<float2> sig(cap);
+    std::vector<double2> w(cap);
+    std::vector<int> on(cap);
+    const double fac = 2.0 * s->dtau * (s->prob.eta_on_source ? s->eta : 1.0);
+    for (int64_t n = 0; n < cap; ++n) {
+        const double tau = n * s->dtau;
+        const double f = fac * ramp_of(tau, s->tau_r);
+        sig[n] = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
+        w[n] = make_double2(std::cos(tau), std::sin(tau));
+        on[n] = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
     }
-    std::swap(s->cur, s->old);
-    s->step = n + 1;
+    // queued steps may still read the old tables
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    (void)hipFree(s->sigma_tab);
+    (void)hipFree(s->w_tab);
+    (void)hipFree(s->dft_tab);
+    s->sigma_tab = nullptr;
+    s->w_tab = nullptr;
+    s->dft_tab = nullptr;
+    s->tab_cap = 0;
+    HIP_TRY(s, hipMalloc(&s->sigma_tab, cap * sizeof(float2)));
+    HIP_TRY(s, hipMalloc(&s->w_tab, cap * sizeof(double2)));
+    HIP_TRY(s, hipMalloc(&s->dft_tab, cap * sizeof(int)));
+    HIP_TRY(s, hipMemcpy(s->sigma_tab, sig.data(), cap * sizeof(float2), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(s->w_tab, w.data(), cap * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(s->dft_tab, on.data(), cap * sizeof(int), hipMemcpyHostToDevice));
+    s->tab_cap = cap;
+    s->tab_gen += 1;
+    return upload_descs(s);
+}
+
+void solver_account_steps(pstd_solver* s, int64_t from, int64_t to) {
+    for (int64_t n = std::max(from, s->prob.dft_begin); n < std::min(to, s->prob.dft_end); ++n)
+        s->inc_sum += ramp_of(n * s->dtau, s->tau_r);
+}
+
+void solver_drop_graph(pstd_solver* s) {
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+}
+
+pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ext_ctr, pstd_solver** out) {
+    *out = nullptr;
+    pstd_status st = validate(p);
+    if (st) return st;
+    pstd_solver* s = new pstd_solver();
+    s->prob = *p;
+    s->stream = stream;
+    (void)hipGetDevice(&s->device);
+    double crit;
+    reduced(p, &s->E0, s->dxb, &s->dtau, &s->eta, &crit);
+    if (s->dtau > crit * (1 + 1e-12) && !p->force_dt) {
+        delete s;
+        return fail(nullptr, PSTD_EUNSTABLE, "dt exceeds the bound of Eq. PSTDstability");
+    }
+    const double th = p->theta, ph = p->phi;
+    s->kh[0] = std::sin(th) * std::cos(ph);
+    s->kh[1] = std::sin(th) * std::sin(ph);
+    s->kh[2] = std::cos(th);
+    s->tau_r = 2 * kPi * p->ramp_periods;
+    s->cells = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    s->points[0] = (int64_t)p->n[1] * p->n[2];
+    s->points[1] = (int64_t)p->n[0] * p->n[2];
+    s->points[2] = (int64_t)p->n[0] * p->n[1];
+    auto cleanup = [&](pstd_status e) {
+        std::string m = s->err;
+        pstd_destroy(s);
+        g_create_error = m;
+        return e;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&s->buf[0], s->cells * sizeof(float2))) || (e = hipMalloc(&s->buf[1], s->cells * sizeof(float2))) ||
+        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))) ||
+        (e = hipMalloc(&s->desc, 3 * sizeof(pstd::PassArgs))) || (e = hipMalloc(&s->off, 6 * sizeof(int))))
+        return cleanup(hip_fail(s, e, "hipMalloc state"));
+    if (ext_ctr) {
+        s->ctr = ext_ctr;
+        s->owns_ctr = false;
+        s->in_batch = true;
+    } else if ((e = hipMalloc(&s->ctr, 2 * sizeof(int64_t)))) {
+        return cleanup(hip_fail(s, e, "hipMalloc counters"));
+    }
+    for (int a = 0; a < 3; ++a)
+        if ((e = hipMalloc(&s->acc[a], 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMalloc acc"));
+    for (int a = 0; a < 3; ++a) pass_variants(local_len(*p, a), p->sub_core[a] > 0, &s->variant[a], 1);
+    if ((st = build_tables(s))) return cleanup(st);
+    const int64_t c0[2] = {0, std::numeric_limits<int64_t>::max()};
+    if ((e = hipMemcpy(s->ctr, c0, sizeof(c0), hipMemcpyHostToDevice))) return cleanup(hip_fail(s, e, "counters"));
+    if ((e = hipMemset(s->buf[0], 0, s->cells * sizeof(float2))) || (e = hipMemset(s->buf[1], 0, s->cells * sizeof(float2))) ||
+        (e = hipMemset(s->v2, 0, s->cells * sizeof(float))))
+        return cleanup(hip_fail(s, e, "hipMemset"));
+    for (int a = 0; a < 3; ++a)
+        if ((e = hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMemset acc"));
+    if ((st = solver_ensure_tables(s, 1024))) return cleanup(st);
+    if ((e = hipDeviceSynchronize())) return cleanup(hip_fail(s, e, "sync"));
+    *out = s;
     return PSTD_OK;
 }
 
-}  // namespace
+pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
+    // time every compiled tile shape of each axis on scratch state (the
+    // solver's own state is left untouched) and keep the fastest
+    float2 *tb0 = nullptr, *tb1 = nullptr, *tL = nullptr;
+    double2* tacc[3] = {nullptr, nullptr, nullptr};
+    pstd::PassArgs* tdesc = nullptr;
+    int* toff = nullptr;
+    int64_t* tctr = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pstd_status st = PSTD_OK;
+    auto release = [&]() {
+        (void)hipFree(tb0);
+        (void)hipFree(tb1);
+        (void)hipFree(tL);
+        (void)hipFree(tdesc);
+        (void)hipFree(toff);
+        (void)hipFree(tctr);
+        for (int a = 0; a < 3; ++a) (void)hipFree(tacc[a]);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&tb0, s->cells * sizeof(float2))) || (e = hipMalloc(&tb1, s->cells * sizeof(float2))) ||
+        (e = hipMalloc(&tL, s->cells * sizeof(float2))) || (e = hipMalloc(&tdesc, sizeof(pstd::PassArgs))) ||
+        (e = hipMalloc(&toff, 2 * sizeof(int))) || (e = hipMalloc(&tctr, 2 * sizeof(int64_t))) ||
+        (e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+        release();
+        return hip_fail(s, e, "autotune scratch");
+    }
+    for (int a = 0; a < 3 && !e; ++a) e = hipMalloc(&tacc[a], 8 * s->points[a] * sizeof(double2));
+    if (!e) e = hipMemset(tb0, 0, s->cells * sizeof(float2));
+    if (!e) e = hipMemset(tb1, 0, s->cells * sizeof(float2));
+    for (int a = 0; a < 3 && !e; ++a) e = hipMemset(tacc[a], 0, 8 * s->points[a] * sizeof(double2));
+    // a step inside the DFT window: the slower form of every pass
+    int64_t win = s->prob.dft_end > s->prob.dft_begin ? s->prob.dft_begin : 0;
+    if (win >= s->tab_cap) win = 0;
+    const int64_t c0[2] = {win, std::numeric_limits<int64_t>::max()};
+    if (!e) e = hipMemcpy(tctr, c0, sizeof(c0), hipMemcpyHostToDevice);
+    if (e) {
+        release();
+        return hip_fail(s, e, "autotune scratch");
+    }
+    for (int axis = 0; axis < 3 && !st; ++axis) {
+        const bool seg = s->prob.sub_core[axis] > 0;
+        int ids[16];
+        const int nv = std::min(16, pass_variants(local_len(s->prob, axis), seg, ids, 16));
+        if (nv <= 1) continue;
+        float best = 1e30f;
+        int best_id = s->variant[axis];
+        for (int k = 0; k < nv && !st; ++k) {
+            PassArgs a;
+            const int keep = s->variant[axis];
+            s->variant[axis] = ids[k];
+            solver_args(s, axis, a);
+            s->variant[axis] = keep;
+            a.buf[0] = tb0;
+            a.buf[1] = tb1;
+            a.L = tL;
+            a.acc = tacc[axis];
+            a.ctr = tctr;
+            const int off[2] = {0, a.tiles};
+            float ms = 0;
+            if (!e) e = hipMemcpy(tdesc, &a, sizeof(a), hipMemcpyHostToDevice);
+            if (!e) e = hipMemcpy(toff, off, sizeof(off), hipMemcpyHostToDevice);
+            if (!e) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, s->stream);
+            if (!e) e = hipEventRecord(e0, s->stream);
+            for (int r = 0; r < reps && !e; ++r) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, s->stream);
+            if (!e) e = hipEventRecord(e1, s->stream);
+            if (!e) e = hipEventSynchronize(e1);
+            if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e) {
+                st = hip_fail(s, e, "autotune");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_id = ids[k];
+            }
+        }
+        s->variant[axis] = best_id;
+    }
+    release();
+    if (st) return st;
+    solver_drop_graph(s);
+    return upload_descs(s);
+}
+
+}  // namespace pstd
+
+using namespace pstd;
 
 extern "C" {
 
@@ -366,52 +570,7 @@ pstd_status pstd_reduced_step(const pstd_problem* p, double* dtau_out, double* e
 
 pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** out) {
     if (!out) return PSTD_EINVAL;
-    *out = nullptr;
-    pstd_status st = validate(p);
-    if (st) return st;
-    pstd_solver* s = new pstd_solver();
-    s->prob = *p;
-    s->stream = (hipStream_t)hip_stream;
-    (void)hipGetDevice(&s->device);
-    double crit;
-    reduced(p, &s->E0, s->dxb, &s->dtau, &s->eta, &crit);
-    if (s->dtau > crit * (1 + 1e-12) && !p->force_dt) {
-        delete s;
-        return fail(nullptr, PSTD_EUNSTABLE, "dt exceeds the bound of Eq. PSTDstability");
-    }
-    const double th = p->theta, ph = p->phi;
-    s->kh[0] = std::sin(th) * std::cos(ph);
-    s->kh[1] = std::sin(th) * std::sin(ph);
-    s->kh[2] = std::cos(th);
-    s->tau_r = 2 * kPi * p->ramp_periods;
-    s->cells = (int64_t)p->n[0] * p->n[1] * p->n[2];
-    s->points[0] = (int64_t)p->n[1] * p->n[2];
-    s->points[1] = (int64_t)p->n[0] * p->n[2];
-    s->points[2] = (int64_t)p->n[0] * p->n[1];
-    auto cleanup = [&](pstd_status e) {
-        std::string m = s->err;
-        pstd_destroy(s);
-        g_create_error = m;
-        return e;
-    };
-    hipError_t e;
-    if ((e = hipMalloc(&s->cur, s->cells * sizeof(float2))) || (e = hipMalloc(&s->old, s->cells * sizeof(float2))) ||
-        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))))
-        return cleanup(hip_fail(s, e, "hipMalloc state"));
-    for (int a = 0; a < 3; ++a)
-        if ((e = hipMalloc(&s->acc[a], 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMalloc acc"));
-    for (int a = 0; a < 3; ++a) pstd::pass_variants(local_len(*p, a), p->sub_core[a] > 0, &s->variant[a], 1);
-    if ((st = build_tables(s))) return cleanup(st);
-    if ((e = hipMemsetAsync(s->cur, 0, s->cells * sizeof(float2), s->stream)) ||
-        (e = hipMemsetAsync(s->old, 0, s->cells * sizeof(float2), s->stream)) ||
-        (e = hipMemsetAsync(s->v2, 0, s->cells * sizeof(float), s->stream)))
-        return cleanup(hip_fail(s, e, "hipMemset"));
-    for (int a = 0; a < 3; ++a)
-        if ((e = hipMemsetAsync(s->acc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream)))
-            return cleanup(hip_fail(s, e, "hipMemset acc"));
-    if ((e = hipStreamSynchronize(s->stream))) return cleanup(hip_fail(s, e, "sync"));
-    *out = s;
-    return PSTD_OK;
+    return solver_create(p, (hipStream_t)hip_stream, nullptr, out);
 }
 
 pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cells) {
@@ -450,10 +609,16 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
 pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, int64_t n_cells, int64_t step) {
     if (!s || !prev || !cur || step < 0) return PSTD_EINVAL;
     if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
-    HIP_TRY(s, hipMemcpyAsync(s->old, prev, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
-    HIP_TRY(s, hipMemcpyAsync(s->cur, cur, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
-    for (int a = 0; a < 3; ++a)
-        HIP_TRY(s, hipMemsetAsync(s->acc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream));
+    pstd_status st = solver_ensure_tables(s, step + 1);
+    if (st) return st;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    HIP_TRY(s, hipMemcpy(s->buf[(step + 1) & 1], prev, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
+    HIP_TRY(s, hipMemcpy(s->buf[step & 1], cur, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
+    for (int a = 0; a < 3; ++a) HIP_TRY(s, hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)));
+    const int64_t c[2] = {step, std::numeric_limits<int64_t>::max()};
+    HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipDeviceSynchronize());
+    if (s->in_batch) return PSTD_OK;  // the batch rebuilds its launch tables on its next run
     s->step = step;
     s->inc_sum = 0;
     return PSTD_OK;
@@ -461,21 +626,32 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
 
 pstd_status pstd_run(pstd_solver* s, int64_t n_steps) {
     if (!s || n_steps < 0) return PSTD_EINVAL;
-    for (int64_t i = 0; i < n_steps; ++i) {
-        pstd_status st = step_once(s, nullptr);
-        if (st) return st;
+    if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
+    pstd_status st = solver_ensure_tables(s, s->step + n_steps);
+    if (st) return st;
+    int64_t left = n_steps;
+    if (left >= kGraphSteps) {
+        if ((st = build_graph(s))) return st;
+        for (; left >= kGraphSteps; left -= kGraphSteps) HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
     }
+    for (; left > 0; --left)
+        if ((st = launch_step(s, s->stream, nullptr))) return st;
+    solver_account_steps(s, s->step, s->step + n_steps);
+    s->step += n_steps;
     return PSTD_OK;
 }
 
 pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     if (!s || n_steps < 0 || !pass_ms) return PSTD_EINVAL;
+    if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
+    pstd_status st = solver_ensure_tables(s, s->step + n_steps);
+    if (st) return st;
     hipEvent_t ev[6];
     for (int i = 0; i < 6; ++i) HIP_TRY(s, hipEventCreate(&ev[i]));
     double sum[3] = {0, 0, 0};
-    pstd_status st = PSTD_OK;
-    for (int64_t i = 0; i < n_steps && !st; ++i) {
-        st = step_once(s, ev);
+    int64_t done = 0;
+    for (; done < n_steps && !st; ++done) {
+        st = launch_step(s, s->stream, ev);
         if (st) break;
         hipError_t e = hipEventSynchronize(ev[5]);
         if (e) {
@@ -489,84 +665,20 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
         }
     }
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    solver_account_steps(s, s->step, s->step + done);
+    s->step += done;
     for (int a = 0; a < 3; ++a) pass_ms[a] = sum[a];
     return st;
 }
 
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps) {
     if (!s || reps < 1) return PSTD_EINVAL;
-    // time every compiled tile shape of each axis on scratch state (the
-    // solver's own state is left untouched) and keep the fastest
-    float2 *tcur = nullptr, *told = nullptr, *tL = nullptr;
-    double2* tacc[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    pstd_status st = PSTD_OK;
-    auto release = [&]() {
-        (void)hipFree(tcur);
-        (void)hipFree(told);
-        (void)hipFree(tL);
-        for (int a = 0; a < 3; ++a) (void)hipFree(tacc[a]);
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-    };
-    hipError_t e;
-    if ((e = hipMalloc(&tcur, s->cells * sizeof(float2))) || (e = hipMalloc(&told, s->cells * sizeof(float2))) ||
-        (e = hipMalloc(&tL, s->cells * sizeof(float2))) || (e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
-        release();
-        return hip_fail(s, e, "autotune scratch");
-    }
-    for (int a = 0; a < 3 && !e; ++a) e = hipMalloc(&tacc[a], 8 * s->points[a] * sizeof(double2));
-    if (!e) e = hipMemsetAsync(tcur, 0, s->cells * sizeof(float2), s->stream);
-    if (!e) e = hipMemsetAsync(told, 0, s->cells * sizeof(float2), s->stream);
-    for (int a = 0; a < 3 && !e; ++a) e = hipMemsetAsync(tacc[a], 0, 8 * s->points[a] * sizeof(double2), s->stream);
-    if (e) {
-        release();
-        return hip_fail(s, e, "autotune scratch");
-    }
-    pstd::PassArgs args{};
-    common_args(s, args);
-    args.psi = tcur;
-    args.psi_old = told;
-    args.L = tL;
-    args.dft_on = 1;
-    args.w = make_double2(1.0, 0.0);
-    args.sigma = make_float2(0.f, 0.f);
-    for (int axis = 0; axis < 3 && !st; ++axis) {
-        const bool seg = s->prob.sub_core[axis] > 0;
-        int ids[16];
-        const int nv = std::min(16, pstd::pass_variants(local_len(s->prob, axis), seg, ids, 16));
-        if (nv <= 1) continue;
-        axis_args(s, axis, args);
-        args.acc = tacc[axis];
-        float best = 1e30f;
-        for (int k = 0; k < nv && !st; ++k) {
-            if ((e = pstd::launch_variant(ids[k], seg, axis, args, s->stream)) ||
-                (e = hipEventRecord(e0, s->stream))) {
-                st = hip_fail(s, e, "autotune launch");
-                break;
-            }
-            for (int r = 0; r < reps && !e; ++r) e = pstd::launch_variant(ids[k], seg, axis, args, s->stream);
-            float ms = 0;
-            if (!e) e = hipEventRecord(e1, s->stream);
-            if (!e) e = hipEventSynchronize(e1);
-            if (!e) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e) {
-                st = hip_fail(s, e, "autotune timing");
-                break;
-            }
-            if (ms < best) {
-                best = ms;
-                s->variant[axis] = ids[k];
-            }
-        }
-    }
-    release();
-    return st;
+    return solver_autotune(s, reps);
 }
 
 pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host) {
     if (!s || !info_host || axis < 0 || axis > 2) return PSTD_EINVAL;
-    const pstd::PassShape sh = pstd::variant_shape(s->variant[axis]);
+    const PassShape sh = variant_shape(s->variant[axis]);
     info_host[0] = sh.N;
     info_host[1] = sh.N1;
     info_host[2] = sh.N2;
@@ -583,8 +695,8 @@ pstd_status pstd_step_index(const pstd_solver* s, int64_t* out) {
 pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n_cells) {
     if (!s || !psi_dev || (level != 0 && level != 1)) return PSTD_EINVAL;
     if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
-    HIP_TRY(s, hipMemcpyAsync(psi_dev, level == 0 ? s->cur : s->old, n_cells * sizeof(float2),
-                              hipMemcpyDeviceToDevice, s->stream));
+    const float2* src = s->buf[(s->step + (level == 0 ? 0 : 1)) & 1];
+    HIP_TRY(s, hipMemcpyAsync(psi_dev, src, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
     return PSTD_OK;
 }
 
@@ -599,31 +711,28 @@ pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n)
     int64_t need;
     pstd_surface_size(s, &need);
     if (n != need) return fail(s, PSTD_EINVAL, "output size must equal pstd_surface_size");
-    const double inc = incident_phasor(s);
-    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
-    hipError_t e = pstd::finalize_phasors(s->acc, s->points, 1.0 / inc, (double2*)out_dev, s->stream);
+    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    hipError_t e = finalize_phasors(s->acc, s->points, 1.0 / s->inc_sum, (double2*)out_dev, s->stream);
     if (e) return hip_fail(s, e, "finalize_phasors");
     return PSTD_OK;
 }
 
 pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
     if (!s || !obs_dev || !out_dev || n_obs < 0) return PSTD_EINVAL;
-    const double inc = incident_phasor(s);
-    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     std::string msg;
-    hipError_t e = pstd::project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / inc,
-                                        (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
+    hipError_t e = project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
+                                  (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
     if (e) return msg.empty() ? hip_fail(s, e, "project") : fail(s, PSTD_EINVAL, msg);
     return PSTD_OK;
 }
 
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
     if (!s || !dir_dev || !out_dev || n_dir < 0) return PSTD_EINVAL;
-    const double inc = incident_phasor(s);
-    if (!(inc > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     std::string msg;
-    hipError_t e = pstd::far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / inc,
-                                   (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
+    hipError_t e = far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
+                             (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
     if (e) return msg.empty() ? hip_fail(s, e, "far_field") : fail(s, PSTD_EINVAL, msg);
     return PSTD_OK;
 }
@@ -632,13 +741,21 @@ pstd_status pstd_destroy(pstd_solver* s) {
     if (!s) return PSTD_OK;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
-    (void)hipFree(s->cur);
-    (void)hipFree(s->old);
+    solver_drop_graph(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    (void)hipFree(s->buf[0]);
+    (void)hipFree(s->buf[1]);
     (void)hipFree(s->L);
     (void)hipFree(s->v2);
     (void)hipFree(s->tables);
+    (void)hipFree(s->desc);
+    (void)hipFree(s->off);
+    (void)hipFree(s->sigma_tab);
+    (void)hipFree(s->w_tab);
+    (void)hipFree(s->dft_tab);
+    if (s->owns_ctr) (void)hipFree(s->ctr);
     for (int a = 0; a < 3; ++a) (void)hipFree(s->acc[a]);
-    pstd::project_free(s->proj);
+    project_free(s->proj);
     delete s;
     return PSTD_OK;
 }

@@ -19,23 +19,29 @@ struct AxisTables {
     const float2* dhi;   // spectral-derivative row for the high plane
 };
 
+// Everything a pass launch needs for one solver instance and one axis.  The
+// structs live in device memory and stay fixed while the solver runs; the
+// per-step quantities are read on the device from the step counter:
+// psi^n = buf[n & 1], psi^{n-1} = buf[(n + 1) & 1], and the tables below.
 struct PassArgs {
-    const float2* psi;   // psi^n
-    float2* L;           // kinetic accumulator (scaled by 2 eta dtau)
-    float2* psi_old;     // psi^{n-1} in, psi^{n+1} out (z pass)
-    const float* v2;     // 2 dtau V / E0
+    float2* buf[2];            // psi ping-pong
+    float2* L;                 // kinetic accumulator (scaled by 2 eta dtau)
+    const float* v2;           // 2 dtau V / E0
     int nx, ny, nz;
     AxisTables ax[3];
-    float2 sigma;        // 2 dtau R(tau_n) exp(-i tau_n) [* eta]
-    int dft_on;
-    double2 w;           // exp(i tau_n)
-    int plane_lo, plane_hi;  // plane indices along this pass's axis
-    double2* acc;        // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]
-    int64_t points;      // points of one plane of this axis
+    const int64_t* ctr;        // device counters: ctr[0] = step n, ctr[1] = end (n >= end: no work)
+    const float2* sigma_tab;   // per step: 2 dtau R(tau_n) exp(-i tau_n) [* eta]
+    const double2* w_tab;      // per step: exp(i tau_n)
+    const int* dft_tab;        // per step: 1 inside the surface-DFT window
+    int plane_lo, plane_hi;    // plane indices along this pass's axis (local in segmented mode)
+    double2* acc;              // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]
+    int64_t points;            // points of one plane of this axis
     // overlapping-subdomain mode along this pass's axis (Section 2.6)
     int seg_core, seg_halo, nseg;
-    const float* wloc;   // local halo weights, length core + 2 halo
-    int seg_plane[2];    // segment holding the low / high plane (plane_lo/hi are local then)
+    const float* wloc;         // local halo weights, length core + 2 halo
+    int seg_plane[2];          // segment holding the low / high plane
+    int tiles;                 // workgroups of this instance in this pass
+    int ntx;                   // x tiles of the y and z passes
 };
 
 // FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
@@ -47,7 +53,14 @@ struct PassShape {
 // subdomain instance).  Writes up to cap variant ids, returns the count.
 int pass_variants(int N, bool segmented, int* out, int cap);
 PassShape variant_shape(int v);
-// Launch variant v for the pass along `axis` (0, 1, 2)
-hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs& args, hipStream_t stream);
+// Workgroups of variant v for one instance's pass along `axis`; also sets
+// args.tiles and args.ntx.
+int variant_tiles(int v, int axis, PassArgs& args);
+// Launch variant v over a group of instances: descs[0..ninst) in device
+// memory, off[0..ninst] (device) = prefix sums of their tiles.
+hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
+                          int total_tiles, hipStream_t stream);
+// advance the step counters of count instances, ctr[2i] = step, ctr[2i+1] = end
+hipError_t launch_advance(int64_t* ctr, int count, hipStream_t stream);
 
 }  // namespace pstd

@@ -39,7 +39,8 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 }
 
 template <int N, int N1, int N2, int P, int AXIS, bool SEG>
-__global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs a) {
+__global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const PassArgs* __restrict__ descs,
+                                                                       const int* __restrict__ off, int ninst) {
     constexpr int NT = P * (N1 > N2 ? N1 : N2);
     constexpr int ROW = N2 + 1;                 // padded exchange row
     // odd pencil stride (float2); also holds the four DFT partials per thread
@@ -49,12 +50,23 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     __shared__ float s_kk[N];
     __shared__ float2 s_dl[N], s_dh[N];
 
+    // instance of this workgroup (uniform), its tile, its step
+    int inst = 0;
+    for (int i = 1; i < ninst; ++i)
+        if ((int)blockIdx.x >= off[i]) inst = i;
+    const PassArgs& a = descs[inst];
+    const int tile = (int)blockIdx.x - off[inst];
+    const int64_t nstep = a.ctr[0];
+    if (nstep >= a.ctr[1]) return;  // whole workgroup, before any barrier
+    const float2* __restrict__ psi = a.buf[nstep & 1];
+    float2* __restrict__ psi_old = a.buf[(nstep + 1) & 1];
+    const bool surf = a.dft_tab[nstep] != 0;
+
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
     const int pA = AXIS == 0 ? t / N2 : t % P;
     const int n2 = AXIS == 0 ? t % N2 : t / P;
     const AxisTables& T = a.ax[AXIS];
-    const bool surf = a.dft_on != 0;
 
     // tables to LDS (issued before the field loads)
     for (int i = t; i < N; i += NT) {
@@ -72,6 +84,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     const int H = SEG ? a.seg_halo : 0;
     const int nseg = SEG ? a.nseg : 1;
     const int Ng = AXIS == 0 ? a.nx : AXIS == 1 ? a.ny : a.nz;
+    const int tx = AXIS == 0 ? 0 : tile % a.ntx;      // x tile (y, z passes)
+    const int tq = AXIS == 0 ? 0 : tile / a.ntx;      // (other, segment) of the y, z passes
 
     // pencil geometry: element e of pencil pA lives at base + e * estride
     int64_t base = 0, estride = 1;
@@ -79,23 +93,23 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     int seg = 0;
     int px = 0, py = 0;  // (x, y) of the pencil for the z-pass update
     if constexpr (AXIS == 0) {
-        const int64_t q = (int64_t)blockIdx.x * P + pA;
+        const int64_t q = (int64_t)tile * P + pA;
         const int64_t row = q / nseg;
         seg = (int)(q % nseg);
         valid = activeA && q < (int64_t)a.ny * a.nz * nseg;
         base = row * a.nx + (seg * C - H);
         estride = 1;
     } else if constexpr (AXIS == 1) {
-        const int x = blockIdx.x * P + pA;
-        const int z = blockIdx.y / nseg;
-        seg = blockIdx.y % nseg;
+        const int x = tx * P + pA;
+        const int z = tq / nseg;
+        seg = tq % nseg;
         valid = activeA && x < a.nx;
         estride = a.nx;
         base = x + (int64_t)a.nx * a.ny * z + (int64_t)(seg * C - H) * estride;
     } else {
-        px = blockIdx.x * P + pA;
-        py = blockIdx.y / nseg;
-        seg = blockIdx.y % nseg;
+        px = tx * P + pA;
+        py = tq / nseg;
+        seg = tq % nseg;
         valid = activeA && px < a.nx;
         estride = (int64_t)a.nx * a.ny;
         base = px + (int64_t)a.nx * py + (int64_t)(seg * C - H) * estride;
@@ -108,7 +122,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         constexpr int n1 = decltype(i)::value;
         const int e = n2 + N2 * n1;
         const bool in = valid && (!SEG || (g0 + e >= 0 && g0 + e < Ng));
-        float2 x = in ? a.psi[base + (int64_t)e * estride] : make_float2(0.f, 0.f);
+        float2 x = in ? psi[base + (int64_t)e * estride] : make_float2(0.f, 0.f);
         if constexpr (AXIS == 2) keep[n1] = x;
         if constexpr (SEG) x = cscale(x, a.wloc[e]);
         v[n1] = x;
@@ -117,8 +131,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     // (planes lie in a core, where the halo weight is 1)
     float2 plo = make_float2(0.f, 0.f), phi = plo;
     if (surf && valid) {
-        if (n2 == a.plane_lo % N2 && seg == a.seg_plane[0]) plo = a.psi[base + (int64_t)a.plane_lo * estride];
-        if (n2 == a.plane_hi % N2 && seg == a.seg_plane[1]) phi = a.psi[base + (int64_t)a.plane_hi * estride];
+        if (n2 == a.plane_lo % N2 && seg == a.seg_plane[0]) plo = psi[base + (int64_t)a.plane_lo * estride];
+        if (n2 == a.plane_hi % N2 && seg == a.seg_plane[1]) phi = psi[base + (int64_t)a.plane_hi * estride];
     }
     __syncthreads();
 
@@ -197,6 +211,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
             const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
             const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
             const float gxy = a.ax[0].gam[px] * a.ax[1].gam[py];
+            const float2 sigma = a.sigma_tab[nstep];
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
@@ -204,14 +219,14 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     const int z = g0 + e;
                     const int64_t ad = base + (int64_t)e * estride;
                     const float2 Lt = cadd(a.L[ad], v[n1]);
-                    const float2 po = a.psi_old[ad];
+                    const float2 po = psi_old[ad];
                     const float vv = a.v2[ad];
                     const float2 s = cadd(cmul(SA, T.zt[z]), cmul(SB, T.dz[z]));
                     float2 q = cadd(Lt, cscale(keep[n1], vv));
-                    q = cadd(q, cmul(a.sigma, s));
+                    q = cadd(q, cmul(sigma, s));
                     const float g = gxy * T.gam[z];
                     // psi^{n+1} = Gamma (psi^{n-1} - i q)
-                    a.psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                    psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
                 }
             });
         }
@@ -234,19 +249,19 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
             const int side = q & 1;
             int64_t pt = -1;
             if constexpr (AXIS == 0) {
-                const int64_t qq = (int64_t)blockIdx.x * P + p;
+                const int64_t qq = (int64_t)tile * P + p;
                 if (qq < (int64_t)a.ny * a.nz * nseg && (int)(qq % nseg) == a.seg_plane[side]) pt = qq / nseg;
             } else {
-                const int x = blockIdx.x * P + p;
-                if (x < a.nx && (int)(blockIdx.y % nseg) == a.seg_plane[side])
-                    pt = x + (int64_t)a.nx * (blockIdx.y / nseg);
+                const int x = tx * P + p;
+                if (x < a.nx && tq % nseg == a.seg_plane[side]) pt = x + (int64_t)a.nx * (tq / nseg);
             }
             if (pt >= 0) {
                 float2 s = make_float2(0.f, 0.f);
                 for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
                 const double re = (double)s.x, im = (double)s.y;
-                const double zr = a.w.x * re - a.w.y * im;
-                const double zi = a.w.x * im + a.w.y * re;
+                const double2 w = a.w_tab[nstep];
+                const double zr = w.x * re - w.y * im;
+                const double zi = w.x * im + w.y * re;
                 const int field = (q >> 1) * 2;
                 double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
                 double2* Cc = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
@@ -296,23 +311,20 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     X(256, 16, 16, 16, 0)       \
     X(288, 16, 18, 16, 0)
 
-using LaunchFn = hipError_t (*)(int axis, const PassArgs& args, hipStream_t stream);
+using LaunchFn = hipError_t (*)(int axis, const PassArgs* descs, const int* off, int ninst, int tiles,
+                                hipStream_t stream);
 
 template <int N, int N1, int N2, int P, bool SEG>
-static hipError_t launch_shape(int axis, const PassArgs& args, hipStream_t stream) {
+static hipError_t launch_shape(int axis, const PassArgs* descs, const int* off, int ninst, int tiles,
+                               hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
-    const int nseg = SEG ? args.nseg : 1;
-    if (axis == 0) {
-        const int64_t pencils = (int64_t)args.ny * args.nz * nseg;
-        dim3 grid((unsigned)((pencils + P - 1) / P));
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), grid, dim3(threads), 0, stream, args);
-    } else if (axis == 1) {
-        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)(args.nz * nseg));
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), grid, dim3(threads), 0, stream, args);
-    } else {
-        dim3 grid((unsigned)((args.nx + P - 1) / P), (unsigned)(args.ny * nseg));
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), grid, dim3(threads), 0, stream, args);
-    }
+    if (tiles <= 0) return hipSuccess;
+    if (axis == 0)
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
+    else if (axis == 1)
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
+    else
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
     return hipGetLastError();
 }
 
@@ -353,11 +365,39 @@ int pass_variants(int N, bool segmented, int* out, int cap) {
 
 PassShape variant_shape(int v) { return kVariants[v].shape; }
 
-hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs& args, hipStream_t stream) {
+int variant_tiles(int v, int axis, PassArgs& a) {
+    const int P = kVariants[v].shape.P;
+    const int nseg = a.nseg > 0 ? a.nseg : 1;
+    if (axis == 0) {
+        a.ntx = 1;
+        a.tiles = (int)(((int64_t)a.ny * a.nz * nseg + P - 1) / P);
+    } else {
+        a.ntx = (a.nx + P - 1) / P;
+        a.tiles = a.ntx * (axis == 1 ? a.nz : a.ny) * nseg;
+    }
+    return a.tiles;
+}
+
+hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
+                          int total_tiles, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
-    return f(axis, args, stream);
+    return f(axis, descs, off, ninst, total_tiles, stream);
+}
+
+// one lane per instance: vector loads and stores of the counters
+__global__ void advance_kernel(int64_t* __restrict__ ctr, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const int64_t n = ctr[2 * i], end = ctr[2 * i + 1];
+        if (n < end) ctr[2 * i] = n + 1;
+    }
+}
+
+hipError_t launch_advance(int64_t* ctr, int count, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_kernel, dim3((count + 63) / 64), dim3(64), 0, stream, ctr, count);
+    return hipGetLastError();
 }
 
 }  // namespace pstd

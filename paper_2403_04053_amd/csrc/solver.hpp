@@ -1,0 +1,66 @@
+// Solver state shared by the single-solver and batch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/pstd.h"
+#include "internal.hpp"
+#include "project.hpp"
+
+struct pstd_solver {
+    pstd_problem prob{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double E0 = 0, dtau = 0, eta = 0, tau_r = 0;
+    double dxb[3] = {0, 0, 0};
+    double kh[3] = {0, 0, 0};
+    int64_t cells = 0;
+    int64_t step = 0;      // host mirror of the device step counter
+    double inc_sum = 0;    // incident phasor at the origin over the window steps run so far
+    float2* buf[2] = {nullptr, nullptr};
+    float2* L = nullptr;
+    float* v2 = nullptr;
+    void* tables = nullptr;
+    pstd::AxisTables ax[3]{};
+    const float* wloc[3] = {nullptr, nullptr, nullptr};
+    double2* acc[3] = {nullptr, nullptr, nullptr};
+    int64_t points[3] = {0, 0, 0};
+    int variant[3] = {0, 0, 0};   // tile shape of each axis pass
+    // per-step tables, steps [0, tab_cap)
+    float2* sigma_tab = nullptr;
+    double2* w_tab = nullptr;
+    int* dft_tab = nullptr;
+    int64_t tab_cap = 0;
+    int tab_gen = 0;       // bumped whenever the tables move
+    // device counters (step, end); owned unless the solver belongs to a batch
+    int64_t* ctr = nullptr;
+    bool owns_ctr = true;
+    // pass descriptors in device memory: desc[3], then off[3][2]
+    pstd::PassArgs* desc = nullptr;
+    int* off = nullptr;
+    // graph of kGraphSteps steps, replayed on `stream`
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    pstd::ProjectState* proj = nullptr;
+    std::string err;
+    bool in_batch = false;
+};
+
+namespace pstd {
+
+pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ext_ctr, pstd_solver** out);
+pstd_status solver_fail(pstd_solver* s, pstd_status st, const std::string& msg);
+pstd_status solver_hip_fail(pstd_solver* s, hipError_t e, const char* what);
+// make the per-step tables cover steps [0, n_end); refreshes the descriptors
+pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end);
+// fill the host copy of the descriptor of one axis
+void solver_args(const pstd_solver* s, int axis, PassArgs& a);
+// incident phasor bookkeeping for steps [from, to)
+void solver_account_steps(pstd_solver* s, int64_t from, int64_t to);
+pstd_status solver_autotune(pstd_solver* s, int32_t reps);
+void solver_drop_graph(pstd_solver* s);
+
+}  // namespace pstd
