@@ -138,6 +138,16 @@ pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
  * {N, N1, N2, pencils per workgroup}.  Host only. */
 pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host);
 
+/* Use the compiled tile shape of axis `axis` with stage-A factor n1 and
+ * `pencils` pencils per workgroup.  EUNSUPPORTED if there is none.
+ * Synchronises. */
+pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils);
+
+/* Compiled tile shapes for pass length n (segmented != 0: subdomain mode):
+ * writes up to cap triples {N1, N2, pencils} to shapes_host[3*cap] and the
+ * total number to *count_out.  Host only. */
+pstd_status pstd_tile_variants(int32_t n, int32_t segmented, int32_t* shapes_host, int32_t cap, int32_t* count_out);
+
 /* Number of steps taken (the current level is psi^step). */
 pstd_status pstd_step_index(const pstd_solver* s, int64_t* step_out_host);
 

@@ -15,7 +15,8 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_batch_create",
+    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
     "EXPORTED",
@@ -117,6 +118,9 @@ _SIGS = {
     "pstd_destroy": [_vp],
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "pstd_set_tile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "pstd_tile_variants": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_int32)],
     "pstd_batch_create": [ctypes.c_void_p, ctypes.c_int32, _vp, ctypes.POINTER(_vp)],
     "pstd_batch_size": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "pstd_batch_solver": [_vp, ctypes.c_int32, ctypes.POINTER(_vp)],
@@ -250,6 +254,17 @@ def pstd_tile_info(solver, axis):
     return tuple(out)
 
 
+def pstd_set_tile(solver, axis, n1, pencils):
+    _check(lib.pstd_set_tile(solver, int(axis), int(n1), int(pencils)), solver)
+
+
+def pstd_tile_variants(n, segmented=False):
+    cnt = ctypes.c_int32()
+    buf = (ctypes.c_int32 * 48)()
+    _check(lib.pstd_tile_variants(int(n), int(bool(segmented)), buf, 16, ctypes.byref(cnt)))
+    return [tuple(buf[3 * k:3 * k + 3]) for k in range(min(cnt.value, 16))]
+
+
 def pstd_destroy(solver):
     _check(lib.pstd_destroy(solver))
 
@@ -343,6 +358,9 @@ class Solver:
     def autotune(self, reps=5):
         pstd_autotune(self.handle, reps)
         return [pstd_tile_info(self.handle, a) for a in range(3)]
+
+    def set_tile(self, axis, n1, pencils):
+        pstd_set_tile(self.handle, axis, n1, pencils)
 
     def tiles(self):
         return [pstd_tile_info(self.handle, a) for a in range(3)]

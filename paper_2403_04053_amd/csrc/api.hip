@@ -618,7 +618,6 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
     const int64_t c[2] = {step, std::numeric_limits<int64_t>::max()};
     HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
     HIP_TRY(s, hipDeviceSynchronize());
-    if (s->in_batch) return PSTD_OK;  // the batch rebuilds its launch tables on its next run
     s->step = step;
     s->inc_sum = 0;
     return PSTD_OK;
@@ -683,6 +682,37 @@ pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_hos
     info_host[1] = sh.N1;
     info_host[2] = sh.N2;
     info_host[3] = sh.P;
+    return PSTD_OK;
+}
+
+pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils) {
+    if (!s || axis < 0 || axis > 2) return PSTD_EINVAL;
+    const bool seg = s->prob.sub_core[axis] > 0;
+    int ids[16];
+    const int nv = std::min(16, pass_variants(local_len(s->prob, axis), seg, ids, 16));
+    for (int k = 0; k < nv; ++k) {
+        const PassShape sh = variant_shape(ids[k]);
+        if (sh.N1 == n1 && sh.P == pencils) {
+            HIP_TRY(s, hipStreamSynchronize(s->stream));
+            s->variant[axis] = ids[k];
+            solver_drop_graph(s);
+            return upload_descs(s);
+        }
+    }
+    return fail(s, PSTD_EUNSUPPORTED, "no compiled tile shape with that factor and pencil count");
+}
+
+pstd_status pstd_tile_variants(int32_t n, int32_t segmented, int32_t* shapes_host, int32_t cap, int32_t* count_out) {
+    if (!count_out || cap < 0 || (cap > 0 && !shapes_host)) return PSTD_EINVAL;
+    int ids[16];
+    const int nv = std::min(16, pass_variants(n, segmented != 0, ids, 16));
+    for (int k = 0; k < nv && k < cap; ++k) {
+        const PassShape sh = variant_shape(ids[k]);
+        shapes_host[3 * k] = sh.N1;
+        shapes_host[3 * k + 1] = sh.N2;
+        shapes_host[3 * k + 2] = sh.P;
+    }
+    *count_out = nv;
     return PSTD_OK;
 }
 

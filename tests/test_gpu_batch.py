@@ -86,6 +86,41 @@ def test_batch_autotune_keeps_results(P):
         assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(y)
 
 
+def _sampled_check(prob, V, got, prev, cur, step, seed):
+    m = opstd.build(prob, V)
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = prob.n
+    pts = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))) for _ in range(24)]
+    ref = opstd.step_at(m, prev.astype(np.complex128), cur.astype(np.complex128), step, pts)
+    g = np.array([got[k, j, i_] for (i_, j, k) in pts])
+    return np.abs(g - ref).max() / np.abs(cur).max()
+
+
+@pytest.mark.parametrize("mode", ["single", "single_tuned", "batch_of_one"])
+def test_uneven_instance_alone(P, mode):
+    prob, V = synth.cfg4_instances(count=1)[0]
+    Vf = V.astype(np.float32).astype(np.float64)
+    prev = synth.random_state(prob.n, 100).astype(np.complex64)
+    cur = synth.random_state(prob.n, 200).astype(np.complex64)
+    if mode == "batch_of_one":
+        b = P.Batch([prob])
+        b.set_potential(0, Vf)
+        b.instance(0).set_state(prev, cur, 11)
+        b.run([1])
+        got = b.instance(0).psi(0).cpu().numpy()
+    else:
+        s = P.Solver(prob)
+        s.set_potential(Vf)
+        if mode == "single_tuned":
+            print("tiles", s.autotune(reps=2))
+        s.set_state(prev, cur, 11)
+        s.run(1)
+        got = s.psi(0).cpu().numpy()
+    err = _sampled_check(prob, Vf, got, prev, cur, 11, 5)
+    print(mode, prob.n, "sampled err", err)
+    assert err < 1e-5
+
+
 def test_uneven_batch_full_size_sampled(P):
     """The uneven-grid workload at its real size (64 instances, grid lengths
     96..192): three instances start from random states; one batched step is
