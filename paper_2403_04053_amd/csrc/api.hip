@@ -251,19 +251,28 @@ pstd_status upload_descs(pstd_solver* s) {
     return PSTD_OK;
 }
 
-// launch one step (three passes and the counter advance) on `stream`
-pstd_status launch_step(pstd_solver* s, hipStream_t stream, hipEvent_t* ev) {
+// launch the three passes of step ctr[0] + koff on `stream`
+pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent_t* ev) {
     for (int axis = 0; axis < 3; ++axis) {
         pstd::PassArgs a;
         pstd::solver_args(s, axis, a);
         const bool seg = s->prob.sub_core[axis] > 0;
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], stream));
         hipError_t e = pstd::launch_variant(s->variant[axis], seg, axis, s->desc + axis, s->off + 2 * axis, 1,
-                                            a.tiles, stream);
+                                            a.tiles, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
     }
-    hipError_t e = pstd::launch_advance(s->ctr, 1, stream);
+    return PSTD_OK;
+}
+
+// `count` consecutive steps, then one counter advance
+pstd_status launch_steps(pstd_solver* s, hipStream_t stream, int count, hipEvent_t* ev) {
+    for (int k = 0; k < count; ++k) {
+        pstd_status st = launch_passes(s, stream, k, ev);
+        if (st) return st;
+    }
+    hipError_t e = pstd::launch_advance(s->ctr, 1, count, stream);
     if (e != hipSuccess) return hip_fail(s, e, "advance launch");
     return PSTD_OK;
 }
@@ -272,8 +281,7 @@ pstd_status build_graph(pstd_solver* s) {
     if (s->graph) return PSTD_OK;
     if (!s->cap_stream) HIP_TRY(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    pstd_status st = PSTD_OK;
-    for (int i = 0; i < kGraphSteps && !st; ++i) st = launch_step(s, s->cap_stream, nullptr);
+    pstd_status st = launch_steps(s, s->cap_stream, kGraphSteps, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
     if (st) {
@@ -491,9 +499,10 @@ pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
             float ms = 0;
             if (!e) e = hipMemcpy(tdesc, &a, sizeof(a), hipMemcpyHostToDevice);
             if (!e) e = hipMemcpy(toff, off, sizeof(off), hipMemcpyHostToDevice);
-            if (!e) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, s->stream);
+            if (!e) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, 0, s->stream);
             if (!e) e = hipEventRecord(e0, s->stream);
-            for (int r = 0; r < reps && !e; ++r) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, s->stream);
+            for (int r = 0; r < reps && !e; ++r)
+                e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, 0, s->stream);
             if (!e) e = hipEventRecord(e1, s->stream);
             if (!e) e = hipEventSynchronize(e1);
             if (!e) e = hipEventElapsedTime(&ms, e0, e1);
@@ -633,8 +642,7 @@ pstd_status pstd_run(pstd_solver* s, int64_t n_steps) {
         if ((st = build_graph(s))) return st;
         for (; left >= kGraphSteps; left -= kGraphSteps) HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
     }
-    for (; left > 0; --left)
-        if ((st = launch_step(s, s->stream, nullptr))) return st;
+    if (left > 0 && (st = launch_steps(s, s->stream, (int)left, nullptr))) return st;
     solver_account_steps(s, s->step, s->step + n_steps);
     s->step += n_steps;
     return PSTD_OK;
@@ -650,7 +658,7 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     double sum[3] = {0, 0, 0};
     int64_t done = 0;
     for (; done < n_steps && !st; ++done) {
-        st = launch_step(s, s->stream, ev);
+        st = launch_steps(s, s->stream, 1, ev);
         if (st) break;
         hipError_t e = hipEventSynchronize(ev[5]);
         if (e) {

@@ -116,14 +116,16 @@ pstd_status build_groups(pstd_batch* b) {
     return PSTD_OK;
 }
 
-pstd_status launch_batch_step(pstd_batch* b, hipStream_t stream) {
-    for (int axis = 0; axis < 3; ++axis)
-        for (const Group& g : b->groups[axis]) {
-            hipError_t e = pstd::launch_variant(g.variant, g.seg, axis, g.d_desc, g.d_off, (int)g.members.size(),
-                                                g.tiles, stream);
-            if (e != hipSuccess) return bhip(b, e, "batch pass launch");
-        }
-    hipError_t e = pstd::launch_advance(b->ctr, (int)b->inst.size(), stream);
+// `count` consecutive steps of every instance, then one counter advance
+pstd_status launch_batch_steps(pstd_batch* b, hipStream_t stream, int count) {
+    for (int k = 0; k < count; ++k)
+        for (int axis = 0; axis < 3; ++axis)
+            for (const Group& g : b->groups[axis]) {
+                hipError_t e = pstd::launch_variant(g.variant, g.seg, axis, g.d_desc, g.d_off, (int)g.members.size(),
+                                                    g.tiles, k, stream);
+                if (e != hipSuccess) return bhip(b, e, "batch pass launch");
+            }
+    hipError_t e = pstd::launch_advance(b->ctr, (int)b->inst.size(), count, stream);
     if (e != hipSuccess) return bhip(b, e, "batch advance");
     return PSTD_OK;
 }
@@ -132,8 +134,7 @@ pstd_status build_batch_graph(pstd_batch* b) {
     if (b->graph) return PSTD_OK;
     if (!b->cap_stream) BHIP_TRY(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     BHIP_TRY(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    pstd_status st = PSTD_OK;
-    for (int i = 0; i < kBatchGraphSteps && !st; ++i) st = launch_batch_step(b, b->cap_stream);
+    pstd_status st = launch_batch_steps(b, b->cap_stream, kBatchGraphSteps);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (st) {
@@ -257,8 +258,8 @@ pstd_status pstd_batch_run(pstd_batch* b, const int64_t* n_steps_host) {
         if (st) return st;
         for (; left >= kBatchGraphSteps; left -= kBatchGraphSteps) BHIP_TRY(b, hipGraphLaunch(b->graph, b->stream));
     }
-    for (; left > 0; --left) {
-        pstd_status st = launch_batch_step(b, b->stream);
+    if (left > 0) {
+        pstd_status st = launch_batch_steps(b, b->stream, (int)left);
         if (st) return st;
     }
     for (int i = 0; i < count; ++i) {

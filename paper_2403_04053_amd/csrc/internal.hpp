@@ -57,10 +57,12 @@ PassShape variant_shape(int v);
 // args.tiles and args.ntx.
 int variant_tiles(int v, int axis, PassArgs& args);
 // Launch variant v over a group of instances: descs[0..ninst) in device
-// memory, off[0..ninst] (device) = prefix sums of their tiles.
+// memory, off[0..ninst] (device) = prefix sums of their tiles.  The launch
+// works on step ctr[0] + koff of each instance.
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, hipStream_t stream);
-// advance the step counters of count instances, ctr[2i] = step, ctr[2i+1] = end
-hipError_t launch_advance(int64_t* ctr, int count, hipStream_t stream);
+                          int total_tiles, int koff, hipStream_t stream);
+// advance the step counters of count instances by `by` steps, never past
+// their end (ctr[2i] = step, ctr[2i+1] = end)
+hipError_t launch_advance(int64_t* ctr, int count, int by, hipStream_t stream);
 
 }  // namespace pstd

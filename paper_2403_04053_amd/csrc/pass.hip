@@ -40,7 +40,8 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 
 template <int N, int N1, int N2, int P, int AXIS, bool SEG>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const PassArgs* __restrict__ descs,
-                                                                       const int* __restrict__ off, int ninst) {
+                                                                       const int* __restrict__ off, int ninst,
+                                                                       int koff) {
     constexpr int NT = P * (N1 > N2 ? N1 : N2);
     constexpr int ROW = N2 + 1;                 // padded exchange row
     // odd pencil stride (float2); also holds the four DFT partials per thread
@@ -50,42 +51,58 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
     __shared__ float s_kk[N];
     __shared__ float2 s_dl[N], s_dh[N];
 
-    // instance of this workgroup (uniform), its tile, its step
+    // instance of this workgroup (uniform), its tile, its step: the base
+    // counter plus this launch's offset in its group of steps
     int inst = 0;
     for (int i = 1; i < ninst; ++i)
         if ((int)blockIdx.x >= off[i]) inst = i;
-    const PassArgs& a = descs[inst];
+    const PassArgs* __restrict__ ap = descs + inst;
     const int tile = (int)blockIdx.x - off[inst];
-    const int64_t nstep = a.ctr[0];
-    if (nstep >= a.ctr[1]) return;  // whole workgroup, before any barrier
-    const float2* __restrict__ psi = a.buf[nstep & 1];
-    float2* __restrict__ psi_old = a.buf[(nstep + 1) & 1];
-    const bool surf = a.dft_tab[nstep] != 0;
+    const int64_t nstep = ap->ctr[0] + koff;
+    if (nstep >= ap->ctr[1]) return;  // whole workgroup, before any barrier
+
+    // every field used below, read once (uniform values)
+    const int nx = ap->nx, ny = ap->ny, nz = ap->nz;
+    const float2* __restrict__ psi = ap->buf[nstep & 1];
+    float2* __restrict__ psi_old = ap->buf[(nstep + 1) & 1];
+    float2* __restrict__ Lbuf = ap->L;
+    const float* __restrict__ v2 = ap->v2;
+    const bool surf = ap->dft_tab[nstep] != 0;
+    const float* __restrict__ t_kk = ap->ax[AXIS].kk;
+    const float2* __restrict__ t_tw = ap->ax[AXIS].tw;
+    const float* __restrict__ t_gam = ap->ax[AXIS].gam;
+    const float2* __restrict__ t_zt = ap->ax[AXIS].zt;
+    const float2* __restrict__ t_dz = ap->ax[AXIS].dz;
+    const float2* __restrict__ t_dlo = ap->ax[AXIS].dlo;
+    const float2* __restrict__ t_dhi = ap->ax[AXIS].dhi;
+    const int plane_lo = ap->plane_lo, plane_hi = ap->plane_hi;
+    const int seg_plane0 = ap->seg_plane[0], seg_plane1 = ap->seg_plane[1];
+    const int ntx = ap->ntx;
+    // segmented pencils: element e of segment `seg` is global index
+    // seg * C - H + e, weighted by wloc[e]; plain pencils: C = N, H = 0
+    const int C = SEG ? ap->seg_core : N;
+    const int H = SEG ? ap->seg_halo : 0;
+    const int nseg = SEG ? ap->nseg : 1;
+    const float* __restrict__ wloc = ap->wloc;
 
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
     const int pA = AXIS == 0 ? t / N2 : t % P;
     const int n2 = AXIS == 0 ? t % N2 : t / P;
-    const AxisTables& T = a.ax[AXIS];
 
     // tables to LDS (issued before the field loads)
     for (int i = t; i < N; i += NT) {
-        s_tw[i] = T.tw[i];
-        s_kk[i] = T.kk[i];
+        s_tw[i] = t_tw[i];
+        s_kk[i] = t_kk[i];
         if (surf) {
-            s_dl[i] = T.dlo[i];
-            s_dh[i] = T.dhi[i];
+            s_dl[i] = t_dlo[i];
+            s_dh[i] = t_dhi[i];
         }
     }
 
-    // segmented pencils: element e of segment `seg` is global index
-    // seg * C - H + e, weighted by wloc[e]; plain pencils: C = N, H = 0
-    const int C = SEG ? a.seg_core : N;
-    const int H = SEG ? a.seg_halo : 0;
-    const int nseg = SEG ? a.nseg : 1;
-    const int Ng = AXIS == 0 ? a.nx : AXIS == 1 ? a.ny : a.nz;
-    const int tx = AXIS == 0 ? 0 : tile % a.ntx;      // x tile (y, z passes)
-    const int tq = AXIS == 0 ? 0 : tile / a.ntx;      // (other, segment) of the y, z passes
+    const int Ng = AXIS == 0 ? nx : AXIS == 1 ? ny : nz;
+    const int tx = AXIS == 0 ? 0 : tile % ntx;      // x tile (y, z passes)
+    const int tq = AXIS == 0 ? 0 : tile / ntx;      // (other, segment) of the y, z passes
 
     // pencil geometry: element e of pencil pA lives at base + e * estride
     int64_t base = 0, estride = 1;
@@ -96,23 +113,23 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
         const int64_t q = (int64_t)tile * P + pA;
         const int64_t row = q / nseg;
         seg = (int)(q % nseg);
-        valid = activeA && q < (int64_t)a.ny * a.nz * nseg;
-        base = row * a.nx + (seg * C - H);
+        valid = activeA && q < (int64_t)ny * nz * nseg;
+        base = row * nx + (seg * C - H);
         estride = 1;
     } else if constexpr (AXIS == 1) {
         const int x = tx * P + pA;
         const int z = tq / nseg;
         seg = tq % nseg;
-        valid = activeA && x < a.nx;
-        estride = a.nx;
-        base = x + (int64_t)a.nx * a.ny * z + (int64_t)(seg * C - H) * estride;
+        valid = activeA && x < nx;
+        estride = nx;
+        base = x + (int64_t)nx * ny * z + (int64_t)(seg * C - H) * estride;
     } else {
         px = tx * P + pA;
         py = tq / nseg;
         seg = tq % nseg;
-        valid = activeA && px < a.nx;
-        estride = (int64_t)a.nx * a.ny;
-        base = px + (int64_t)a.nx * py + (int64_t)(seg * C - H) * estride;
+        valid = activeA && px < nx;
+        estride = (int64_t)nx * ny;
+        base = px + (int64_t)nx * py + (int64_t)(seg * C - H) * estride;
     }
     const int g0 = seg * C - H;  // global index of element 0
 
@@ -124,15 +141,15 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
         const bool in = valid && (!SEG || (g0 + e >= 0 && g0 + e < Ng));
         float2 x = in ? psi[base + (int64_t)e * estride] : make_float2(0.f, 0.f);
         if constexpr (AXIS == 2) keep[n1] = x;
-        if constexpr (SEG) x = cscale(x, a.wloc[e]);
+        if constexpr (SEG) x = cscale(x, wloc[e]);
         v[n1] = x;
     });
     // plane values: read directly by the thread that owns the element
     // (planes lie in a core, where the halo weight is 1)
     float2 plo = make_float2(0.f, 0.f), phi = plo;
     if (surf && valid) {
-        if (n2 == a.plane_lo % N2 && seg == a.seg_plane[0]) plo = psi[base + (int64_t)a.plane_lo * estride];
-        if (n2 == a.plane_hi % N2 && seg == a.seg_plane[1]) phi = psi[base + (int64_t)a.plane_hi * estride];
+        if (n2 == plane_lo % N2 && seg == seg_plane0) plo = psi[base + (int64_t)plane_lo * estride];
+        if (n2 == plane_hi % N2 && seg == seg_plane1) phi = psi[base + (int64_t)plane_hi * estride];
     }
     __syncthreads();
 
@@ -194,7 +211,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
-                if (!SEG || (e >= H && e < H + C)) a.L[base + e] = v[n1];
+                if (!SEG || (e >= H && e < H + C)) Lbuf[base + e] = v[n1];
             });
         } else if constexpr (AXIS == 1) {
             unroll<N1>([&](auto i) {
@@ -202,29 +219,31 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
                 const int e = n2 + N2 * n1;
                 if (!SEG || (e >= H && e < H + C)) {
                     const int64_t ad = base + (int64_t)e * estride;
-                    a.L[ad] = cadd(a.L[ad], v[n1]);
+                    Lbuf[ad] = cadd(Lbuf[ad], v[n1]);
                 }
             });
         } else {
-            const float2 Zx = a.ax[0].zt[px], Dx = a.ax[0].dz[px];
-            const float2 Zy = a.ax[1].zt[py], Dy = a.ax[1].dz[py];
+            const AxisTables& X = ap->ax[0];
+            const AxisTables& Y = ap->ax[1];
+            const float2 Zx = X.zt[px], Dx = X.dz[px];
+            const float2 Zy = Y.zt[py], Dy = Y.dz[py];
             const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
             const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
-            const float gxy = a.ax[0].gam[px] * a.ax[1].gam[py];
-            const float2 sigma = a.sigma_tab[nstep];
+            const float gxy = X.gam[px] * Y.gam[py];
+            const float2 sigma = ap->sigma_tab[nstep];
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
                 if (!SEG || (e >= H && e < H + C)) {
                     const int z = g0 + e;
                     const int64_t ad = base + (int64_t)e * estride;
-                    const float2 Lt = cadd(a.L[ad], v[n1]);
+                    const float2 Lt = cadd(Lbuf[ad], v[n1]);
                     const float2 po = psi_old[ad];
-                    const float vv = a.v2[ad];
-                    const float2 s = cadd(cmul(SA, T.zt[z]), cmul(SB, T.dz[z]));
+                    const float vv = v2[ad];
+                    const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
                     float2 q = cadd(Lt, cscale(keep[n1], vv));
                     q = cadd(q, cmul(sigma, s));
-                    const float g = gxy * T.gam[z];
+                    const float g = gxy * t_gam[z];
                     // psi^{n+1} = Gamma (psi^{n-1} - i q)
                     psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
                 }
@@ -247,24 +266,26 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
             const int p = t >> 2;
             const int q = t & 3;
             const int side = q & 1;
+            const int segp = side ? seg_plane1 : seg_plane0;
             int64_t pt = -1;
             if constexpr (AXIS == 0) {
                 const int64_t qq = (int64_t)tile * P + p;
-                if (qq < (int64_t)a.ny * a.nz * nseg && (int)(qq % nseg) == a.seg_plane[side]) pt = qq / nseg;
+                if (qq < (int64_t)ny * nz * nseg && (int)(qq % nseg) == segp) pt = qq / nseg;
             } else {
                 const int x = tx * P + p;
-                if (x < a.nx && tq % nseg == a.seg_plane[side]) pt = x + (int64_t)a.nx * (tq / nseg);
+                if (x < nx && tq % nseg == segp) pt = x + (int64_t)nx * (tq / nseg);
             }
             if (pt >= 0) {
                 float2 s = make_float2(0.f, 0.f);
                 for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
                 const double re = (double)s.x, im = (double)s.y;
-                const double2 w = a.w_tab[nstep];
+                const double2 w = ap->w_tab[nstep];
                 const double zr = w.x * re - w.y * im;
                 const double zi = w.x * im + w.y * re;
                 const int field = (q >> 1) * 2;
-                double2* S = a.acc + (int64_t)(side * 4 + field) * a.points + pt;
-                double2* Cc = a.acc + (int64_t)(side * 4 + field + 1) * a.points + pt;
+                const int64_t points = ap->points;
+                double2* __restrict__ S = ap->acc + (int64_t)(side * 4 + field) * points + pt;
+                double2* __restrict__ Cc = ap->acc + (int64_t)(side * 4 + field + 1) * points + pt;
                 double2 sv = *S, cv = *Cc;
                 neumaier(sv.x, cv.x, zr);
                 neumaier(sv.y, cv.y, zi);
@@ -311,20 +332,23 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
     X(256, 16, 16, 16, 0)       \
     X(288, 16, 18, 16, 0)
 
-using LaunchFn = hipError_t (*)(int axis, const PassArgs* descs, const int* off, int ninst, int tiles,
+using LaunchFn = hipError_t (*)(int axis, const PassArgs* descs, const int* off, int ninst, int tiles, int koff,
                                 hipStream_t stream);
 
 template <int N, int N1, int N2, int P, bool SEG>
-static hipError_t launch_shape(int axis, const PassArgs* descs, const int* off, int ninst, int tiles,
+static hipError_t launch_shape(int axis, const PassArgs* descs, const int* off, int ninst, int tiles, int koff,
                                hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
     if (tiles <= 0) return hipSuccess;
     if (axis == 0)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
+                           koff);
     else if (axis == 1)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
+                           koff);
     else
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst);
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
+                           koff);
     return hipGetLastError();
 }
 
@@ -379,24 +403,24 @@ int variant_tiles(int v, int axis, PassArgs& a) {
 }
 
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, hipStream_t stream) {
+                          int total_tiles, int koff, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
-    return f(axis, descs, off, ninst, total_tiles, stream);
+    return f(axis, descs, off, ninst, total_tiles, koff, stream);
 }
 
 // one lane per instance: vector loads and stores of the counters
-__global__ void advance_kernel(int64_t* __restrict__ ctr, int count) {
+__global__ void advance_kernel(int64_t* __restrict__ ctr, int count, int by) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
         const int64_t n = ctr[2 * i], end = ctr[2 * i + 1];
-        if (n < end) ctr[2 * i] = n + 1;
+        ctr[2 * i] = n + by < end ? n + by : (n < end ? end : n);
     }
 }
 
-hipError_t launch_advance(int64_t* ctr, int count, hipStream_t stream) {
-    hipLaunchKernelGGL(advance_kernel, dim3((count + 63) / 64), dim3(64), 0, stream, ctr, count);
+hipError_t launch_advance(int64_t* ctr, int count, int by, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_kernel, dim3((count + 63) / 64), dim3(64), 0, stream, ctr, count, by);
     return hipGetLastError();
 }
 
