@@ -258,8 +258,7 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent
         pstd::solver_args(s, axis, a);
         const bool seg = s->prob.sub_core[axis] > 0;
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis], stream));
-        hipError_t e = pstd::launch_variant(s->variant[axis], seg, axis, s->desc + axis, s->off + 2 * axis, 1,
-                                            a.tiles, koff, stream);
+        hipError_t e = pstd::launch_variant_single(s->variant[axis], seg, axis, a, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
     }
@@ -499,10 +498,9 @@ pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
             float ms = 0;
             if (!e) e = hipMemcpy(tdesc, &a, sizeof(a), hipMemcpyHostToDevice);
             if (!e) e = hipMemcpy(toff, off, sizeof(off), hipMemcpyHostToDevice);
-            if (!e) e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, 0, s->stream);
+            if (!e) e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
             if (!e) e = hipEventRecord(e0, s->stream);
-            for (int r = 0; r < reps && !e; ++r)
-                e = launch_variant(ids[k], seg, axis, tdesc, toff, 1, a.tiles, 0, s->stream);
+            for (int r = 0; r < reps && !e; ++r) e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
             if (!e) e = hipEventRecord(e1, s->stream);
             if (!e) e = hipEventSynchronize(e1);
             if (!e) e = hipEventElapsedTime(&ms, e0, e1);

@@ -61,6 +61,8 @@ int variant_tiles(int v, int axis, PassArgs& args);
 // works on step ctr[0] + koff of each instance.
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
                           int total_tiles, int koff, hipStream_t stream);
+// Launch variant v for one instance described by `args` (passed by value)
+hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs& args, int koff, hipStream_t stream);
 // advance the step counters of count instances by `by` steps, never past
 // their end (ctr[2i] = step, ctr[2i+1] = end)
 hipError_t launch_advance(int64_t* ctr, int count, int by, hipStream_t stream);

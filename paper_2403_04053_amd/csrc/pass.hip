@@ -38,8 +38,79 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
     s = t;
 }
 
-template <int N, int N1, int N2, int P, int AXIS, bool SEG>
-__global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const PassArgs* __restrict__ descs,
+// Pointers into device global memory.  The descriptor may come from the
+// kernel arguments or from a table in memory; qualifying every pointer keeps
+// the loads and stores global (not flat) either way.
+#define GMEM __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GMEM T* gmem(T* p) { return (GMEM T*)p; }
+
+// the descriptor fields a pass uses, copied once into (uniform) registers
+struct Fields {
+    GMEM const int64_t* ctr;
+    GMEM float2* buf[2];
+    GMEM float2* L;
+    GMEM const float* v2;
+    int nx, ny, nz;
+    GMEM const float *kk, *gam;
+    GMEM const float2 *tw, *zt, *dz, *dlo, *dhi;
+    GMEM const float2 *zt_x, *dz_x, *zt_y, *dz_y;
+    GMEM const float *gam_x, *gam_y;
+    GMEM const float2* sigma_tab;
+    GMEM const double2* w_tab;
+    GMEM const int* dft_tab;
+    int plane_lo, plane_hi, seg_plane0, seg_plane1;
+    GMEM double2* acc;
+    int64_t points;
+    int seg_core, seg_halo, nseg;
+    GMEM const float* wloc;
+    int ntx;
+};
+
+template <int AXIS>
+__device__ __forceinline__ Fields fields(const PassArgs& a) {
+    Fields f;
+    f.ctr = gmem(a.ctr);
+    f.buf[0] = gmem(a.buf[0]);
+    f.buf[1] = gmem(a.buf[1]);
+    f.L = gmem(a.L);
+    f.v2 = gmem(a.v2);
+    f.nx = a.nx;
+    f.ny = a.ny;
+    f.nz = a.nz;
+    f.kk = gmem(a.ax[AXIS].kk);
+    f.gam = gmem(a.ax[AXIS].gam);
+    f.tw = gmem(a.ax[AXIS].tw);
+    f.zt = gmem(a.ax[AXIS].zt);
+    f.dz = gmem(a.ax[AXIS].dz);
+    f.dlo = gmem(a.ax[AXIS].dlo);
+    f.dhi = gmem(a.ax[AXIS].dhi);
+    f.zt_x = gmem(a.ax[0].zt);
+    f.dz_x = gmem(a.ax[0].dz);
+    f.zt_y = gmem(a.ax[1].zt);
+    f.dz_y = gmem(a.ax[1].dz);
+    f.gam_x = gmem(a.ax[0].gam);
+    f.gam_y = gmem(a.ax[1].gam);
+    f.sigma_tab = gmem(a.sigma_tab);
+    f.w_tab = gmem(a.w_tab);
+    f.dft_tab = gmem(a.dft_tab);
+    f.plane_lo = a.plane_lo;
+    f.plane_hi = a.plane_hi;
+    f.seg_plane0 = a.seg_plane[0];
+    f.seg_plane1 = a.seg_plane[1];
+    f.acc = gmem(a.acc);
+    f.points = a.points;
+    f.seg_core = a.seg_core;
+    f.seg_halo = a.seg_halo;
+    f.nseg = a.nseg;
+    f.wloc = gmem(a.wloc);
+    f.ntx = a.ntx;
+    return f;
+}
+
+template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI>
+__global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
+                                                                       const PassArgs* __restrict__ descs,
                                                                        const int* __restrict__ off, int ninst,
                                                                        int koff) {
     constexpr int NT = P * (N1 > N2 ? N1 : N2);
@@ -53,37 +124,44 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
 
     // instance of this workgroup (uniform), its tile, its step: the base
     // counter plus this launch's offset in its group of steps
-    int inst = 0;
-    for (int i = 1; i < ninst; ++i)
-        if ((int)blockIdx.x >= off[i]) inst = i;
-    const PassArgs* __restrict__ ap = descs + inst;
-    const int tile = (int)blockIdx.x - off[inst];
-    const int64_t nstep = ap->ctr[0] + koff;
-    if (nstep >= ap->ctr[1]) return;  // whole workgroup, before any barrier
+    // (MULTI == false: one instance, described by the `single` argument)
+    Fields f;
+    int tile;
+    if constexpr (!MULTI) {
+        f = fields<AXIS>(single);
+        tile = (int)blockIdx.x;
+    } else {
+        int inst = 0;
+        for (int i = 1; i < ninst; ++i)
+            if ((int)blockIdx.x >= off[i]) inst = i;
+        f = fields<AXIS>(descs[inst]);
+        tile = (int)blockIdx.x - off[inst];
+    }
+    const int64_t nstep = f.ctr[0] + koff;
+    if (nstep >= f.ctr[1]) return;  // whole workgroup, before any barrier
 
-    // every field used below, read once (uniform values)
-    const int nx = ap->nx, ny = ap->ny, nz = ap->nz;
-    const float2* __restrict__ psi = ap->buf[nstep & 1];
-    float2* __restrict__ psi_old = ap->buf[(nstep + 1) & 1];
-    float2* __restrict__ Lbuf = ap->L;
-    const float* __restrict__ v2 = ap->v2;
-    const bool surf = ap->dft_tab[nstep] != 0;
-    const float* __restrict__ t_kk = ap->ax[AXIS].kk;
-    const float2* __restrict__ t_tw = ap->ax[AXIS].tw;
-    const float* __restrict__ t_gam = ap->ax[AXIS].gam;
-    const float2* __restrict__ t_zt = ap->ax[AXIS].zt;
-    const float2* __restrict__ t_dz = ap->ax[AXIS].dz;
-    const float2* __restrict__ t_dlo = ap->ax[AXIS].dlo;
-    const float2* __restrict__ t_dhi = ap->ax[AXIS].dhi;
-    const int plane_lo = ap->plane_lo, plane_hi = ap->plane_hi;
-    const int seg_plane0 = ap->seg_plane[0], seg_plane1 = ap->seg_plane[1];
-    const int ntx = ap->ntx;
+    const int nx = f.nx, ny = f.ny, nz = f.nz;
+    GMEM const float2* __restrict__ psi = f.buf[nstep & 1];
+    GMEM float2* __restrict__ psi_old = f.buf[(nstep + 1) & 1];
+    GMEM float2* __restrict__ Lbuf = f.L;
+    GMEM const float* __restrict__ v2 = f.v2;
+    const bool surf = f.dft_tab[nstep] != 0;
+    GMEM const float* __restrict__ t_kk = f.kk;
+    GMEM const float2* __restrict__ t_tw = f.tw;
+    GMEM const float* __restrict__ t_gam = f.gam;
+    GMEM const float2* __restrict__ t_zt = f.zt;
+    GMEM const float2* __restrict__ t_dz = f.dz;
+    GMEM const float2* __restrict__ t_dlo = f.dlo;
+    GMEM const float2* __restrict__ t_dhi = f.dhi;
+    const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
+    const int seg_plane0 = f.seg_plane0, seg_plane1 = f.seg_plane1;
+    const int ntx = f.ntx;
     // segmented pencils: element e of segment `seg` is global index
     // seg * C - H + e, weighted by wloc[e]; plain pencils: C = N, H = 0
-    const int C = SEG ? ap->seg_core : N;
-    const int H = SEG ? ap->seg_halo : 0;
-    const int nseg = SEG ? ap->nseg : 1;
-    const float* __restrict__ wloc = ap->wloc;
+    const int C = SEG ? f.seg_core : N;
+    const int H = SEG ? f.seg_halo : 0;
+    const int nseg = SEG ? f.nseg : 1;
+    GMEM const float* __restrict__ wloc = f.wloc;
 
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
@@ -139,7 +217,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
         constexpr int n1 = decltype(i)::value;
         const int e = n2 + N2 * n1;
         const bool in = valid && (!SEG || (g0 + e >= 0 && g0 + e < Ng));
-        float2 x = in ? psi[base + (int64_t)e * estride] : make_float2(0.f, 0.f);
+        float2 x = make_float2(0.f, 0.f);
+        if (in) x = psi[base + (int64_t)e * estride];
         if constexpr (AXIS == 2) keep[n1] = x;
         if constexpr (SEG) x = cscale(x, wloc[e]);
         v[n1] = x;
@@ -223,14 +302,12 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
                 }
             });
         } else {
-            const AxisTables& X = ap->ax[0];
-            const AxisTables& Y = ap->ax[1];
-            const float2 Zx = X.zt[px], Dx = X.dz[px];
-            const float2 Zy = Y.zt[py], Dy = Y.dz[py];
+            const float2 Zx = f.zt_x[px], Dx = f.dz_x[px];
+            const float2 Zy = f.zt_y[py], Dy = f.dz_y[py];
             const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
             const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
-            const float gxy = X.gam[px] * Y.gam[py];
-            const float2 sigma = ap->sigma_tab[nstep];
+            const float gxy = f.gam_x[px] * f.gam_y[py];
+            const float2 sigma = f.sigma_tab[nstep];
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
@@ -279,13 +356,13 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
                 float2 s = make_float2(0.f, 0.f);
                 for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
                 const double re = (double)s.x, im = (double)s.y;
-                const double2 w = ap->w_tab[nstep];
+                const double2 w = f.w_tab[nstep];
                 const double zr = w.x * re - w.y * im;
                 const double zi = w.x * im + w.y * re;
                 const int field = (q >> 1) * 2;
-                const int64_t points = ap->points;
-                double2* __restrict__ S = ap->acc + (int64_t)(side * 4 + field) * points + pt;
-                double2* __restrict__ Cc = ap->acc + (int64_t)(side * 4 + field + 1) * points + pt;
+                const int64_t points = f.points;
+                GMEM double2* __restrict__ S = f.acc + (int64_t)(side * 4 + field) * points + pt;
+                GMEM double2* __restrict__ Cc = f.acc + (int64_t)(side * 4 + field + 1) * points + pt;
                 double2 sv = *S, cv = *Cc;
                 neumaier(sv.x, cv.x, zr);
                 neumaier(sv.y, cv.y, zi);
@@ -332,23 +409,35 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(const Pas
     X(256, 16, 16, 16, 0)       \
     X(288, 16, 18, 16, 0)
 
-using LaunchFn = hipError_t (*)(int axis, const PassArgs* descs, const int* off, int ninst, int tiles, int koff,
-                                hipStream_t stream);
+using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
+                                int tiles, int koff, hipStream_t stream);
 
 template <int N, int N1, int N2, int P, bool SEG>
-static hipError_t launch_shape(int axis, const PassArgs* descs, const int* off, int ninst, int tiles, int koff,
-                               hipStream_t stream) {
+static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
+                               int tiles, int koff, hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
     if (tiles <= 0) return hipSuccess;
-    if (axis == 0)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
-                           koff);
-    else if (axis == 1)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
-                           koff);
-    else
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG>), dim3(tiles), dim3(threads), 0, stream, descs, off, ninst,
-                           koff);
+    if (ninst == 0) {
+        if (axis == 0)
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+        else if (axis == 1)
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+        else
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+    } else {
+        if (axis == 0)
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+        else if (axis == 1)
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+        else
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+                               descs, off, ninst, koff);
+    }
     return hipGetLastError();
 }
 
@@ -404,10 +493,18 @@ int variant_tiles(int v, int axis, PassArgs& a) {
 
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
                           int total_tiles, int koff, hipStream_t stream) {
+    if (v < 0 || v >= kNumVariants || ninst < 1) return hipErrorInvalidValue;
+    LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
+    if (!f) return hipErrorInvalidValue;
+    const PassArgs none{};
+    return f(axis, none, descs, off, ninst, total_tiles, koff, stream);
+}
+
+hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs& args, int koff, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
-    return f(axis, descs, off, ninst, total_tiles, koff, stream);
+    return f(axis, args, nullptr, nullptr, 0, args.tiles, koff, stream);
 }
 
 // one lane per instance: vector loads and stores of the counters
