@@ -41,7 +41,11 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 // Pointers into device global memory.  The descriptor may come from the
 // kernel arguments or from a table in memory; qualifying every pointer keeps
 // the loads and stores global (not flat) either way.
+#if defined(__HIP_DEVICE_COMPILE__)
 #define GMEM __attribute__((address_space(1)))
+#else
+#define GMEM
+#endif
 template <class T>
 __device__ __forceinline__ GMEM T* gmem(T* p) { return (GMEM T*)p; }
 
