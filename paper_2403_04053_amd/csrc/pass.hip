@@ -52,7 +52,8 @@ __device__ __forceinline__ GMEM T* gmem(T* p) { return (GMEM T*)p; }
 // the descriptor fields a pass uses, copied once into (uniform) registers
 struct Fields {
     GMEM const int64_t* ctr;
-    GMEM float2* buf[2];
+    GMEM float2* buf0;
+    GMEM float2* buf1;
     GMEM float2* L;
     GMEM const float* v2;
     int nx, ny, nz;
@@ -75,8 +76,8 @@ template <int AXIS>
 __device__ __forceinline__ Fields fields(const PassArgs& a) {
     Fields f;
     f.ctr = gmem(a.ctr);
-    f.buf[0] = gmem(a.buf[0]);
-    f.buf[1] = gmem(a.buf[1]);
+    f.buf0 = gmem(a.buf[0]);
+    f.buf1 = gmem(a.buf[1]);
     f.L = gmem(a.L);
     f.v2 = gmem(a.v2);
     f.nx = a.nx;
@@ -145,8 +146,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     if (nstep >= f.ctr[1]) return;  // whole workgroup, before any barrier
 
     const int nx = f.nx, ny = f.ny, nz = f.nz;
-    GMEM const float2* __restrict__ psi = f.buf[nstep & 1];
-    GMEM float2* __restrict__ psi_old = f.buf[(nstep + 1) & 1];
+    GMEM const float2* __restrict__ psi = (nstep & 1) ? f.buf1 : f.buf0;
+    GMEM float2* __restrict__ psi_old = (nstep & 1) ? f.buf0 : f.buf1;
     GMEM float2* __restrict__ Lbuf = f.L;
     GMEM const float* __restrict__ v2 = f.v2;
     const bool surf = f.dft_tab[nstep] != 0;
