@@ -178,6 +178,40 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_ob
  * of Eq. FDTDfarfieldapprox.  Output complex128. */
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
 
+/*
+ * Differentiation with respect to the voxel potential (not in the paper; the
+ * discrete adjoint of Eq. PSTDupdating, of the surface DFT of Eqs. psiphasor /
+ * dpsiphasor / scaledphsiphasor and of the box projection of Section 3.2).
+ *
+ * Misfit of a detector-plane intensity:
+ *   J(V) = 1/2 sum_o (|exp(i k0 khat . r_o) + Psi_o|^2 - I_o)^2,
+ * Psi_o = pstd_project at the points r_o, I_o the target intensities.
+ */
+
+/* From rest (psi^{-1} = psi^0 = 0, step 0, surface DFT cleared), run n_steps
+ * steps with the current potential, keeping n_checkpoints checkpoint pairs
+ * (psi^{kS-1}, psi^{kS}) at the segment starts kS, S = ceil(n_steps /
+ * n_checkpoints), and evaluate J (written to *J_out_host, FP64).
+ * obs_xyz_dev: n_obs physical points (double[3] each, outside the box);
+ * target_I_dev: n_obs doubles.  Both are copied.  Device memory held until
+ * pstd_destroy or a forward call with other sizes:
+ * (2 n_checkpoints + S + 5) complex64 fields of the grid plus one FP64 field.
+ * Synchronises.  EINVAL: n_checkpoints outside [1, n_steps], no window step
+ * before n_steps, a point inside the box.  EUNSUPPORTED: segmented axes.
+ * ESTATE: a batch instance.  ENONFINITE: J is not finite. */
+pstd_status pstd_misfit_forward(pstd_solver* s, int64_t n_steps, const double* obs_xyz_dev, int64_t n_obs,
+                                const double* target_I_dev, int32_t n_checkpoints, double* J_out_host);
+
+/* dJ/dV (float32, energy^-1 per cell times energy^2 of J: d J / d V_c in the
+ * units of V, layout [k][j][i]) of the last pstd_misfit_forward.  Recomputes
+ * each segment from its checkpoint and runs the adjoint steps backwards
+ * (about two forward steps of work per step).  The gradient covers every
+ * cell; pstd_set_potential accepts V only where the taper is one, so callers
+ * mask the rest.  Leaves the solver in the state the forward run ended in and
+ * may be called again.  Synchronises.  ESTATE: no forward run, or the solver
+ * stepped, took a new potential or state since. */
+pstd_status pstd_misfit_backward(pstd_solver* s, float* dJdV_dev, int64_t n_cells);
+
 pstd_status pstd_destroy(pstd_solver* s);
 
 /*

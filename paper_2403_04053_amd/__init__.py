@@ -15,7 +15,7 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_far_field", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -115,6 +115,8 @@ _SIGS = {
     "pstd_get_surface_phasors": [_vp, _vp, _i64],
     "pstd_project": [_vp, _vp, _i64, _vp],
     "pstd_far_field": [_vp, _vp, _i64, _vp],
+    "pstd_misfit_forward": [_vp, _i64, _vp, _i64, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "pstd_misfit_backward": [_vp, _vp, _i64],
     "pstd_destroy": [_vp],
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
@@ -242,6 +244,17 @@ def pstd_project(solver, obs_dev, n_obs, out_dev):
 
 def pstd_far_field(solver, dir_dev, n_dir, out_dev):
     _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
+
+
+def pstd_misfit_forward(solver, n_steps, obs_dev, n_obs, target_dev, n_checkpoints):
+    J = ctypes.c_double()
+    _check(lib.pstd_misfit_forward(solver, int(n_steps), _ptr(obs_dev), int(n_obs), _ptr(target_dev),
+                                   int(n_checkpoints), ctypes.byref(J)), solver)
+    return J.value
+
+
+def pstd_misfit_backward(solver, out_dev, n_cells):
+    _check(lib.pstd_misfit_backward(solver, _ptr(out_dev), int(n_cells)), solver)
 
 
 def pstd_autotune(solver, reps=5):
@@ -407,6 +420,56 @@ class Solver:
         out = self.torch.empty(d.shape[0], dtype=self.torch.complex128, device=self.device)
         pstd_far_field(self.handle, d, d.shape[0], out)
         return out
+
+
+    def misfit(self, n_steps, points, target, n_checkpoints=None):
+        """J of the detector-plane intensity misfit (pstd_misfit_forward)."""
+        import math
+        torch = self.torch
+        pts = torch.as_tensor(points, dtype=torch.float64, device=self.device).contiguous()
+        tgt = torch.as_tensor(target, dtype=torch.float64, device=self.device).contiguous()
+        if n_checkpoints is None:
+            n_checkpoints = max(1, math.ceil(math.sqrt(n_steps)))
+        return pstd_misfit_forward(self.handle, n_steps, pts, pts.shape[0], tgt, n_checkpoints)
+
+    def misfit_gradient(self):
+        """dJ/dV of the last misfit run (pstd_misfit_backward), [k][j][i] float32."""
+        out = self.torch.empty(self._shape(), dtype=self.torch.float32, device=self.device)
+        pstd_misfit_backward(self.handle, out, self.cells)
+        return out
+
+
+def _fresnel_misfit_class():
+    import torch
+
+    class FresnelMisfit(torch.autograd.Function):
+        """J(V) with dJ/dV from the library's adjoint run.
+
+        apply(V, solver, n_steps, points, target, n_checkpoints) -> 0-d float64
+        tensor; V is a float32 [nz, ny, nx] CUDA tensor in energy units.
+        """
+
+        @staticmethod
+        def forward(ctx, V, solver, n_steps, points, target, n_checkpoints=None):
+            solver.set_potential(V.detach())
+            J = solver.misfit(n_steps, points, target, n_checkpoints)
+            ctx.solver = solver
+            return torch.tensor(J, dtype=torch.float64, device=V.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.solver.misfit_gradient()
+            return (g * grad_out.to(g.dtype)).reshape(g.shape), None, None, None, None, None
+
+    return FresnelMisfit
+
+
+def __getattr__(name):
+    if name == "FresnelMisfit":
+        cls = _fresnel_misfit_class()
+        globals()["FresnelMisfit"] = cls
+        return cls
+    raise AttributeError(name)
 
 
 class _BorrowedSolver(Solver):

@@ -363,6 +363,7 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     HIP_TRY(s, hipMemcpy(s->dft_tab, on.data(), cap * sizeof(int), hipMemcpyHostToDevice));
     s->tab_cap = cap;
     s->tab_gen += 1;
+    solver_drop_graph(s);  // the graph's launches hold the old table addresses
     return upload_descs(s);
 }
 
@@ -583,6 +584,7 @@ pstd_status pstd_create(const pstd_problem* p, void* hip_stream, pstd_solver** o
 pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cells) {
     if (!s || !V_dev) return PSTD_EINVAL;
     if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
+    adjoint_invalidate(s);
     std::vector<float> V(n_cells);
     HIP_TRY(s, hipMemcpyAsync(V.data(), V_dev, n_cells * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -616,6 +618,7 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
 pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, int64_t n_cells, int64_t step) {
     if (!s || !prev || !cur || step < 0) return PSTD_EINVAL;
     if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
+    adjoint_invalidate(s);
     pstd_status st = solver_ensure_tables(s, step + 1);
     if (st) return st;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -633,6 +636,7 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
 pstd_status pstd_run(pstd_solver* s, int64_t n_steps) {
     if (!s || n_steps < 0) return PSTD_EINVAL;
     if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
+    adjoint_invalidate(s);
     pstd_status st = solver_ensure_tables(s, s->step + n_steps);
     if (st) return st;
     int64_t left = n_steps;
@@ -649,6 +653,7 @@ pstd_status pstd_run(pstd_solver* s, int64_t n_steps) {
 pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     if (!s || n_steps < 0 || !pass_ms) return PSTD_EINVAL;
     if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
+    adjoint_invalidate(s);
     pstd_status st = solver_ensure_tables(s, s->step + n_steps);
     if (st) return st;
     hipEvent_t ev[6];
@@ -792,6 +797,7 @@ pstd_status pstd_destroy(pstd_solver* s) {
     if (s->owns_ctr) (void)hipFree(s->ctr);
     for (int a = 0; a < 3; ++a) (void)hipFree(s->acc[a]);
     project_free(s->proj);
+    adjoint_free(s);
     delete s;
     return PSTD_OK;
 }

@@ -42,6 +42,18 @@ struct PassArgs {
     int seg_plane[2];          // segment holding the low / high plane
     int tiles;                 // workgroups of this instance in this pass
     int ntx;                   // x tiles of the y and z passes
+    // adjoint steps only: injected surface terms of this axis's low / high
+    // planes (psi part, derivative part), the forward state each step pairs
+    // with, and the gradient accumulator
+    const float2* inj_lo_p;
+    const float2* inj_lo_d;
+    const float2* inj_hi_p;
+    const float2* inj_hi_d;
+    const float2* const* fwd_tab;
+    float* grad;
+    // forward steps only, may be null: per step, where to store a copy of
+    // psi^{n+1} (null entry: no copy)
+    float2* const* stash_tab;
 };
 
 // FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
@@ -63,6 +75,12 @@ hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs
                           int total_tiles, int koff, hipStream_t stream);
 // Launch variant v for one instance described by `args` (passed by value)
 hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs& args, int koff, hipStream_t stream);
+// Adjoint step pass (plain pencils, one instance)
+hipError_t launch_variant_adjoint(int v, int axis, const PassArgs& args, int koff, hipStream_t stream);
+// acc64[i] += acc32[i]; acc32[i] = 0
+hipError_t launch_fold(double* acc64, float* acc32, int64_t n, hipStream_t stream);
+// out[i] = (float)(scale * acc64[i])
+hipError_t launch_scale_out(const double* acc64, double scale, float* out, int64_t n, hipStream_t stream);
 // advance the step counters of count instances by `by` steps, never past
 // their end (ctr[2i] = step, ctr[2i+1] = end)
 hipError_t launch_advance(int64_t* ctr, int count, int by, hipStream_t stream);

@@ -49,6 +49,9 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 template <class T>
 __device__ __forceinline__ GMEM T* gmem(T* p) { return (GMEM T*)p; }
 
+using PtrF2 = float2*;
+using CPtrF2 = const float2*;
+
 // the descriptor fields a pass uses, copied once into (uniform) registers
 struct Fields {
     GMEM const int64_t* ctr;
@@ -70,6 +73,10 @@ struct Fields {
     int seg_core, seg_halo, nseg;
     GMEM const float* wloc;
     int ntx;
+    GMEM const float2 *inj_lo_p, *inj_lo_d, *inj_hi_p, *inj_hi_d;
+    GMEM const CPtrF2* fwd_tab;
+    GMEM float* grad;
+    GMEM const PtrF2* stash_tab;
 };
 
 template <int AXIS>
@@ -110,10 +117,17 @@ __device__ __forceinline__ Fields fields(const PassArgs& a) {
     f.nseg = a.nseg;
     f.wloc = gmem(a.wloc);
     f.ntx = a.ntx;
+    f.inj_lo_p = gmem(a.inj_lo_p);
+    f.inj_lo_d = gmem(a.inj_lo_d);
+    f.inj_hi_p = gmem(a.inj_hi_p);
+    f.inj_hi_d = gmem(a.inj_hi_d);
+    f.fwd_tab = gmem(a.fwd_tab);
+    f.grad = gmem(a.grad);
+    f.stash_tab = gmem(a.stash_tab);
     return f;
 }
 
-template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI>
+template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
                                                                        const PassArgs* __restrict__ descs,
                                                                        const int* __restrict__ off, int ninst,
@@ -231,7 +245,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     // plane values: read directly by the thread that owns the element
     // (planes lie in a core, where the halo weight is 1)
     float2 plo = make_float2(0.f, 0.f), phi = plo;
-    if (surf && valid) {
+    if (!ADJ && surf && valid) {
         if (n2 == plane_lo % N2 && seg == seg_plane0) plo = psi[base + (int64_t)plane_lo * estride];
         if (n2 == plane_hi % N2 && seg == seg_plane1) phi = psi[base + (int64_t)plane_hi * estride];
     }
@@ -239,7 +253,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
 
     // spectral normal derivative on the two planes: partial dot products
     float2 dlo = make_float2(0.f, 0.f), dhi = dlo;
-    if (surf) {
+    if (!ADJ && surf) {
         unroll<N1>([&](auto i) {
             constexpr int n1 = decltype(i)::value;
             const int e = n2 + N2 * n1;
@@ -289,6 +303,37 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     }
     dft<N1, 1>(v);
 
+    // ---- adjoint steps: the surface terms injected along this pencil,
+    // c (plane values on the planes + derivative rows times the derivative
+    // parts), c = i w_m from the step table ----
+    float2 cinj = make_float2(0.f, 0.f);
+    float2 hpl = cinj, hdl = cinj, hph = cinj, hdh = cinj;
+    if constexpr (ADJ) {
+        if (surf && valid) {
+            const double2 cw = f.w_tab[nstep];
+            cinj = make_float2((float)cw.x, (float)cw.y);
+            int64_t pt;
+            if constexpr (AXIS == 0) pt = (int64_t)tile * P + pA;
+            else pt = tx * P + pA + (int64_t)nx * tq;
+            hpl = cmul(cinj, f.inj_lo_p[pt]);
+            hdl = cmul(cinj, f.inj_lo_d[pt]);
+            hph = cmul(cinj, f.inj_hi_p[pt]);
+            hdh = cmul(cinj, f.inj_hi_d[pt]);
+        }
+        if (surf) {
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                const int e = n2 + N2 * n1;
+                if (e < N) {
+                    float2 x = cadd(cmul(s_dl[e], hdl), cmul(s_dh[e], hdh));
+                    if (e == plane_lo) x = cadd(x, hpl);
+                    if (e == plane_hi) x = cadd(x, hph);
+                    v[n1] = cadd(v[n1], x);
+                }
+            });
+        }
+    }
+
     // ---- epilogue (only core elements are written) ----
     if (valid) {
         if constexpr (AXIS == 0) {
@@ -312,7 +357,12 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
             const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
             const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
             const float gxy = f.gam_x[px] * f.gam_y[py];
-            const float2 sigma = f.sigma_tab[nstep];
+            float2 sigma = make_float2(0.f, 0.f);
+            if constexpr (!ADJ) sigma = f.sigma_tab[nstep];
+            GMEM const float2* __restrict__ fwd = nullptr;
+            GMEM float2* __restrict__ stash = nullptr;
+            if constexpr (ADJ) fwd = gmem(f.fwd_tab[nstep]);
+            else if (f.stash_tab) stash = gmem(f.stash_tab[nstep]);
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
@@ -322,19 +372,28 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     const float2 Lt = cadd(Lbuf[ad], v[n1]);
                     const float2 po = psi_old[ad];
                     const float vv = v2[ad];
-                    const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
                     float2 q = cadd(Lt, cscale(keep[n1], vv));
-                    q = cadd(q, cmul(sigma, s));
+                    if constexpr (!ADJ) {
+                        const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
+                        q = cadd(q, cmul(sigma, s));
+                    }
                     const float g = gxy * t_gam[z];
                     // psi^{n+1} = Gamma (psi^{n-1} - i q)
-                    psi_old[ad] = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                    const float2 nv = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                    psi_old[ad] = nv;
+                    if (stash) stash[ad] = nv;
+                    if constexpr (ADJ) {
+                        // Im(chi^m psi^{m-1})
+                        const float2 fv = fwd[ad];
+                        f.grad[ad] += nv.x * fv.y + nv.y * fv.x;
+                    }
                 }
             });
         }
     }
 
     // ---- surface DFT: reduce the per-thread partials, accumulate in FP64 ----
-    if (surf) {
+    if (!ADJ && surf) {
         __syncthreads();  // every thread has read its exchange slots
         if (activeA) {
             float2* r = &ex[pA * STRIDE + n2 * 4];
@@ -424,27 +483,45 @@ static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs*
     if (tiles <= 0) return hipSuccess;
     if (ninst == 0) {
         if (axis == 0)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
         else if (axis == 1)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
         else
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, false>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
     } else {
         if (axis == 0)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
         else if (axis == 1)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
         else
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, true>), dim3(tiles), dim3(threads), 0, stream, single,
+            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
                                descs, off, ninst, koff);
     }
     return hipGetLastError();
 }
+
+template <int N, int N1, int N2, int P>
+static hipError_t launch_adjoint_shape(int axis, const PassArgs& a, int koff, hipStream_t stream) {
+    constexpr int threads = P * (N1 > N2 ? N1 : N2);
+    if (a.tiles <= 0) return hipSuccess;
+    if (axis == 0)
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
+                           a, nullptr, nullptr, 0, koff);
+    else if (axis == 1)
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
+                           a, nullptr, nullptr, 0, koff);
+    else
+        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
+                           a, nullptr, nullptr, 0, koff);
+    return hipGetLastError();
+}
+
+using AdjFn = hipError_t (*)(int axis, const PassArgs& a, int koff, hipStream_t stream);
 
 namespace {
 
@@ -452,6 +529,7 @@ struct VariantEntry {
     PassShape shape;
     LaunchFn plain;
     LaunchFn seg;  // null when the shape has no segmented instance
+    AdjFn adj;
 };
 
 template <int N, int N1, int N2, int P, int S>
@@ -461,8 +539,9 @@ constexpr LaunchFn seg_fn() {
 }
 
 const VariantEntry kVariants[] = {
-#define PSTD_ENTRY(n, a, b, p, s) \
-    {PassShape{n, a, b, p, p * (a > b ? a : b)}, &launch_shape<n, a, b, p, false>, seg_fn<n, a, b, p, s>()},
+#define PSTD_ENTRY(n, a, b, p, s)                                                                             \
+    {PassShape{n, a, b, p, p * (a > b ? a : b)}, &launch_shape<n, a, b, p, false>, seg_fn<n, a, b, p, s>(), \
+     &launch_adjoint_shape<n, a, b, p>},
     PSTD_VARIANTS(PSTD_ENTRY)
 #undef PSTD_ENTRY
 };
@@ -510,6 +589,34 @@ hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
     return f(axis, args, nullptr, nullptr, 0, args.tiles, koff, stream);
+}
+
+hipError_t launch_variant_adjoint(int v, int axis, const PassArgs& args, int koff, hipStream_t stream) {
+    if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
+    return kVariants[v].adj(axis, args, koff, stream);
+}
+
+__global__ void fold_kernel(double* __restrict__ acc64, float* __restrict__ acc32, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        acc64[i] += (double)acc32[i];
+        acc32[i] = 0.f;
+    }
+}
+
+hipError_t launch_fold(double* acc64, float* acc32, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(fold_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, acc64, acc32, n);
+    return hipGetLastError();
+}
+
+__global__ void scale_out_kernel(const double* __restrict__ acc64, double scale, float* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)(scale * acc64[i]);
+}
+
+hipError_t launch_scale_out(const double* acc64, double scale, float* out, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(scale_out_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, acc64, scale, out, n);
+    return hipGetLastError();
 }
 
 // one lane per instance: vector loads and stores of the counters

@@ -218,14 +218,15 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
     __shared__ double2 sq[kCellChunk * 2 * kTerms * kTerms];
     const int64_t pi = (int64_t)blockIdx.x * kNearThreads + threadIdx.x;
     const bool live = pi < n_obs;
-    double r[3] = {0, 0, 0};
+    double ra_ = 0, rb_ = 0, rc_ = 0;  // point in the face frame (normal, b, c)
     if (live) {
         const double3 o = obs[pi];
-        r[0] = o.x * k0;
-        r[1] = o.y * k0;
-        r[2] = o.z * k0;
+        const double x = o.x * k0, y = o.y * k0, z = o.z * k0;
+        ra_ = g.a == 0 ? x : g.a == 1 ? y : z;
+        rb_ = g.b == 0 ? x : g.b == 1 ? y : z;
+        rc_ = g.c == 0 ? x : g.c == 1 ? y : z;
     }
-    const double Ra = r[g.a] - g.xa;
+    const double Ra = ra_ - g.xa;
     double2 acc = make_double2(0, 0);
     const int64_t ncell = (int64_t)g.L * g.M;
     constexpr int per_cell = 2 * kTerms * kTerms;
@@ -238,19 +239,22 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
         for (int ci = 0; ci < nc; ++ci) {
             const int64_t cell = c0 + ci;
             const int m = (int)(cell / g.L), l = (int)(cell % g.L);
-            const double Rb = r[g.b] - (g.xb0 + l * g.db);
-            const double Rc = r[g.c] - (g.xc0 + m * g.dc);
+            const double Rb = rb_ - (g.xb0 + l * g.db);
+            const double Rc = rc_ - (g.xc0 + m * g.dc);
             const double R2 = Ra * Ra + Rb * Rb + Rc * Rc;
             const double Rn = sqrt(R2);
             const double inv = 1.0 / Rn;
             const double ab = g.db * Rb * inv * 0.5, ac = g.dc * Rc * inv * 0.5;
             const double2* q = &sq[ci * per_cell];
-            double2 S[2];
+            double2 S0 = make_double2(0, 0), S1 = S0;
+#pragma unroll 1
             for (int fld = 0; fld < 2; ++fld) {
                 double2 outer = make_double2(0, 0);
+#pragma unroll 1
                 for (int p = kOrder; p >= 0; --p) {
                     double2 inner = make_double2(0, 0);
                     const double2* row = q + (fld * kTerms + p) * kTerms;
+#pragma unroll
                     for (int qq = kOrder; qq >= 0; --qq) {
                         inner.x = inner.x * ac + row[qq].x;
                         inner.y = inner.y * ac + row[qq].y;
@@ -258,18 +262,88 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
                     outer.x = outer.x * ab + inner.x;
                     outer.y = outer.y * ab + inner.y;
                 }
-                S[fld] = outer;
+                if (fld == 0) S0 = outer;
+                else S1 = outer;
             }
             // e^{iR}/R (S_dpsi + (i - 1/R) (R_a/R) S_psi)
             const double ra = Ra * inv;
             const double2 coef = make_double2(-inv * ra, ra);
-            const double2 inner = zadd(S[1], zmul(coef, S[0]));
+            const double2 inner = zadd(S1, zmul(coef, S0));
             double sn, cs;
             sincos(Rn, &sn, &cs);
             acc = zadd(acc, zmul(make_double2(cs * inv, sn * inv), inner));
         }
     }
     if (live) out[pi] = zadd(out[pi], make_double2(acc.x * g.pref, acc.y * g.pref));
+}
+
+// Adjoint of the per-point cell sums: for one cell and one p,
+// Qbar[fld][p][q][cell] = sum_o conj(pref e^{iR}/R alpha_b^p alpha_c^q [coef]) g_o,
+// coef = (i - 1/R) R_a / R for the psi field (fld 0), 1 for dpsi (fld 1).
+constexpr int kAdjObsChunk = 256;
+
+__global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __restrict__ obs, const double2* __restrict__ gv,
+                                                           int64_t n_obs, double k0, FaceGeo g,
+                                                           double2* __restrict__ Qbar) {
+    __shared__ double3 so[kAdjObsChunk];
+    __shared__ double2 sg[kAdjObsChunk];
+    const int64_t ncell = (int64_t)g.L * g.M;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = id < ncell * kTerms;
+    const int64_t cell = live ? id % ncell : 0;
+    const int p = live ? (int)(id / ncell) : 0;
+    const int m = (int)(cell / g.L), l = (int)(cell % g.L);
+    const double yb = g.xb0 + l * g.db, yc = g.xc0 + m * g.dc;
+    double2 acc[2][kTerms];
+    for (int f = 0; f < 2; ++f)
+        for (int q = 0; q < kTerms; ++q) acc[f][q] = make_double2(0, 0);
+    for (int64_t o0 = 0; o0 < n_obs; o0 += kAdjObsChunk) {
+        const int no = (int)min<int64_t>(kAdjObsChunk, n_obs - o0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < no; e += blockDim.x) {
+            so[e] = obs[o0 + e];
+            sg[e] = gv[o0 + e];
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int e = 0; e < no; ++e) {
+            const double x = so[e].x * k0, y = so[e].y * k0, z = so[e].z * k0;
+            const double Ra = (g.a == 0 ? x : g.a == 1 ? y : z) - g.xa;
+            const double Rb = (g.b == 0 ? x : g.b == 1 ? y : z) - yb;
+            const double Rc = (g.c == 0 ? x : g.c == 1 ? y : z) - yc;
+            const double Rn = sqrt(Ra * Ra + Rb * Rb + Rc * Rc);
+            const double inv = 1.0 / Rn;
+            const double ab = g.db * Rb * inv * 0.5, ac = g.dc * Rc * inv * 0.5;
+            double sn, cs;
+            sincos(Rn, &sn, &cs);
+            // conj(pref e^{iR}/R alpha_b^p) g
+            double abp = 1.0;
+            for (int t = 0; t < p; ++t) abp *= ab;
+            const double wr = g.pref * inv * abp;
+            const double2 gg = sg[e];
+            const double2 base = make_double2(wr * (cs * gg.x + sn * gg.y), wr * (cs * gg.y - sn * gg.x));
+            // conj(coef) = (-i - 1/R) R_a/R
+            const double rr = Ra * inv;
+            const double2 cbase = make_double2(-inv * rr * base.x + rr * base.y, -inv * rr * base.y - rr * base.x);
+            double acq = 1.0;
+            for (int q = 0; q < kTerms; ++q) {
+                acc[0][q].x += acq * cbase.x;
+                acc[0][q].y += acq * cbase.y;
+                acc[1][q].x += acq * base.x;
+                acc[1][q].y += acq * base.y;
+                acq *= ac;
+            }
+        }
+    }
+    if (!live) return;
+    for (int f = 0; f < 2; ++f)
+        for (int q = 0; q < kTerms; ++q) Qbar[(((int64_t)f * kTerms + p) * kTerms + q) * ncell + cell] = acc[f][q];
+}
+
+// out = conj(x) * scale as complex64
+__global__ void conj_scale_kernel(const double2* __restrict__ x, int64_t n, double scale, float2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_float2((float)(x[i].x * scale), (float)(-x[i].y * scale));
 }
 
 // Q[p][q][m][l] (GEMM output) -> [cell][field][p][q]
@@ -306,7 +380,8 @@ struct ProjectState {
     double2* spectra = nullptr;   // [face][2][plane]
     double2* work = nullptr;      // scratch
     size_t work_bytes = 0;
-    double2* tw = nullptr;        // per distinct length: twiddles (3 axes)
+    double2* tw = nullptr;        // per axis: twiddles exp(-2 pi i j / N)
+    double2* twc = nullptr;       // per axis: conjugate twiddles
     int64_t face_off[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t total = 0;
 };
@@ -343,7 +418,8 @@ hipError_t prepare(ProjectState** pst, const pstd_problem& p, double2* const acc
         s->total = off;
         hipError_t e;
         if ((e = hipMalloc(&s->phasors, off * sizeof(double2))) || (e = hipMalloc(&s->spectra, off * sizeof(double2))) ||
-            (e = hipMalloc(&s->tw, (size_t)(p.n[0] + p.n[1] + p.n[2]) * sizeof(double2)))) {
+            (e = hipMalloc(&s->tw, (size_t)(p.n[0] + p.n[1] + p.n[2]) * sizeof(double2))) ||
+            (e = hipMalloc(&s->twc, (size_t)(p.n[0] + p.n[1] + p.n[2]) * sizeof(double2)))) {
             project_free(s);
             return e;
         }
@@ -351,7 +427,10 @@ hipError_t prepare(ProjectState** pst, const pstd_problem& p, double2* const acc
         for (int a = 0; a < 3; ++a)
             for (int j = 0; j < p.n[a]; ++j)
                 tw.push_back(make_double2(std::cos(2 * kPi * j / p.n[a]), -std::sin(2 * kPi * j / p.n[a])));
-        if ((e = hipMemcpy(s->tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice))) {
+        std::vector<double2> twc(tw);
+        for (auto& v : twc) v.y = -v.y;
+        if ((e = hipMemcpy(s->tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(s->twc, twc.data(), twc.size() * sizeof(double2), hipMemcpyHostToDevice))) {
             project_free(s);
             return e;
         }
@@ -530,12 +609,90 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
     return hipGetLastError();
 }
 
+hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                           const int64_t points[3], double scale, const double3* obs, int64_t n_obs, const double2* g,
+                           float2* inj, hipStream_t stream, std::string* msg) {
+    // the state (twiddles, offsets) is shared with the forward projection
+    TRY(prepare(pst, p, acc, points, 1.0, stream));
+    ProjectState* s = *pst;
+    const double2* twc[3] = {s->twc, s->twc + p.n[0], s->twc + p.n[0] + p.n[1]};
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2, side = f % 2, b = face_axis_b(a), c = face_axis_c(a);
+        const int Nb = p.n[b], Nc = p.n[c];
+        const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
+        const int64_t ncell = (int64_t)L * M, np_ = (int64_t)Nb * Nc;
+        // conjugated expansion tables: Vh[c'][q M + m] = conj V_q[m][c'], Uc[p L + l][b'] = conj U_p[l][b']
+        std::vector<double2> Vh((size_t)Nc * kTerms * M), Uc((size_t)kTerms * L * Nb);
+        auto table = [&](int ax, int lo, int cells, int N, auto put) {
+            const double d = dxb[ax], Lp = N * d;
+            double sp[kTerms];
+            for (int mm = 0; mm < N; ++mm) {
+                const int bp = mm < N / 2 ? mm : mm - N;
+                sinc_taylor(kPi * bp / N, sp);
+                for (int l = 0; l < cells; ++l) {
+                    const double xc = (lo + l - N / 2 + 0.5) * d;
+                    const double ph = 2 * kPi * bp * xc / Lp;
+                    const double sg = (bp & 1) ? -1.0 : 1.0;
+                    for (int q = 0; q < kTerms; ++q)
+                        put(q, l, mm, make_double2(sg * sp[q] * std::cos(ph), -sg * sp[q] * std::sin(ph)));
+                }
+            }
+        };
+        table(c, p.surf_lo[c], M, Nc, [&](int q, int m, int cc, double2 v) { Vh[((size_t)cc * kTerms + q) * M + m] = v; });
+        table(b, p.surf_lo[b], L, Nb, [&](int pp, int l, int bb, double2 v) { Uc[((size_t)pp * L + l) * Nb + bb] = v; });
+        const size_t nVh = Vh.size(), nUc = Uc.size(), nQ = (size_t)2 * kTerms * kTerms * ncell,
+                     nW = (size_t)Nc * kTerms * L, nF = (size_t)np_;
+        TRY(ensure(&s->work, &s->work_bytes, (nVh + nUc + nQ + nW + 2 * nF) * sizeof(double2)));
+        double2* dVh = s->work;
+        double2* dUc = dVh + nVh;
+        double2* dQ = dUc + nUc;
+        double2* dW = dQ + nQ;
+        double2* dF = dW + nW;
+        double2* dT = dF + nF;
+        TRY(hipMemcpyAsync(dVh, Vh.data(), nVh * sizeof(double2), hipMemcpyHostToDevice, stream));
+        TRY(hipMemcpyAsync(dUc, Uc.data(), nUc * sizeof(double2), hipMemcpyHostToDevice, stream));
+        FaceGeo geo;
+        geo.a = a;
+        geo.b = b;
+        geo.c = c;
+        geo.lo_b = p.surf_lo[b];
+        geo.lo_c = p.surf_lo[c];
+        geo.L = L;
+        geo.M = M;
+        geo.db = dxb[b];
+        geo.dc = dxb[c];
+        geo.xa = ((side == 0 ? p.surf_lo[a] : p.surf_hi[a]) - p.n[a] / 2) * dxb[a];
+        geo.xb0 = (p.surf_lo[b] - Nb / 2 + 0.5) * dxb[b];
+        geo.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
+        geo.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
+        const int64_t nthr = ncell * kTerms;
+        hipLaunchKernelGGL(near_adjoint_kernel, dim3((unsigned)((nthr + 127) / 128)), dim3(128), 0, stream, obs, g,
+                           n_obs, p.k0, geo, dQ);
+        for (int fld = 0; fld < 2; ++fld) {
+            // Wbar[c'][p L + l] = sum_q Vh_q [Nc x M] Qbar[fld][p][q] [M x L]
+            TRY(zgemm(Nc, L, kTerms * M, dVh, (int64_t)kTerms * M, 0, dQ + (size_t)fld * kTerms * kTerms * ncell, L,
+                      (int64_t)kTerms * ncell, dW, (int64_t)kTerms * L, L, kTerms, stream));
+            // Fbar = Wbar [Nc x 9L] * Uc [9L x Nb]
+            TRY(zgemm(Nc, Nb, kTerms * L, dW, (int64_t)kTerms * L, 0, dUc, Nb, 0, dF, Nb, 0, 1, stream));
+            // plane adjoint of the forward 2D DFT: the unnormalised conjugate DFT
+            const unsigned blocks = (unsigned)((np_ + 255) / 256);
+            hipLaunchKernelGGL(dft_rows_kernel, dim3(blocks), dim3(256), 0, stream, dF, dT, Nb, Nc, twc[b]);
+            hipLaunchKernelGGL(dft_cols_kernel, dim3(blocks), dim3(256), 0, stream, dT, dF, Nb, Nc, twc[c]);
+            hipLaunchKernelGGL(conj_scale_kernel, dim3(blocks), dim3(256), 0, stream, dF, np_, scale,
+                               inj + s->face_off[f] + fld * np_);
+        }
+        TRY(hipStreamSynchronize(stream));  // the scratch is reused by the next face
+    }
+    return hipGetLastError();
+}
+
 void project_free(ProjectState* s) {
     if (!s) return;
     (void)hipFree(s->phasors);
     (void)hipFree(s->spectra);
     (void)hipFree(s->work);
     (void)hipFree(s->tw);
+    (void)hipFree(s->twc);
     delete s;
 }
 

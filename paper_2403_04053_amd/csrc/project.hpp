@@ -24,6 +24,13 @@ hipError_t far_field(ProjectState** st, const pstd_problem& p, const double dxb[
                      const int64_t points[3], double scale, const double3* dirs, int64_t n_dir, double2* out,
                      hipStream_t stream, std::string* msg);
 
+// Adjoint of project_points on the normalised phasors: given g (complex128,
+// one per point), writes conj(G^H g) * scale as complex64 in the phasor
+// layout (per face: psi plane, dpsi plane).
+hipError_t project_adjoint(ProjectState** st, const pstd_problem& p, const double dxb[3], double2* const acc[3],
+                           const int64_t points[3], double scale, const double3* obs, int64_t n_obs, const double2* g,
+                           float2* inj, hipStream_t stream, std::string* msg);
+
 void project_free(ProjectState* st);
 
 }  // namespace pstd

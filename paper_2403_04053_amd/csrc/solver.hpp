@@ -10,6 +10,10 @@
 #include "internal.hpp"
 #include "project.hpp"
 
+namespace pstd {
+struct AdjointState;  // misfit checkpoints and adjoint buffers
+}
+
 struct pstd_solver {
     pstd_problem prob{};
     hipStream_t stream = nullptr;
@@ -45,6 +49,7 @@ struct pstd_solver {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     pstd::ProjectState* proj = nullptr;
+    pstd::AdjointState* adj = nullptr;
     std::string err;
     bool in_batch = false;
 };
@@ -62,5 +67,8 @@ void solver_args(const pstd_solver* s, int axis, PassArgs& a);
 void solver_account_steps(pstd_solver* s, int64_t from, int64_t to);
 pstd_status solver_autotune(pstd_solver* s, int32_t reps);
 void solver_drop_graph(pstd_solver* s);
+// the misfit forward run no longer matches the solver state
+void adjoint_invalidate(pstd_solver* s);
+void adjoint_free(pstd_solver* s);
 
 }  // namespace pstd

@@ -1,0 +1,166 @@
+"""GPU parity of the misfit gradient (discrete adjoint with checkpointed
+recompute) against the FP64 oracle adjoint, itself pinned by dot-product
+tests and finite differences (tests/test_oracle_adjoint.py)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint as oadj
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N_STEPS = 60
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available()
+    import paper_2403_04053_amd as mod
+    return mod
+
+
+def detector(z, n=5, half=0.6):
+    g = np.linspace(-half, half, n)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    prob, V = synth.tiny(n=(20, 20, 24), P=3, transition=3, v0=1.5, radius_cells=2, steps=N_STEPS, dft=(20, N_STEPS))
+    prob = prob.replace(ramp_periods=0.5)
+    V = V.astype(np.float32).astype(np.float64)
+    pts = np.vstack([detector(1.5), [[0.0, 0.0, -1.5]]])
+    target = oadj.intensity(prob, 0.5 * V, pts)
+    J, grad = oadj.gradient(prob, V, pts, target)
+    return prob, V, pts, target, J, grad
+
+
+def solver_for(P, prob, V):
+    s = P.Solver(prob)
+    s.set_potential(V)
+    return s
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n_ck", [8, 1, N_STEPS])
+def test_gradient_matches_oracle(P, setup, n_ck):
+    prob, V, pts, target, J_ref, g_ref = setup
+    print(f"adjoint parity: grid {prob.n}, {N_STEPS} steps, {n_ck} checkpoints", flush=True)
+    s = solver_for(P, prob, V)
+    J = s.misfit(N_STEPS, pts, target, n_checkpoints=n_ck)
+    g = s.misfit_gradient().cpu().numpy().astype(np.float64)
+    print(f"  J rel err {abs(J - J_ref) / J_ref:.2e}, gradient rel L2 {rel_l2(g, g_ref):.2e}", flush=True)
+    assert J == pytest.approx(J_ref, rel=1e-4)
+    assert rel_l2(g, g_ref) <= 1e-3
+    s.close()
+
+
+def test_checkpoint_count_does_not_change_the_gradient(P, setup):
+    prob, V, pts, target, _, _ = setup
+    s = solver_for(P, prob, V)
+    out = []
+    for n_ck in (1, 7, 13, N_STEPS):
+        s.misfit(N_STEPS, pts, target, n_checkpoints=n_ck)
+        out.append(s.misfit_gradient().cpu().numpy())
+    for g in out[1:]:
+        assert rel_l2(g, out[0]) <= 1e-6
+    s.close()
+
+
+def test_backward_restores_the_forward_state_and_repeats(P, setup):
+    prob, V, pts, target, _, _ = setup
+    s = solver_for(P, prob, V)
+    s.misfit(N_STEPS, pts, target, n_checkpoints=6)
+    cur, prev = s.psi(0).clone(), s.psi(1).clone()
+    ph = s.phasors().clone()
+    g1 = s.misfit_gradient()
+    assert s.step == N_STEPS
+    assert torch.equal(s.psi(0), cur) and torch.equal(s.psi(1), prev)
+    assert torch.equal(s.phasors(), ph)
+    g2 = s.misfit_gradient()
+    assert torch.equal(g1, g2)
+    # the forward run equals a plain run of the same steps
+    s2 = solver_for(P, prob, V)
+    s2.run(N_STEPS)
+    assert torch.equal(s2.psi(0), cur)
+    s.close()
+    s2.close()
+
+
+def test_state_errors(P, setup):
+    prob, V, pts, target, _, _ = setup
+    s = solver_for(P, prob, V)
+    with pytest.raises(P.PstdError) as e:
+        s.misfit_gradient()
+    assert e.value.name == "PSTD_ESTATE"
+    with pytest.raises(P.PstdError) as e:
+        s.misfit(N_STEPS, pts, target, n_checkpoints=0)
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:
+        s.misfit(N_STEPS, pts, target, n_checkpoints=N_STEPS + 1)
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:  # no window step before step 10
+        s.misfit(10, pts, target)
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:  # a point inside the box
+        s.misfit(N_STEPS, np.zeros((1, 3)), np.zeros(1))
+    assert e.value.name == "PSTD_EINVAL"
+    s.misfit(N_STEPS, pts, target)
+    s.run(1)
+    with pytest.raises(P.PstdError) as e:
+        s.misfit_gradient()
+    assert e.value.name == "PSTD_ESTATE"
+    s.misfit(N_STEPS, pts, target)
+    s.set_potential(V)
+    with pytest.raises(P.PstdError) as e:
+        s.misfit_gradient()
+    assert e.value.name == "PSTD_ESTATE"
+    s.close()
+
+
+def test_autograd_function(P, setup):
+    prob, V, pts, target, J_ref, g_ref = setup
+    s = P.Solver(prob)
+    Vt = torch.tensor(V, dtype=torch.float32, device="cuda", requires_grad=True)
+    J = P.FresnelMisfit.apply(Vt, s, N_STEPS, pts, target, 5)
+    assert J.dtype == torch.float64 and J.dim() == 0
+    (3.0 * J).backward()
+    g = Vt.grad.cpu().numpy().astype(np.float64)
+    assert float(J) == pytest.approx(J_ref, rel=1e-4)
+    assert rel_l2(g, 3.0 * g_ref) <= 1e-3
+    s.close()
+
+
+def test_gradient_matches_gpu_finite_differences(P, setup):
+    """Central differences of the GPU misfit itself at core voxels where the
+    gradient is large (FP32 forward runs: a large step, 2e-2 E0)."""
+    prob, V, pts, target, _, g_ref = setup
+    s = solver_for(P, prob, V)
+    s.misfit(N_STEPS, pts, target)
+    g = s.misfit_gradient().cpu().numpy().astype(np.float64)
+    c0, c1 = prob.tfsf[0][1], prob.tfsf[0][2]
+    core = np.zeros_like(g, dtype=bool)
+    core[c0:c1 + 1, c0:c1 + 1, c0:c1 + 1] = True
+    core &= V == 0  # room for the +-eps step below v_max
+    order = np.argsort(-np.abs(np.where(core, g, 0.0)).ravel())[:4]
+    eps = 2e-2 * prob.k0 ** 2 / 2
+    for flat in order:
+        idx = np.unravel_index(flat, g.shape)
+        Vp = V.copy()
+        Vp[idx] += eps
+        Vm = V.copy()
+        Vm[idx] -= eps
+        s.set_potential(Vp)
+        Jp = s.misfit(N_STEPS, pts, target)
+        s.set_potential(Vm)
+        Jm = s.misfit(N_STEPS, pts, target)
+        fd = (Jp - Jm) / (2 * eps)
+        print(f"  voxel {tuple(int(i) for i in idx)}: adjoint {g[idx]:.6e}, FD {fd:.6e}, oracle {g_ref[idx]:.6e}",
+              flush=True)
+        assert abs(g[idx] - fd) <= 1e-2 * abs(fd), (idx, g[idx], fd)
+    s.close()
