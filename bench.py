@@ -33,8 +33,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--n", type=int, default=160, help="FFT grid length per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
-                    help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch")
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint"], default="single",
+                    help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
+                         "adjoint: misfit gradient of the 160^3 voxel potential (6000 steps)")
+    ap.add_argument("--fd-voxels", type=int, default=64, help="adjoint: finite-difference check voxels")
+    ap.add_argument("--fd-delta", type=float, default=1e-2, help="adjoint: FD step in units of E0")
+    ap.add_argument("--adj-steps", type=int, default=6000, help="adjoint: forward steps of the misfit run")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run a plain FP32 copy kernel over this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -59,6 +63,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
 
     prob, V = synth.cfg2(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window
@@ -174,6 +180,109 @@ def bench_batch(args):
         "config": {"workload": "64 instances, per-axis FFT lengths 96..192, isotropic directions, "
                                "k0 in [pi/(8h), pi/(3h)], Gaussian bumps", "cells": cells},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Voxel-potential misfit on the 160^3 grid (128^3 interior): smoothed
+    N(0, 0.1 E0) prior, target intensity of a hidden potential on a 128x128
+    detector plane at z = 39.2 (spacing h), 6000 steps with the DFT window
+    over all of them, sqrt(N) checkpoints.  Reports the backward / forward
+    wall-time ratio and a central finite-difference check on seed-chosen
+    core voxels."""
+    import numpy as np
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+    prob, V0, Vh = synth.cfg5()
+    N = args.adj_steps
+    prob = prob.replace(dft_end=N)
+    n_ck = max(1, math.ceil(math.sqrt(N)))
+    pts = synth.fresnel_plane(128, prob.h[0], 39.2)
+    stream = torch.cuda.current_stream()
+    s = P.Solver(prob, stream=stream)
+    tiles = s.autotune(reps=5)
+    dev = torch.device("cuda:0")
+    # target: total-field intensity of the hidden potential
+    s.set_potential(Vh.astype(np.float32))
+    s.run(N)
+    psi = s.project(pts)
+    r = torch.as_tensor(pts, dtype=torch.float64, device=dev)
+    kh = torch.tensor([math.sin(prob.theta) * math.cos(prob.phi), math.sin(prob.theta) * math.sin(prob.phi),
+                       math.cos(prob.theta)], dtype=torch.float64, device=dev)
+    target = (torch.exp(1j * prob.k0 * (r @ kh)) + psi).abs() ** 2
+    V = V0.astype(np.float32)
+    s.set_potential(V)
+    # first pair allocates the checkpoints
+    s.misfit(N, pts, target, n_ck)
+    s.misfit_gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = s.misfit(N, pts, target, n_ck)
+    t1 = time.perf_counter()
+    g = s.misfit_gradient()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    # plain forward steps for reference
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(N)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain = e0.elapsed_time(e1) / 1e3
+    g = g.cpu().numpy().astype(np.float64)
+    out = {
+        "metric": "adjoint/forward time ratio (misfit gradient vs misfit, sqrt(N) checkpoints)",
+        "value": round(bwd / fwd, 4),
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": N,
+        "warmup": 1,
+        "ms_per_step": round(1e3 * bwd / N, 5),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "voxel potential (smoothed N(0, 0.1 E0) prior) on a 128^3 interior, 160^3 FFT grid, "
+                               f"{N} steps, DFT window all steps, Fresnel plane 128x128 at z=39.2, "
+                               f"{n_ck} checkpoints", "cells": prob.cells},
+        "forward_s": round(fwd, 4),
+        "backward_s": round(bwd, 4),
+        "plain_steps_s": round(plain, 4),
+        "forward_gcells": round(prob.cells * N / fwd / 1e9, 3),
+        "J": J,
+        "tiles": [list(t) for t in tiles],
+    }
+    if args.fd_voxels > 0:
+        E0 = prob.k0 ** 2 / 2
+        delta = args.fd_delta * E0
+        worst = 0.0
+        rows = []
+        gmax = 0.0
+        fds = []
+        vox = synth.fd_voxels(prob, args.fd_voxels, 555)
+        for i, v in enumerate(vox):
+            Vp = V.copy()
+            Vp[v] += delta
+            Vm = V.copy()
+            Vm[v] -= delta
+            s.set_potential(Vp)
+            Jp = s.misfit(N, pts, target, 1)
+            s.set_potential(Vm)
+            Jm = s.misfit(N, pts, target, 1)
+            fds.append((Jp - Jm) / (2 * delta))
+            print(f"fd {i + 1}/{len(vox)} voxel {v}: adjoint {g[v]:.6e} fd {fds[-1]:.6e}", file=sys.stderr, flush=True)
+        fds = np.array(fds)
+        ga = np.array([g[v] for v in vox])
+        gmax = np.abs(fds).max()
+        err = np.abs(ga - fds) / np.maximum(np.abs(fds), 1e-3 * gmax)
+        out["fd_check"] = {"voxels": len(vox), "delta_E0": args.fd_delta, "max_rel_err": float(err.max()),
+                           "median_rel_err": float(np.median(err)),
+                           "criterion": "|g_adj - g_fd| / max(|g_fd|, 1e-3 max|g_fd|)"}
     print(json.dumps(out), flush=True)
 
 

@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "square_barrier", "gaussian_bumps", "smoothed_prior",
-    "cfg1", "cfg2", "cfg3_global", "cfg4_instances", "cfg5", "tiny",
+    "cfg1", "cfg2", "cfg3_global", "cfg4_instances", "cfg5", "tiny", "fresnel_plane", "fd_voxels",
     "paper_u0",
 ]
 
@@ -289,6 +289,29 @@ def cfg5(seed_prior=5, seed_hidden=55, n_fft=160):
                    v_max=vmax, n_steps=6000, dft_begin=0, dft_end=6000,
                    surf_lo=(18,) * 3, surf_hi=(n_fft - 18,) * 3)
     return prob, V0, Vh
+
+
+def fresnel_plane(n_side, spacing, z):
+    """n_side x n_side detector points (physical xyz) at height z, centred on
+    the z axis, lateral spacing `spacing`; row-major in (y, x)."""
+    g = (np.arange(n_side) - (n_side - 1) / 2.0) * spacing
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, float(z))], axis=1)
+
+
+def fd_voxels(prob, count, seed):
+    """`count` distinct seed-chosen voxels (k, j, i) of the TF core."""
+    rng = np.random.default_rng(seed)
+    lo = [prob.tfsf[a][1] for a in range(3)]
+    hi = [prob.tfsf[a][2] for a in range(3)]
+    seen, out = set(), []
+    while len(out) < count:
+        v = (int(rng.integers(lo[2], hi[2] + 1)), int(rng.integers(lo[1], hi[1] + 1)),
+             int(rng.integers(lo[0], hi[0] + 1)))
+        if v not in seen:
+            seen.add(v)
+            out.append(v)
+    return out
 
 
 def tiny(n=(24, 24, 24), P=4, transition=3, theta=0.0, phi=0.0, k_ppw=8,

@@ -164,3 +164,45 @@ def test_gradient_matches_gpu_finite_differences(P, setup):
               flush=True)
         assert abs(g[idx] - fd) <= 1e-2 * abs(fd), (idx, g[idx], fd)
     s.close()
+
+
+def test_full_size_gradient_finite_differences(P):
+    """The 160^3 voxel-potential workload in its benchmark configuration
+    (128x128 detector plane at z = 39.2, sqrt(N) checkpoints), cut to 600
+    steps: central differences of the GPU misfit at the seed-chosen core
+    voxels with the largest gradient.  FD in FP32 has a noise floor near
+    5e-7 in J differences, so the step is large (5e-2 E0) and the bar 1e-2."""
+    import math
+    prob, V0, Vh = synth.cfg5()
+    N = 600
+    prob = prob.replace(dft_end=N)
+    pts = synth.fresnel_plane(128, prob.h[0], 39.2)
+    print(f"adjoint full size: grid {prob.n}, {N} steps, {len(pts)} points", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(Vh.astype(np.float32))
+    s.run(N)
+    psi = s.project(pts).cpu().numpy()
+    target = np.abs(np.exp(1j * prob.k0 * pts[:, 2]) + psi) ** 2
+    V = V0.astype(np.float32)
+    s.set_potential(V)
+    J = s.misfit(N, pts, target, math.ceil(math.sqrt(N)))
+    assert np.isfinite(J) and J > 0
+    g = s.misfit_gradient().cpu().numpy().astype(np.float64)
+    assert np.isfinite(g).all()
+    vox = synth.fd_voxels(prob, 64, 555)
+    vox = sorted(vox, key=lambda v: -abs(g[v]))[:3]
+    E0 = prob.k0 ** 2 / 2
+    delta = 5e-2 * E0
+    for v in vox:
+        Vp = V.copy()
+        Vp[v] += delta
+        Vm = V.copy()
+        Vm[v] -= delta
+        s.set_potential(Vp)
+        Jp = s.misfit(N, pts, target, 1)
+        s.set_potential(Vm)
+        Jm = s.misfit(N, pts, target, 1)
+        fd = (Jp - Jm) / (2 * delta)
+        print(f"  voxel {v}: adjoint {g[v]:.6e}, FD {fd:.6e}", flush=True)
+        assert abs(g[v] - fd) <= 1e-2 * abs(fd)
+    s.close()
