@@ -127,6 +127,76 @@ __device__ __forceinline__ Fields fields(const PassArgs& a) {
     return f;
 }
 
+// Pencil geometry of one tile: element e of pencil pA lives at
+// base + e * estride (segmented pencils: e is a local index, global index g0 + e)
+struct TileGeo {
+    int64_t base, estride;
+    bool valid;
+    int seg, g0, Ng;
+    int px, py;   // (x, y) of the pencil (z pass update)
+    int tx, tq;   // x tile and (other, segment) of the y, z passes
+};
+
+template <int N, int P, int AXIS, bool SEG>
+__device__ __forceinline__ TileGeo tile_geo(const Fields& f, int tile, int pA, bool activeA) {
+    TileGeo g;
+    const int nx = f.nx, ny = f.ny, nz = f.nz;
+    const int C = SEG ? f.seg_core : N;
+    const int H = SEG ? f.seg_halo : 0;
+    const int nseg = SEG ? f.nseg : 1;
+    g.px = 0;
+    g.py = 0;
+    g.tx = 0;
+    g.tq = 0;
+    if constexpr (AXIS == 0) {
+        const int64_t q = (int64_t)tile * P + pA;
+        const int64_t row = q / nseg;
+        g.seg = (int)(q % nseg);
+        g.valid = activeA && q < (int64_t)ny * nz * nseg;
+        g.base = row * nx + (g.seg * C - H);
+        g.estride = 1;
+        g.Ng = nx;
+    } else if constexpr (AXIS == 1) {
+        g.tx = tile % f.ntx;
+        g.tq = tile / f.ntx;
+        const int x = g.tx * P + pA;
+        const int z = g.tq / nseg;
+        g.seg = g.tq % nseg;
+        g.valid = activeA && x < nx;
+        g.estride = nx;
+        g.base = x + (int64_t)nx * ny * z + (int64_t)(g.seg * C - H) * g.estride;
+        g.Ng = ny;
+    } else {
+        g.tx = tile % f.ntx;
+        g.tq = tile / f.ntx;
+        g.px = g.tx * P + pA;
+        g.py = g.tq / nseg;
+        g.seg = g.tq % nseg;
+        g.valid = activeA && g.px < nx;
+        g.estride = (int64_t)nx * ny;
+        g.base = g.px + (int64_t)nx * g.py + (int64_t)(g.seg * C - H) * g.estride;
+        g.Ng = nz;
+    }
+    g.g0 = g.seg * C - H;
+    return g;
+}
+
+// raw pencil values of one tile (zero outside the grid and for idle lanes)
+template <int N, int N1, int N2, bool SEG>
+__device__ __forceinline__ void load_tile(GMEM const float2* __restrict__ psi, const TileGeo& g, int n2,
+                                          float2 (&x)[N1]) {
+    unroll<N1>([&](auto i) {
+        constexpr int n1 = decltype(i)::value;
+        const int e = n2 + N2 * n1;
+        const bool in = g.valid && (e < N) && (!SEG || (g.g0 + e >= 0 && g.g0 + e < g.Ng));
+        float2 val = make_float2(0.f, 0.f);
+        if (in) val = psi[g.base + (int64_t)e * g.estride];
+        x[n1] = val;
+    });
+}
+
+// One workgroup per tile of P pencils; MULTI launches find their instance
+// from the prefix table of tiles.
 template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
                                                                        const PassArgs* __restrict__ descs,
@@ -141,9 +211,13 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     __shared__ float s_kk[N];
     __shared__ float2 s_dl[N], s_dh[N];
 
+    const int t = threadIdx.x;
+    const bool activeA = t < P * N2;
+    const int pA = AXIS == 0 ? t / N2 : t % P;
+    const int n2 = AXIS == 0 ? t % N2 : t / P;
+
     // instance of this workgroup (uniform), its tile, its step: the base
     // counter plus this launch's offset in its group of steps
-    // (MULTI == false: one instance, described by the `single` argument)
     Fields f;
     int tile;
     if constexpr (!MULTI) {
@@ -158,280 +232,236 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     }
     const int64_t nstep = f.ctr[0] + koff;
     if (nstep >= f.ctr[1]) return;  // whole workgroup, before any barrier
-
-    const int nx = f.nx, ny = f.ny, nz = f.nz;
+    const bool surf = f.dft_tab[nstep] != 0;
     GMEM const float2* __restrict__ psi = (nstep & 1) ? f.buf1 : f.buf0;
     GMEM float2* __restrict__ psi_old = (nstep & 1) ? f.buf0 : f.buf1;
-    GMEM float2* __restrict__ Lbuf = f.L;
-    GMEM const float* __restrict__ v2 = f.v2;
-    const bool surf = f.dft_tab[nstep] != 0;
-    GMEM const float* __restrict__ t_kk = f.kk;
-    GMEM const float2* __restrict__ t_tw = f.tw;
-    GMEM const float* __restrict__ t_gam = f.gam;
-    GMEM const float2* __restrict__ t_zt = f.zt;
-    GMEM const float2* __restrict__ t_dz = f.dz;
-    GMEM const float2* __restrict__ t_dlo = f.dlo;
-    GMEM const float2* __restrict__ t_dhi = f.dhi;
-    const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
-    const int seg_plane0 = f.seg_plane0, seg_plane1 = f.seg_plane1;
-    const int ntx = f.ntx;
-    // segmented pencils: element e of segment `seg` is global index
-    // seg * C - H + e, weighted by wloc[e]; plain pencils: C = N, H = 0
-    const int C = SEG ? f.seg_core : N;
-    const int H = SEG ? f.seg_halo : 0;
-    const int nseg = SEG ? f.nseg : 1;
-    GMEM const float* __restrict__ wloc = f.wloc;
-
-    const int t = threadIdx.x;
-    const bool activeA = t < P * N2;
-    const int pA = AXIS == 0 ? t / N2 : t % P;
-    const int n2 = AXIS == 0 ? t % N2 : t / P;
 
     // tables to LDS (issued before the field loads)
     for (int i = t; i < N; i += NT) {
-        s_tw[i] = t_tw[i];
-        s_kk[i] = t_kk[i];
+        s_tw[i] = f.tw[i];
+        s_kk[i] = f.kk[i];
         if (surf) {
-            s_dl[i] = t_dlo[i];
-            s_dh[i] = t_dhi[i];
+            s_dl[i] = f.dlo[i];
+            s_dh[i] = f.dhi[i];
         }
     }
 
-    const int Ng = AXIS == 0 ? nx : AXIS == 1 ? ny : nz;
-    const int tx = AXIS == 0 ? 0 : tile % ntx;      // x tile (y, z passes)
-    const int tq = AXIS == 0 ? 0 : tile / ntx;      // (other, segment) of the y, z passes
+    {
+        const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
+        float2 raw[N1];
+        load_tile<N, N1, N2, SEG>(psi, geo, n2, raw);
 
-    // pencil geometry: element e of pencil pA lives at base + e * estride
-    int64_t base = 0, estride = 1;
-    bool valid;
-    int seg = 0;
-    int px = 0, py = 0;  // (x, y) of the pencil for the z-pass update
-    if constexpr (AXIS == 0) {
-        const int64_t q = (int64_t)tile * P + pA;
-        const int64_t row = q / nseg;
-        seg = (int)(q % nseg);
-        valid = activeA && q < (int64_t)ny * nz * nseg;
-        base = row * nx + (seg * C - H);
-        estride = 1;
-    } else if constexpr (AXIS == 1) {
-        const int x = tx * P + pA;
-        const int z = tq / nseg;
-        seg = tq % nseg;
-        valid = activeA && x < nx;
-        estride = nx;
-        base = x + (int64_t)nx * ny * z + (int64_t)(seg * C - H) * estride;
-    } else {
-        px = tx * P + pA;
-        py = tq / nseg;
-        seg = tq % nseg;
-        valid = activeA && px < nx;
-        estride = (int64_t)nx * ny;
-        base = px + (int64_t)nx * py + (int64_t)(seg * C - H) * estride;
-    }
-    const int g0 = seg * C - H;  // global index of element 0
-
-    float2 v[N1];
-    float2 keep[AXIS == 2 ? N1 : 1];
-    unroll<N1>([&](auto i) {
-        constexpr int n1 = decltype(i)::value;
-        const int e = n2 + N2 * n1;
-        const bool in = valid && (!SEG || (g0 + e >= 0 && g0 + e < Ng));
-        float2 x = make_float2(0.f, 0.f);
-        if (in) x = psi[base + (int64_t)e * estride];
-        if constexpr (AXIS == 2) keep[n1] = x;
-        if constexpr (SEG) x = cscale(x, wloc[e]);
-        v[n1] = x;
-    });
-    // plane values: read directly by the thread that owns the element
-    // (planes lie in a core, where the halo weight is 1)
-    float2 plo = make_float2(0.f, 0.f), phi = plo;
-    if (!ADJ && surf && valid) {
-        if (n2 == plane_lo % N2 && seg == seg_plane0) plo = psi[base + (int64_t)plane_lo * estride];
-        if (n2 == plane_hi % N2 && seg == seg_plane1) phi = psi[base + (int64_t)plane_hi * estride];
-    }
-    __syncthreads();
-
-    // spectral normal derivative on the two planes: partial dot products
-    float2 dlo = make_float2(0.f, 0.f), dhi = dlo;
-    if (!ADJ && surf) {
+        GMEM const float* __restrict__ wloc = f.wloc;
+        const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
+        float2 v[N1];
+        float2 plo = make_float2(0.f, 0.f), phi = plo;
         unroll<N1>([&](auto i) {
             constexpr int n1 = decltype(i)::value;
             const int e = n2 + N2 * n1;
-            if (e < N) {
-                dlo = cadd(dlo, cmul(s_dl[e], v[n1]));
-                dhi = cadd(dhi, cmul(s_dh[e], v[n1]));
-            }
+            float2 x = raw[n1];
+            if constexpr (SEG) x = cscale(x, e < N ? wloc[e] : 0.f);
+            v[n1] = x;
         });
-    }
-
-    // ---- forward: stage A (N1-point DFTs), twiddle, exchange ----
-    dft<N1, -1>(v);
-    if (activeA) {
-        unroll<N1>([&](auto i) {
-            constexpr int k1 = decltype(i)::value;
-            float2 x = v[k1];
-            if constexpr (k1 != 0) x = cmul(x, s_tw[n2 * k1]);
-            ex[pA * STRIDE + k1 * ROW + n2] = x;
-        });
-    }
-    __syncthreads();
-
-    // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
-    if (t < P * N1) {
-        const int pB = AXIS == 0 ? t / N1 : t % P;
-        const int k1 = AXIS == 0 ? t % N1 : t / P;
-        float2 u[N2];
-        unroll<N2>([&](auto i) { u[decltype(i)::value] = ex[pB * STRIDE + k1 * ROW + decltype(i)::value]; });
-        dft<N2, -1>(u);
-        unroll<N2>([&](auto i) {
-            constexpr int k2 = decltype(i)::value;
-            u[k2] = cscale(u[k2], s_kk[k1 + N1 * k2]);
-        });
-        dft<N2, 1>(u);
-        unroll<N2>([&](auto i) {
-            constexpr int nn = decltype(i)::value;
-            float2 x = u[nn];
-            if constexpr (nn != 0) x = cmulc(x, s_tw[nn * k1]);
-            ex[pB * STRIDE + k1 * ROW + nn] = x;
-        });
-    }
-    __syncthreads();
-
-    // ---- inverse: stage A ----
-    if (activeA) {
-        unroll<N1>([&](auto i) { v[decltype(i)::value] = ex[pA * STRIDE + decltype(i)::value * ROW + n2]; });
-    }
-    dft<N1, 1>(v);
-
-    // ---- adjoint steps: the surface terms injected along this pencil,
-    // c (plane values on the planes + derivative rows times the derivative
-    // parts), c = i w_m from the step table ----
-    float2 cinj = make_float2(0.f, 0.f);
-    float2 hpl = cinj, hdl = cinj, hph = cinj, hdh = cinj;
-    if constexpr (ADJ) {
-        if (surf && valid) {
-            const double2 cw = f.w_tab[nstep];
-            cinj = make_float2((float)cw.x, (float)cw.y);
-            int64_t pt;
-            if constexpr (AXIS == 0) pt = (int64_t)tile * P + pA;
-            else pt = tx * P + pA + (int64_t)nx * tq;
-            hpl = cmul(cinj, f.inj_lo_p[pt]);
-            hdl = cmul(cinj, f.inj_lo_d[pt]);
-            hph = cmul(cinj, f.inj_hi_p[pt]);
-            hdh = cmul(cinj, f.inj_hi_d[pt]);
+        // plane values: read directly by the thread that owns the element
+        // (planes lie in a core, where the halo weight is 1)
+        if (!ADJ && surf && geo.valid) {
+            if (n2 == plane_lo % N2 && geo.seg == f.seg_plane0) plo = psi[geo.base + (int64_t)plane_lo * geo.estride];
+            if (n2 == plane_hi % N2 && geo.seg == f.seg_plane1) phi = psi[geo.base + (int64_t)plane_hi * geo.estride];
         }
-        if (surf) {
+        __syncthreads();  // tables staged
+
+        // spectral normal derivative on the two planes: partial dot products
+        float2 dlo = make_float2(0.f, 0.f), dhi = dlo;
+        if (!ADJ && surf) {
             unroll<N1>([&](auto i) {
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
                 if (e < N) {
-                    float2 x = cadd(cmul(s_dl[e], hdl), cmul(s_dh[e], hdh));
-                    if (e == plane_lo) x = cadd(x, hpl);
-                    if (e == plane_hi) x = cadd(x, hph);
-                    v[n1] = cadd(v[n1], x);
+                    dlo = cadd(dlo, cmul(s_dl[e], v[n1]));
+                    dhi = cadd(dhi, cmul(s_dh[e], v[n1]));
                 }
             });
         }
-    }
 
-    // ---- epilogue (only core elements are written) ----
-    if (valid) {
-        if constexpr (AXIS == 0) {
-            unroll<N1>([&](auto i) {
-                constexpr int n1 = decltype(i)::value;
-                const int e = n2 + N2 * n1;
-                if (!SEG || (e >= H && e < H + C)) Lbuf[base + e] = v[n1];
-            });
-        } else if constexpr (AXIS == 1) {
-            unroll<N1>([&](auto i) {
-                constexpr int n1 = decltype(i)::value;
-                const int e = n2 + N2 * n1;
-                if (!SEG || (e >= H && e < H + C)) {
-                    const int64_t ad = base + (int64_t)e * estride;
-                    Lbuf[ad] = cadd(Lbuf[ad], v[n1]);
-                }
-            });
-        } else {
-            const float2 Zx = f.zt_x[px], Dx = f.dz_x[px];
-            const float2 Zy = f.zt_y[py], Dy = f.dz_y[py];
-            const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
-            const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
-            const float gxy = f.gam_x[px] * f.gam_y[py];
-            float2 sigma = make_float2(0.f, 0.f);
-            if constexpr (!ADJ) sigma = f.sigma_tab[nstep];
-            GMEM const float2* __restrict__ fwd = nullptr;
-            GMEM float2* __restrict__ stash = nullptr;
-            if constexpr (ADJ) fwd = gmem(f.fwd_tab[nstep]);
-            else if (f.stash_tab) stash = gmem(f.stash_tab[nstep]);
-            unroll<N1>([&](auto i) {
-                constexpr int n1 = decltype(i)::value;
-                const int e = n2 + N2 * n1;
-                if (!SEG || (e >= H && e < H + C)) {
-                    const int z = g0 + e;
-                    const int64_t ad = base + (int64_t)e * estride;
-                    const float2 Lt = cadd(Lbuf[ad], v[n1]);
-                    const float2 po = psi_old[ad];
-                    const float vv = v2[ad];
-                    float2 q = cadd(Lt, cscale(keep[n1], vv));
-                    if constexpr (!ADJ) {
-                        const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
-                        q = cadd(q, cmul(sigma, s));
-                    }
-                    const float g = gxy * t_gam[z];
-                    // psi^{n+1} = Gamma (psi^{n-1} - i q)
-                    const float2 nv = make_float2(g * (po.x + q.y), g * (po.y - q.x));
-                    psi_old[ad] = nv;
-                    if (stash) stash[ad] = nv;
-                    if constexpr (ADJ) {
-                        // Im(chi^m psi^{m-1})
-                        const float2 fv = fwd[ad];
-                        f.grad[ad] += nv.x * fv.y + nv.y * fv.x;
-                    }
-                }
-            });
-        }
-    }
-
-    // ---- surface DFT: reduce the per-thread partials, accumulate in FP64 ----
-    if (!ADJ && surf) {
-        __syncthreads();  // every thread has read its exchange slots
+        // ---- forward: stage A (N1-point DFTs), twiddle, exchange ----
+        dft<N1, -1>(v);
         if (activeA) {
-            float2* r = &ex[pA * STRIDE + n2 * 4];
-            r[0] = plo;
-            r[1] = phi;
-            r[2] = dlo;
-            r[3] = dhi;
+            unroll<N1>([&](auto i) {
+                constexpr int k1 = decltype(i)::value;
+                float2 x = v[k1];
+                if constexpr (k1 != 0) x = cmul(x, s_tw[n2 * k1]);
+                ex[pA * STRIDE + k1 * ROW + n2] = x;
+            });
         }
         __syncthreads();
-        if (t < P * 4) {
-            const int p = t >> 2;
-            const int q = t & 3;
-            const int side = q & 1;
-            const int segp = side ? seg_plane1 : seg_plane0;
-            int64_t pt = -1;
-            if constexpr (AXIS == 0) {
-                const int64_t qq = (int64_t)tile * P + p;
-                if (qq < (int64_t)ny * nz * nseg && (int)(qq % nseg) == segp) pt = qq / nseg;
-            } else {
-                const int x = tx * P + p;
-                if (x < nx && tq % nseg == segp) pt = x + (int64_t)nx * (tq / nseg);
+
+        // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
+        if (t < P * N1) {
+            const int pB = AXIS == 0 ? t / N1 : t % P;
+            const int k1 = AXIS == 0 ? t % N1 : t / P;
+            float2 u[N2];
+            unroll<N2>([&](auto i) { u[decltype(i)::value] = ex[pB * STRIDE + k1 * ROW + decltype(i)::value]; });
+            dft<N2, -1>(u);
+            unroll<N2>([&](auto i) {
+                constexpr int k2 = decltype(i)::value;
+                u[k2] = cscale(u[k2], s_kk[k1 + N1 * k2]);
+            });
+            dft<N2, 1>(u);
+            unroll<N2>([&](auto i) {
+                constexpr int nn = decltype(i)::value;
+                float2 x = u[nn];
+                if constexpr (nn != 0) x = cmulc(x, s_tw[nn * k1]);
+                ex[pB * STRIDE + k1 * ROW + nn] = x;
+            });
+        }
+        __syncthreads();
+
+        // ---- inverse: stage A ----
+        if (activeA) {
+            unroll<N1>([&](auto i) { v[decltype(i)::value] = ex[pA * STRIDE + decltype(i)::value * ROW + n2]; });
+        }
+        dft<N1, 1>(v);
+
+        // surface point of this pencil on the planes normal to the axis
+        int64_t pt;
+        if constexpr (AXIS == 0) pt = (int64_t)tile * P + pA;
+        else pt = geo.tx * P + pA + (int64_t)f.nx * geo.tq;
+
+        // ---- adjoint steps: the surface terms injected along this pencil,
+        // c (plane values on the planes + derivative rows times the derivative
+        // parts), c = i w_m from the step table ----
+        if constexpr (ADJ) {
+            if (surf) {
+                float2 hpl = make_float2(0.f, 0.f), hdl = hpl, hph = hpl, hdh = hpl;
+                if (geo.valid) {
+                    const double2 cw = f.w_tab[nstep];
+                    const float2 cinj = make_float2((float)cw.x, (float)cw.y);
+                    hpl = cmul(cinj, f.inj_lo_p[pt]);
+                    hdl = cmul(cinj, f.inj_lo_d[pt]);
+                    hph = cmul(cinj, f.inj_hi_p[pt]);
+                    hdh = cmul(cinj, f.inj_hi_d[pt]);
+                }
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    if (e < N) {
+                        float2 x = cadd(cmul(s_dl[e], hdl), cmul(s_dh[e], hdh));
+                        if (e == plane_lo) x = cadd(x, hpl);
+                        if (e == plane_hi) x = cadd(x, hph);
+                        v[n1] = cadd(v[n1], x);
+                    }
+                });
             }
-            if (pt >= 0) {
-                float2 s = make_float2(0.f, 0.f);
-                for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
-                const double re = (double)s.x, im = (double)s.y;
-                const double2 w = f.w_tab[nstep];
-                const double zr = w.x * re - w.y * im;
-                const double zi = w.x * im + w.y * re;
-                const int field = (q >> 1) * 2;
-                const int64_t points = f.points;
-                GMEM double2* __restrict__ S = f.acc + (int64_t)(side * 4 + field) * points + pt;
-                GMEM double2* __restrict__ Cc = f.acc + (int64_t)(side * 4 + field + 1) * points + pt;
-                double2 sv = *S, cv = *Cc;
-                neumaier(sv.x, cv.x, zr);
-                neumaier(sv.y, cv.y, zi);
-                *S = sv;
-                *Cc = cv;
+        }
+
+        // ---- epilogue (only core elements are written) ----
+        const int C = SEG ? f.seg_core : N;
+        const int H = SEG ? f.seg_halo : 0;
+        GMEM float2* __restrict__ Lbuf = f.L;
+        if (geo.valid) {
+            if constexpr (AXIS == 0) {
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    if (e < N && (!SEG || (e >= H && e < H + C))) Lbuf[geo.base + e] = v[n1];
+                });
+            } else if constexpr (AXIS == 1) {
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    if (e < N && (!SEG || (e >= H && e < H + C))) {
+                        const int64_t ad = geo.base + (int64_t)e * geo.estride;
+                        Lbuf[ad] = cadd(Lbuf[ad], v[n1]);
+                    }
+                });
+            } else {
+                GMEM const float* __restrict__ v2 = f.v2;
+                GMEM const float* __restrict__ t_gam = f.gam;
+                GMEM const float2* __restrict__ t_zt = f.zt;
+                GMEM const float2* __restrict__ t_dz = f.dz;
+                const int px = geo.px, py = geo.py;
+                const float2 Zx = f.zt_x[px], Dx = f.dz_x[px];
+                const float2 Zy = f.zt_y[py], Dy = f.dz_y[py];
+                const float2 SA = cadd(cmul(Dx, Zy), cmul(Zx, Dy));  // source terms of axes x, y
+                const float2 SB = cmul(Zx, Zy);                      // multiplies the z-axis term
+                const float gxy = f.gam_x[px] * f.gam_y[py];
+                float2 sigma = make_float2(0.f, 0.f);
+                if constexpr (!ADJ) sigma = f.sigma_tab[nstep];
+                GMEM const float2* __restrict__ fwd = nullptr;
+                GMEM float2* __restrict__ stash = nullptr;
+                if constexpr (ADJ) fwd = gmem(f.fwd_tab[nstep]);
+                else if (f.stash_tab) stash = gmem(f.stash_tab[nstep]);
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    if (e < N && (!SEG || (e >= H && e < H + C))) {
+                        const int z = geo.g0 + e;
+                        const int64_t ad = geo.base + (int64_t)e * geo.estride;
+                        const float2 Lt = cadd(Lbuf[ad], v[n1]);
+                        const float2 po = psi_old[ad];
+                        const float vv = v2[ad];
+                        float2 q = cadd(Lt, cscale(raw[n1], vv));
+                        if constexpr (!ADJ) {
+                            const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
+                            q = cadd(q, cmul(sigma, s));
+                        }
+                        const float g = gxy * t_gam[z];
+                        // psi^{n+1} = Gamma (psi^{n-1} - i q)
+                        const float2 nv = make_float2(g * (po.x + q.y), g * (po.y - q.x));
+                        psi_old[ad] = nv;
+                        if (stash) stash[ad] = nv;
+                        if constexpr (ADJ) {
+                            // Im(chi^m psi^{m-1})
+                            const float2 fv = fwd[ad];
+                            f.grad[ad] += nv.x * fv.y + nv.y * fv.x;
+                        }
+                    }
+                });
+            }
+        }
+
+        // ---- surface DFT: reduce the per-thread partials, accumulate in FP64 ----
+        if (!ADJ && surf) {
+            __syncthreads();  // every thread has read its exchange slots
+            if (activeA) {
+                float2* r = &ex[pA * STRIDE + n2 * 4];
+                r[0] = plo;
+                r[1] = phi;
+                r[2] = dlo;
+                r[3] = dhi;
+            }
+            __syncthreads();
+            if (t < P * 4) {
+                const int p = t >> 2;
+                const int q = t & 3;
+                const int side = q & 1;
+                const int segp = side ? f.seg_plane1 : f.seg_plane0;
+                const int nseg = SEG ? f.nseg : 1;
+                int64_t spt = -1;
+                if constexpr (AXIS == 0) {
+                    const int64_t qq = (int64_t)tile * P + p;
+                    if (qq < (int64_t)f.ny * f.nz * nseg && (int)(qq % nseg) == segp) spt = qq / nseg;
+                } else {
+                    const int x = geo.tx * P + p;
+                    if (x < f.nx && geo.tq % nseg == segp) spt = x + (int64_t)f.nx * (geo.tq / nseg);
+                }
+                if (spt >= 0) {
+                    float2 s = make_float2(0.f, 0.f);
+                    for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
+                    const double re = (double)s.x, im = (double)s.y;
+                    const double2 w = f.w_tab[nstep];
+                    const double zr = w.x * re - w.y * im;
+                    const double zi = w.x * im + w.y * re;
+                    const int field = (q >> 1) * 2;
+                    const int64_t points = f.points;
+                    GMEM double2* __restrict__ S = f.acc + (int64_t)(side * 4 + field) * points + spt;
+                    GMEM double2* __restrict__ Cc = f.acc + (int64_t)(side * 4 + field + 1) * points + spt;
+                    double2 sv = *S, cv = *Cc;
+                    neumaier(sv.x, cv.x, zr);
+                    neumaier(sv.y, cv.y, zi);
+                    *S = sv;
+                    *Cc = cv;
+                }
             }
         }
     }
@@ -476,49 +506,34 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);
 
+template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ>
+hipError_t launch_kernel(const PassArgs& single, const PassArgs* descs, const int* off, int ninst, int tiles,
+                         int koff, hipStream_t stream) {
+    constexpr int threads = P * (N1 > N2 ? N1 : N2);
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, AXIS, SEG, MULTI, ADJ>), dim3(tiles), dim3(threads), 0, stream, single,
+                       descs, off, ninst, koff);
+    return hipGetLastError();
+}
+
 template <int N, int N1, int N2, int P, bool SEG>
 static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                int tiles, int koff, hipStream_t stream) {
-    constexpr int threads = P * (N1 > N2 ? N1 : N2);
-    if (tiles <= 0) return hipSuccess;
     if (ninst == 0) {
-        if (axis == 0)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
-        else if (axis == 1)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
-        else
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, false, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
-    } else {
-        if (axis == 0)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
-        else if (axis == 1)
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
-        else
-            hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, SEG, true, false>), dim3(tiles), dim3(threads), 0, stream, single,
-                               descs, off, ninst, koff);
+        if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        return launch_kernel<N, N1, N2, P, 2, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
     }
-    return hipGetLastError();
+    if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    return launch_kernel<N, N1, N2, P, 2, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
 }
 
 template <int N, int N1, int N2, int P>
 static hipError_t launch_adjoint_shape(int axis, const PassArgs& a, int koff, hipStream_t stream) {
-    constexpr int threads = P * (N1 > N2 ? N1 : N2);
-    if (a.tiles <= 0) return hipSuccess;
-    if (axis == 0)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 0, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
-                           a, nullptr, nullptr, 0, koff);
-    else if (axis == 1)
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 1, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
-                           a, nullptr, nullptr, 0, koff);
-    else
-        hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, 2, false, false, true>), dim3(a.tiles), dim3(threads), 0, stream,
-                           a, nullptr, nullptr, 0, koff);
-    return hipGetLastError();
+    if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
+    if (axis == 1) return launch_kernel<N, N1, N2, P, 1, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
+    return launch_kernel<N, N1, N2, P, 2, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
 }
 
 using AdjFn = hipError_t (*)(int axis, const PassArgs& a, int koff, hipStream_t stream);
