@@ -25,6 +25,40 @@ HBM_PEAK_GBS = 8000.0
 PASS_BYTES = {"x": 16, "y": 24, "z": 36}
 STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 
+# HBM traffic per launch of the pass kernels on the 160^3 workload, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this script (KiB
+# per dispatch, scaled by what the same counters read for a plain copy of
+# 512 MiB: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
+# sources whose SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported
+# as null.  Key: (N, N1, N2, pencils per workgroup, axis).
+TRAFFIC_SRC_SHA256 = "f69c887915b8d5de2afef791fdbef1d652ec5606d22d1456f0548c31097855cb"
+TRAFFIC_KIB = {  # (fetch, write) KiB per launch, surface DFT active
+    (160, 10, 16, 16, 0): (35380, 35200), (160, 10, 16, 16, 1): (67407, 35200), (160, 10, 16, 16, 2): (131580, 35200),
+    (160, 10, 16, 32, 0): (35389, 35200), (160, 10, 16, 32, 1): (67397, 35200), (160, 10, 16, 32, 2): (115598, 35200),
+    (160, 10, 16, 8, 0): (35385, 35200), (160, 10, 16, 8, 1): (131424, 35200), (160, 10, 16, 8, 2): (259577, 35200),
+    (160, 16, 10, 16, 0): (35400, 35200), (160, 16, 10, 16, 1): (67423, 35200), (160, 16, 10, 16, 2): (131691, 35200),
+}
+KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
+                  "paper_2403_04053_amd/csrc/internal.hpp")
+
+
+def kernel_src_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tile, axis):
+    """(fetch + write) bytes per launch, or None when not measured for these sources."""
+    if TRAFFIC_SRC_SHA256 is None or kernel_src_sha256() != TRAFFIC_SRC_SHA256:
+        return None
+    kib = TRAFFIC_KIB.get((*tile, axis))
+    return None if kib is None else 1024 * (kib[0] + kib[1])
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -124,7 +158,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(tuple(tiles["xyz".index(dom)]), "xyz".index(dom)),
             "bytes_per_cell": PASS_BYTES[dom],
             "pass_ms": {k: round(v, 5) for k, v in avg.items()},
             "tiles": {k: list(tiles[i]) for i, k in enumerate("xyz")},

@@ -131,7 +131,10 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host
 /* Pick, for each axis pass, the fastest compiled tile shape (FFT factor
  * order N1 x N2 and pencils per workgroup) by timing `reps` launches of every
  * candidate on scratch buffers of the solver's size; the solver's state is
- * not touched.  Synchronises.  ENOMEM if the scratch cannot be allocated. */
+ * not touched.  Candidates are tried in compiled order and a later one
+ * replaces the current choice only when it is at least 3 % faster, so timing
+ * noise does not flip the choice between runs.  Synchronises.  ENOMEM if the
+ * scratch cannot be allocated. */
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
 
 /* Tile shape used by the pass along axis (0, 1, 2): info_host[4] =
@@ -153,6 +156,18 @@ pstd_status pstd_step_index(const pstd_solver* s, int64_t* step_out_host);
 
 /* Copy psi^step (level 0) or psi^{step-1} (level 1) to a complex64 array. */
 pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n_cells);
+
+/* Checkpoint / resume of a solve: pstd_state_size gives the bytes of a
+ * device buffer that holds (psi^{n-1}, psi^n), the FP64 surface-DFT sums with
+ * their compensation terms, the step index and the incident-phasor sum.
+ * pstd_save_state fills such a buffer (caller-owned device memory);
+ * pstd_load_state restores it into a solver of the same grid, after which
+ * pstd_run continues exactly as the saved solver would (bit-identical
+ * results).  Both synchronise.  EINVAL: buffer too small, or (load) a buffer
+ * that holds no state of this grid.  ESTATE: load into a batch instance. */
+pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out_host);
+pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes);
+pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes);
 
 /* Number of complex128 values pstd_get_surface_phasors writes:
  * 2 * (2 Ny Nz + 2 Nx Nz + 2 Nx Ny). */

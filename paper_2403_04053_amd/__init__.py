@@ -15,7 +15,7 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_far_field", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -26,6 +26,12 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpstd.so"
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2403_04053_amd/build.py`")
+
+# torch ships its own HIP runtime under the same soname as the system one
+# libpstd.so links against; whichever is loaded first serves the process.
+# Loading torch first makes the library and torch share torch's runtime (two
+# runtimes in one process do not see the same devices).
+import torch as _torch  # noqa: E402,F401
 
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -117,6 +123,9 @@ _SIGS = {
     "pstd_far_field": [_vp, _vp, _i64, _vp],
     "pstd_misfit_forward": [_vp, _i64, _vp, _i64, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pstd_misfit_backward": [_vp, _vp, _i64],
+    "pstd_state_size": [_vp, ctypes.POINTER(_i64)],
+    "pstd_save_state": [_vp, _vp, _i64],
+    "pstd_load_state": [_vp, _vp, _i64],
     "pstd_destroy": [_vp],
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
@@ -246,6 +255,20 @@ def pstd_far_field(solver, dir_dev, n_dir, out_dev):
     _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
 
 
+def pstd_state_size(solver):
+    out = _i64()
+    _check(lib.pstd_state_size(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
+def pstd_save_state(solver, buf_dev, nbytes):
+    _check(lib.pstd_save_state(solver, _ptr(buf_dev), int(nbytes)), solver)
+
+
+def pstd_load_state(solver, buf_dev, nbytes):
+    _check(lib.pstd_load_state(solver, _ptr(buf_dev), int(nbytes)), solver)
+
+
 def pstd_misfit_forward(solver, n_steps, obs_dev, n_obs, target_dev, n_checkpoints):
     J = ctypes.c_double()
     _check(lib.pstd_misfit_forward(solver, int(n_steps), _ptr(obs_dev), int(n_obs), _ptr(target_dev),
@@ -338,6 +361,8 @@ class Solver:
         self.n = tuple(self.problem.n[a] for a in range(3))
         self.cells = self.n[0] * self.n[1] * self.n[2]
         self.stream = stream
+        if self.device.type == "cuda":
+            torch.cuda.init()  # torch's runtime first: it owns the buffers passed in
         self.handle = pstd_create(self.problem, stream)
 
     def close(self):
@@ -422,6 +447,16 @@ class Solver:
         return out
 
 
+    def save_state(self):
+        """The solver state as a uint8 CUDA tensor (pstd_save_state)."""
+        n = pstd_state_size(self.handle)
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        pstd_save_state(self.handle, buf, n)
+        return buf
+
+    def load_state(self, buf):
+        pstd_load_state(self.handle, buf, buf.numel() * buf.element_size())
+
     def misfit(self, n_steps, points, target, n_checkpoints=None):
         """J of the detector-plane intensity misfit (pstd_misfit_forward)."""
         import math
@@ -494,8 +529,10 @@ class Batch:
     """Owning wrapper around a pstd_batch handle."""
 
     def __init__(self, problems, stream=None):
+        import torch
         self.problems = [p if isinstance(p, pstd_problem) else problem_from(p) for p in problems]
         self.stream = stream
+        torch.cuda.init()  # torch's runtime first: it owns the buffers passed in
         self.handle = pstd_batch_create(self.problems, stream)
         self.count = len(self.problems)
 

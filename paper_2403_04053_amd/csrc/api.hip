@@ -509,7 +509,7 @@ pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
                 st = hip_fail(s, e, "autotune");
                 break;
             }
-            if (ms < best) {
+            if (ms < 0.97f * best) {  // a later shape must win clearly: stable choices
                 best = ms;
                 best_id = ids[k];
             }
@@ -738,6 +738,84 @@ pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n
     if (n_cells != s->cells) return fail(s, PSTD_EINVAL, "n_cells does not match the grid");
     const float2* src = s->buf[(s->step + (level == 0 ? 0 : 1)) & 1];
     HIP_TRY(s, hipMemcpyAsync(psi_dev, src, n_cells * sizeof(float2), hipMemcpyDeviceToDevice, s->stream));
+    return PSTD_OK;
+}
+
+// serialized state: header, psi^{n-1}, psi^n, the surface DFT sums (value
+// and compensation) of the three axes
+struct StateHeader {
+    int64_t magic;
+    int64_t n[3];
+    int64_t step;
+    double inc_sum;
+    int64_t bytes;
+    int64_t pad;
+};
+constexpr int64_t kStateMagic = 0x3176534454535050LL;  // "PPSTDSv1"
+
+static int64_t state_bytes(const pstd_solver* s) {
+    int64_t b = (int64_t)sizeof(StateHeader) + 2 * s->cells * (int64_t)sizeof(float2);
+    for (int a = 0; a < 3; ++a) b += 8 * s->points[a] * (int64_t)sizeof(double2);
+    return b;
+}
+
+pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out) {
+    if (!s || !bytes_out) return PSTD_EINVAL;
+    *bytes_out = state_bytes(s);
+    return PSTD_OK;
+}
+
+pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
+    if (!s || !dev_buf) return PSTD_EINVAL;
+    const int64_t need = state_bytes(s);
+    if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
+    StateHeader h{kStateMagic, {s->prob.n[0], s->prob.n[1], s->prob.n[2]}, s->step, s->inc_sum, need, 0};
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    char* d = (char*)dev_buf;
+    HIP_TRY(s, hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice));
+    d += sizeof(h);
+    const size_t fb = s->cells * sizeof(float2);
+    HIP_TRY(s, hipMemcpyAsync(d, s->buf[(s->step + 1) & 1], fb, hipMemcpyDeviceToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(d + fb, s->buf[s->step & 1], fb, hipMemcpyDeviceToDevice, s->stream));
+    d += 2 * fb;
+    for (int a = 0; a < 3; ++a) {
+        const size_t ab = 8 * s->points[a] * sizeof(double2);
+        HIP_TRY(s, hipMemcpyAsync(d, s->acc[a], ab, hipMemcpyDeviceToDevice, s->stream));
+        d += ab;
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return PSTD_OK;
+}
+
+pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) {
+    if (!s || !dev_buf) return PSTD_EINVAL;
+    if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
+    const int64_t need = state_bytes(s);
+    if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
+    StateHeader h{};
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    HIP_TRY(s, hipMemcpy(&h, dev_buf, sizeof(h), hipMemcpyDeviceToHost));
+    if (h.magic != kStateMagic || h.bytes != need || h.n[0] != s->prob.n[0] || h.n[1] != s->prob.n[1] ||
+        h.n[2] != s->prob.n[2] || h.step < 0 || !(h.inc_sum >= 0))
+        return fail(s, PSTD_EINVAL, "buffer does not hold a saved state of this grid");
+    adjoint_invalidate(s);
+    pstd_status st = solver_ensure_tables(s, h.step + 1);
+    if (st) return st;
+    const char* d = (const char*)dev_buf + sizeof(h);
+    const size_t fb = s->cells * sizeof(float2);
+    HIP_TRY(s, hipMemcpyAsync(s->buf[(h.step + 1) & 1], d, fb, hipMemcpyDeviceToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->buf[h.step & 1], d + fb, fb, hipMemcpyDeviceToDevice, s->stream));
+    d += 2 * fb;
+    for (int a = 0; a < 3; ++a) {
+        const size_t ab = 8 * s->points[a] * sizeof(double2);
+        HIP_TRY(s, hipMemcpyAsync(s->acc[a], d, ab, hipMemcpyDeviceToDevice, s->stream));
+        d += ab;
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const int64_t c[2] = {h.step, std::numeric_limits<int64_t>::max()};
+    HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
+    s->step = h.step;
+    s->inc_sum = h.inc_sum;
     return PSTD_OK;
 }
 
