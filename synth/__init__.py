@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "square_barrier", "gaussian_bumps", "smoothed_prior",
-    "cfg1", "cfg2", "cfg3_global", "cfg4_instances", "cfg5", "tiny", "fresnel_plane", "fd_voxels",
+    "cfg1", "cfg1_refined", "cfg2", "cfg3_global", "cfg4_instances", "cfg5", "tiny", "fresnel_plane", "fd_voxels",
     "paper_u0",
 ]
 
@@ -192,6 +192,28 @@ def cfg1():
                    abc_U0=paper_u0(alpha, k0 * h, P), tfsf=((12, 18, 30, 36),) * 3,
                    v_max=0.5 * E0, n_steps=6649, dft_begin=6649 - 1354, dft_end=6649,
                    surf_lo=(10, 10, 10), surf_hi=(38, 38, 38))
+    V = square_barrier(n, prob.h, 0.6, 0.5 * E0)
+    return prob, V
+
+
+def cfg1_refined():
+    """The plain-method barrier (r = 0.6, V0 = E0/2, k0 = pi/(4h0), h0 = 0.1)
+    at half the spacing, h = 0.05, with an absorber twice as wide (32 cells,
+    1.6 length units) and the same time T = 4.0: FFT grid 128^3, TF/SF walls
+    of 12 cells, box surface 4 cells outside the TF box."""
+    h = 0.05
+    k0 = math.pi / 0.4
+    E0 = k0 * k0 / 2
+    n = (128, 128, 128)
+    P = 32
+    alpha = 4.0 / P
+    dtau = 0.9 / (math.pi ** 2 * 3 / (k0 * h) ** 2 + 0.5)
+    steps = int(math.ceil(4.0 * E0 / dtau))
+    window = int(round(4 * 2 * math.pi / dtau))
+    prob = Problem(n=n, h=(h, h, h), k0=k0, abc_cells=(P,) * 3, abc_alpha=alpha,
+                   abc_U0=paper_u0(alpha, k0 * h, P), tfsf=((40, 52, 76, 88),) * 3,
+                   v_max=0.5 * E0, n_steps=steps, dft_begin=steps - window, dft_end=steps,
+                   surf_lo=(36, 36, 36), surf_hi=(92, 92, 92))
     V = square_barrier(n, prob.h, 0.6, 0.5 * E0)
     return prob, V
 

@@ -102,3 +102,28 @@ def test_plain_method_against_partial_waves(P):
     print("plain method: solid-angle rel-L2 of f vs partial waves", rel)
     print("f(0)", f[0, 0], ref[0, 0], "f(90)", f[18, 0], ref[18, 0], "f(180)", f[-1, 0], ref[-1, 0])
     assert rel < 0.05
+
+
+def test_refined_plain_method_within_one_percent(P):
+    """The same barrier at h = 0.05 with a 1.6-wide absorber (FFT grid 128^3,
+    26 388 steps): the far-field amplitude converges to the partial-wave
+    series, within 1 % (solid-angle weighted rel-L2).  At the 8-points-per-
+    wavelength spacing of the plain-method workload the same measure is 3.5 %,
+    which is the method's discretisation error at that spacing (the error
+    falls by about h^3 once the absorber is wide enough)."""
+    prob, V = synth.cfg1_refined()
+    print(f"refined plain method: grid {prob.n}, {prob.n_steps} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(prob.n_steps)
+    th = np.deg2rad(np.arange(0, 181, 5.0))
+    ph = np.deg2rad(np.arange(0, 360, 30.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3)
+    f = s.far_field(d).cpu().numpy().reshape(T.shape)
+    ref = pw.amplitude(prob.k0, 0.6, 0.5 * prob.k0 ** 2 / 2, th)[:, None] * np.ones_like(F)
+    w = np.sin(T) + 1e-3
+    rel = math.sqrt(np.sum(w * np.abs(f - ref) ** 2) / np.sum(w * np.abs(ref) ** 2))
+    print("  solid-angle rel-L2 of f vs partial waves", rel, flush=True)
+    assert rel < 0.01
+    s.close()
