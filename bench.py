@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--n", type=int, default=160, help="FFT grid length per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "adjoint"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project"], default="single",
                     help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
                          "adjoint: misfit gradient of the 160^3 voxel potential (6000 steps)")
     ap.add_argument("--fd-voxels", type=int, default=64, help="adjoint: finite-difference check voxels")
@@ -99,6 +99,8 @@ def main():
         return bench_batch(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "project":
+        return bench_project(args)
 
     prob, V = synth.cfg2(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window
@@ -317,6 +319,73 @@ def bench_adjoint(args):
         out["fd_check"] = {"voxels": len(vox), "delta_E0": args.fd_delta, "max_rel_err": float(err.max()),
                            "median_rel_err": float(np.median(err)),
                            "criterion": "|g_adj - g_fd| / max(|g_fd|, 1e-3 max|g_fd|)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_project(args):
+    """The projection of the 160^3 square-barrier workload's box phasors: far
+    field on the 181 x 360 grid of directions (1 degree), Fresnel plane of
+    256 x 256 points at z = 7.2 (spacing h).  The phasors come from a short
+    run with the window over all of it (their values do not change the
+    cost).  The far field is one complex FP64 GEMM per face on the matrix
+    cores, [directions x N_b] x [N_b x 2 N_c]."""
+    import numpy as np
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+    prob, V = synth.cfg2()
+    prob = prob.replace(dft_begin=0, dft_end=10 ** 12)
+    stream = torch.cuda.current_stream()
+    s = P.Solver(prob, stream=stream)
+    s.set_potential(V)
+    s.run(200)
+    th = np.deg2rad(np.arange(0, 181, 1.0))
+    ph = np.deg2rad(np.arange(0, 360, 1.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    dirs = torch.tensor(np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3),
+                        dtype=torch.float64, device="cuda")
+    pts = torch.tensor(synth.fresnel_plane(256, prob.h[0], 7.2), dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ff_ms = timed(lambda: s.far_field(dirs), max(1, args.steps // 100))
+    fr_ms = timed(lambda: s.project(pts), 1)
+    nd = dirs.shape[0]
+    n = prob.n
+    # per face normal to axis a (in-plane axes b, c): M = directions, N = 2 N_c, K = N_b
+    planes = [((1 if a == 0 else 0), (1 if a == 2 else 2)) for a in range(3)]
+    gemm_flop = sum(2 * 8.0 * nd * (2 * n[c]) * n[b] for b, c in planes)
+    out = {
+        "metric": "NTDF projection time (far field 181x360 directions, Fresnel 256x256 points), box phasors of 160^3",
+        "value": round(ff_ms + fr_ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": 200,
+        "warmup": 1,
+        "ms_per_step": None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "square barrier 160^3 box phasors -> far field 65160 directions and Fresnel 65536 points "
+                               "at z=7.2", "directions": nd, "points": int(pts.shape[0])},
+        "far_field_ms": round(ff_ms, 4),
+        "fresnel_ms": round(fr_ms, 4),
+        "far_field_gemm_tflops_whole_call": round(gemm_flop / (ff_ms / 1e3) / 1e12, 3),
+        "fp64_mfma_peak_tflops": 78.6,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -81,58 +81,86 @@ __global__ void dft_cols_kernel(const double2* __restrict__ y, double2* __restri
 }
 
 // ---------------------------------------------------------------------------
-// batched complex GEMM, row-major: C[i][j] (+)= sum_k A[i][k] B[k][j]
+// batched complex GEMM on the FP64 matrix cores, row-major:
+// C[i][j] = sum_k A[i][k] B[k][j]
+//
+// v_mfma_f64_16x16x4f64 takes, per lane l, A[i][k] with i = l % 16, k = l / 16
+// and B[k][j] with j = l % 16, k = l / 16, and leaves D[i][j] in register r
+// of lane l for i = 4 r + l / 16, j = l % 16.  A complex product is four real
+// ones: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br.  A workgroup (4 waves)
+// computes a 64 x 64 tile, each wave 32 x 32 (2 x 2 MFMA tiles), from
+// 16-deep slices of A and B staged in LDS.
 // ---------------------------------------------------------------------------
 
-constexpr int GBM = 32, GBN = 32, GBK = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int ZT = 64;   // output tile edge
+constexpr int ZK = 16;   // K slice
 
 __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const double2* __restrict__ A, int64_t lda,
                                                     int64_t sA, const double2* __restrict__ B, int64_t ldb, int64_t sB,
                                                     double2* __restrict__ C, int64_t ldc, int64_t sC) {
-    __shared__ double2 As[GBM][GBK + 1];
-    __shared__ double2 Bs[GBK][GBN + 1];
+    __shared__ double2 As[ZT][ZK + 1];
+    __shared__ double2 Bs[ZK][ZT + 1];
     const int bz = blockIdx.z;
     A += bz * sA;
     B += bz * sB;
     C += bz * sC;
-    const int i0 = blockIdx.y * GBM, j0 = blockIdx.x * GBN;
+    const int i0 = blockIdx.y * ZT, j0 = blockIdx.x * ZT;
     const int t = threadIdx.x;
-    const int ti = (t / 16) * 2, tj = (t % 16) * 2;
-    double2 acc[2][2] = {{make_double2(0, 0), make_double2(0, 0)}, {make_double2(0, 0), make_double2(0, 0)}};
-    for (int k0 = 0; k0 < K; k0 += GBK) {
-        for (int e = t; e < GBM * GBK; e += 256) {
-            const int r = e / GBK, c = e % GBK;
+    const int lane = t & 63, wave = t >> 6;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    v4d re[2][2], im[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            re[u][v] = v4d{0, 0, 0, 0};
+            im[u][v] = v4d{0, 0, 0, 0};
+        }
+    for (int k0 = 0; k0 < K; k0 += ZK) {
+        for (int e = t; e < ZT * ZK; e += 256) {
+            const int r = e / ZK, c = e % ZK;
             const int gi = i0 + r, gk = k0 + c;
             As[r][c] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : make_double2(0, 0);
         }
-        for (int e = t; e < GBK * GBN; e += 256) {
-            const int r = e / GBN, c = e % GBN;
+        for (int e = t; e < ZK * ZT; e += 256) {
+            const int r = e / ZT, c = e % ZT;
             const int gk = k0 + r, gj = j0 + c;
             Bs[r][c] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : make_double2(0, 0);
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < GBK; ++kk) {
-            const double2 a0 = As[ti][kk], a1 = As[ti + 1][kk];
-            const double2 b0 = Bs[kk][tj], b1 = Bs[kk][tj + 1];
-            acc[0][0] = zadd(acc[0][0], zmul(a0, b0));
-            acc[0][1] = zadd(acc[0][1], zmul(a0, b1));
-            acc[1][0] = zadd(acc[1][0], zmul(a1, b0));
-            acc[1][1] = zadd(acc[1][1], zmul(a1, b1));
+#pragma unroll
+        for (int ks = 0; ks < ZK; ks += 4) {
+            double2 a[2], b[2];
+            for (int u = 0; u < 2; ++u) a[u] = As[wi + u * 16 + li][ks + lk];
+            for (int v = 0; v < 2; ++v) b[v] = Bs[ks + lk][wj + v * 16 + li];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[v].x, re[u][v], 0, 0, 0);
+                    re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[v].y, re[u][v], 0, 0, 0);
+                    im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[v].y, im[u][v], 0, 0, 0);
+                    im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[v].x, im[u][v], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
+#pragma unroll
     for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
-            const int gi = i0 + ti + u, gj = j0 + tj + v;
-            if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[u][v];
-        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + wi + u * 16 + 4 * r + lk, gj = j0 + wj + v * 16 + li;
+                if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = make_double2(re[u][v][r], im[u][v][r]);
+            }
 }
 
 hipError_t zgemm(int M, int N, int K, const double2* A, int64_t lda, int64_t sA, const double2* B, int64_t ldb,
                  int64_t sB, double2* C, int64_t ldc, int64_t sC, int batch, hipStream_t stream) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, batch);
+    dim3 grid((N + ZT - 1) / ZT, (M + ZT - 1) / ZT, batch);
     hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, stream, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC);
     return hipGetLastError();
 }
@@ -174,26 +202,41 @@ __global__ void stack_transpose_kernel(const double2* __restrict__ Fp, const dou
 }
 
 // f[d] += pref exp(-i r_a x_a) sum_c' Gc[d][c'] (T[d][c'] + i r_a T[d][Nc + c'])
-__global__ void farfield_dot_kernel(const double3* __restrict__ dirs, int64_t nd, int comp_a, double xa, double pref,
-                                    const double2* __restrict__ Gc, const double2* __restrict__ T, int Nc,
-                                    double2* __restrict__ f) {
-    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= nd) return;
+// One wave per direction: the lanes read consecutive c' (coalesced rows of T
+// and Gc) and the partial sums are reduced across the wave.
+constexpr int kDotWaves = 4;
+
+__global__ __launch_bounds__(64 * kDotWaves) void farfield_dot_kernel(const double3* __restrict__ dirs, int64_t nd,
+                                                                      int comp_a, double xa, double pref,
+                                                                      const double2* __restrict__ Gc,
+                                                                      const double2* __restrict__ T, int Nc,
+                                                                      double2* __restrict__ f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t d = (int64_t)blockIdx.x * kDotWaves + (threadIdx.x >> 6);
+    if (d >= nd) return;  // whole wave
     const double3 rh = dirs[d];
     const double ra = comp_a == 0 ? rh.x : comp_a == 1 ? rh.y : rh.z;
-    double2 s = make_double2(0, 0);
+    double sx = 0, sy = 0;
     const double2* t = T + d * 2 * Nc;
     const double2* g = Gc + d * Nc;
-    for (int c = 0; c < Nc; ++c) {
+    for (int c = lane; c < Nc; c += 64) {
         const double2 a = t[c], b = t[Nc + c];
         // a + i ra b
         const double2 m = make_double2(a.x - ra * b.y, a.y + ra * b.x);
-        s = zadd(s, zmul(g[c], m));
+        const double2 p = zmul(g[c], m);
+        sx += p.x;
+        sy += p.y;
     }
-    double sn, cs;
-    sincos(-ra * xa, &sn, &cs);
-    const double2 r = zmul(s, make_double2(pref * cs, pref * sn));
-    f[d] = zadd(f[d], r);
+    for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_down(sx, o, 64);
+        sy += __shfl_down(sy, o, 64);
+    }
+    if (lane == 0) {
+        double sn, cs;
+        sincos(-ra * xa, &sn, &cs);
+        const double2 r = zmul(make_double2(sx, sy), make_double2(pref * cs, pref * sn));
+        f[d] = zadd(f[d], r);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +434,10 @@ namespace {
 template <class T>
 hipError_t ensure(T** ptr, size_t* have, size_t need) {
     if (*have >= need) return hipSuccess;
-    if (*ptr) (void)hipFree(*ptr);
+    if (*ptr) {
+        (void)hipDeviceSynchronize();  // queued launches may still use the old buffer
+        (void)hipFree(*ptr);
+    }
     *ptr = nullptr;
     *have = 0;
     hipError_t e = hipMalloc((void**)ptr, need);
@@ -480,6 +526,17 @@ hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb
     ProjectState* s = *pst;
     TRY(hipMemsetAsync(out, 0, n_dir * sizeof(double2), stream));
     const int64_t chunk = 8192;
+    {
+        // the largest scratch any face needs, allocated before the first
+        // launch that uses it
+        size_t need = 0;
+        for (int f = 0; f < 6; ++f) {
+            const int a = f / 2, Nb = p.n[face_axis_b(a)], Nc = p.n[face_axis_c(a)];
+            const size_t nd = (size_t)std::min(chunk, n_dir);
+            need = std::max(need, (nd * Nb + nd * Nc + (size_t)Nb * 2 * Nc + nd * 2 * Nc) * sizeof(double2));
+        }
+        TRY(ensure(&s->work, &s->work_bytes, need));
+    }
     for (int64_t d0 = 0; d0 < n_dir; d0 += chunk) {
         const int64_t nd = std::min(chunk, n_dir - d0);
         for (int f = 0; f < 6; ++f) {
@@ -489,9 +546,6 @@ hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb
             const double xa = (idx - p.n[a] / 2) * dxb[a];
             const double pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc) / p.k0;
             // scratch: Gb [nd][Nb], Gc [nd][Nc], Mt [Nb][2Nc], T [nd][2Nc]
-            const size_t need = ((size_t)nd * Nb + (size_t)nd * Nc + (size_t)Nb * 2 * Nc + (size_t)nd * 2 * Nc) *
-                                sizeof(double2);
-            TRY(ensure(&s->work, &s->work_bytes, need));
             double2* Gb = s->work;
             double2* Gc = Gb + nd * Nb;
             double2* Mt = Gc + nd * Nc;
@@ -505,8 +559,8 @@ hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb
             hipLaunchKernelGGL(stack_transpose_kernel, dim3((unsigned)(((int64_t)Nb * 2 * Nc + 255) / 256)), dim3(256),
                                0, stream, Fp, Fd, Nb, Nc, Mt);
             TRY(zgemm((int)nd, 2 * Nc, Nb, Gb, Nb, 0, Mt, 2 * Nc, 0, T, 2 * Nc, 0, 1, stream));
-            hipLaunchKernelGGL(farfield_dot_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, stream,
-                               dirs + d0, nd, a, xa, pref, Gc, T, Nc, out + d0);
+            hipLaunchKernelGGL(farfield_dot_kernel, dim3((unsigned)((nd + kDotWaves - 1) / kDotWaves)),
+                               dim3(64 * kDotWaves), 0, stream, dirs + d0, nd, a, xa, pref, Gc, T, Nc, out + d0);
         }
     }
     return hipGetLastError();
