@@ -21,7 +21,7 @@ import numpy as np
 
 def sph_jn(lmax, x):
     """j_0..j_lmax at x > 0 by Miller's downward recurrence
-    j_{l-1} = (2l+1)/x j_l - j_{l+1}, normalised with j_0 = sin x / x."""
+    j_{l-1} = (2l+1)/x j_l - j_{l+1}, normalised by the sum rule."""
     start = lmax + 20 + int(x) + int(2 * math.sqrt(max(x, 1.0)) * 4)
     jp1, j = 0.0, 1e-300
     vals = [0.0] * (start + 1)
@@ -34,8 +34,19 @@ def sph_jn(lmax, x):
             vals = [v * 1e-250 for v in vals]
             j *= 1e-250
             jp1 *= 1e-250
-    scale = (math.sin(x) / x) / vals[0]
-    return np.array(vals[:lmax + 1]) * scale
+    # normalise with the sum rule sum_l (2l+1) j_l(x)^2 = 1 (j_0 = sin x / x
+    # vanishes at x = n pi, so it cannot fix the scale there); the sign comes
+    # from whichever of j_0, j_1 is larger in magnitude
+    v = np.array(vals)
+    v = v / np.abs(v).max()
+    scale = 1.0 / math.sqrt(float(np.sum((2 * np.arange(len(v)) + 1) * v * v)))
+    j0 = math.sin(x) / x
+    j1 = math.sin(x) / (x * x) - math.cos(x) / x
+    if abs(j0) >= abs(j1):
+        scale = math.copysign(scale, j0 * v[0])
+    else:
+        scale = math.copysign(scale, j1 * v[1])
+    return v[:lmax + 1] * scale
 
 
 def sph_yn(lmax, x):

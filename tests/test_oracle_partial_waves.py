@@ -1,5 +1,6 @@
-"""Pins of the partial-wave reference (Section 4): library Bessel functions,
-the optical theorem, the Born limit and the hard-sphere limit."""
+"""Pins of the partial-wave reference (Section 4): library Bessel functions
+(also at ka = n pi, where j_0 vanishes), the optical theorem, the Born limit
+and the hard-sphere limit."""
 import math
 
 import numpy as np
@@ -9,10 +10,12 @@ from scipy import special
 from oracle import partial_waves as pw
 
 
-@pytest.mark.parametrize("x", [0.3, 2.0, 4.712, 7.3, 18.85, 40.0])
+@pytest.mark.parametrize("x", [0.3, 2.0, 4.712, 7.3, 18.85, 40.0, 3 * math.pi, 6 * math.pi, 1.5 * math.pi])
 def test_bessel_functions_match_library(x):
     l = np.arange(31)
-    assert np.allclose(pw.sph_jn(30, x), special.spherical_jn(l, x), rtol=1e-11, atol=1e-300)
+    ref = special.spherical_jn(l, x)
+    # j_0 vanishes at x = n pi: compare there on the scale of the largest j_l
+    assert np.allclose(pw.sph_jn(30, x), ref, rtol=1e-11, atol=1e-14 * np.abs(ref).max())
     yy = special.spherical_yn(l[:20], x)
     assert np.allclose(pw.sph_yn(19, x), yy, rtol=1e-11)
     assert np.allclose(pw.sph_in(30, x), special.spherical_in(l, x), rtol=1e-11, atol=1e-300)
