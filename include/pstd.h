@@ -80,7 +80,20 @@ typedef struct pstd_problem {
     int32_t sub_core[3];
     int32_t sub_halo;
     int32_t sub_taper;
-    int32_t reserved[2];
+    /* Equivalence surface used by pstd_project / pstd_far_field.  Section 3.1
+     * allows any closed surface around the scatterer; the paper integrates
+     * over the box faces (surface_kind 0).  surface_kind 1 uses a sphere of
+     * radius sphere_radius (physical, centred at the origin) with
+     * sphere_nodes = (n_theta, n_phi) Gauss-Legendre x uniform quadrature
+     * nodes (0, 0: 64 x 128): the running DFT is taken on the shell of grid
+     * cells that 8-point Lagrange stencils around the nodes touch, the
+     * incident part zeta psi_inc is removed, and the Kirchhoff integral with
+     * G = exp(ikR)/(4 pi R) is summed over the nodes.  The box faces are
+     * accumulated in both cases.  The sphere must enclose the region where
+     * the taper is one and its shell must stay outside the absorber. */
+    int32_t surface_kind;
+    int32_t sphere_nodes[2];
+    double  sphere_radius;
 } pstd_problem;
 
 typedef struct pstd_solver pstd_solver;  /* opaque; owns all its device memory */
@@ -181,16 +194,29 @@ pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out_host);
  * ESTATE if no step of the window has run. */
 pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n);
 
+/* Number of quadrature nodes of the spherical surface (0 for the box). */
+pstd_status pstd_sphere_size(const pstd_solver* s, int64_t* n_nodes_out_host);
+
+/* Scattered-field phasors at the sphere's nodes, normalised like the box
+ * phasors: out_dev = [psi at the nodes][d psi / d n_bar at the nodes],
+ * complex128, n = 2 * pstd_sphere_size; nodes ordered [theta][phi] with
+ * cos(theta) ascending (Gauss-Legendre) and phi = 2 pi j / n_phi.  ESTATE
+ * without a sphere or before any window step. */
+pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n);
+
 /* Scattered wave Psi(r) at n_obs points (physical xyz, double[3] each) by the
  * box integral of Eqs. bottomPsi_lm ... leftrightPsi_ln summed by Eq. Psi,
  * with each sinc expanded to 8th order in its shift.  Output complex128,
  * relative to a unit-amplitude incident wave.  Points must lie outside the
- * box.  ESTATE before any window step. */
+ * box (outside the sphere with surface_kind 1, which sums the Kirchhoff
+ * integral over the sphere's nodes instead).  ESTATE before any window
+ * step. */
 pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_obs, double* psi_out_dev);
 
 /* Far-field amplitude f(r_hat) = lim r e^{-ikr} Psi (physical length units)
  * for n_dir unit directions (double[3] each): the cell formula in the limit
- * of Eq. FDTDfarfieldapprox.  Output complex128. */
+ * of Eq. FDTDfarfieldapprox (with surface_kind 1, the limit of the sphere's
+ * Kirchhoff sum).  Output complex128. */
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
 
 /*

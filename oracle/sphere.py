@@ -10,6 +10,8 @@ Definition (reduced units, k = 1, x_bar = k0 x):
     w_q = R^2 w_GL 2 pi / n_phi;
   * the running DFT (Eq. psiphasor, weight exp(i tau_n)) is taken on the
     shell of grid cells the interpolation stencils touch;
+  * the incident part zeta psi_inc of the stored field is removed from the
+    shell phasors (so stencils may reach into the taper walls);
   * node values psi_q and normal derivatives d_n psi_q come from separable
     Lagrange interpolation of `order` points per axis around each node
     (index space, derivative of the interpolant), normalised by the incident
@@ -171,7 +173,13 @@ class ShellDFT:
         self.inc += _pstd.ramp(tau, self.m.tau_r)
 
     def normalized(self):
-        return self.phi / self.inc
+        """Scattered-field phasors on the shell: the total-field phasor minus
+        the incident part.  The stored field is psi_s + zeta psi_inc (Eq.
+        PSTD_TF-SF) and the DFT of zeta R(tau_n) exp(i(k.x - tau_n)) with
+        weights exp(i tau_n) is zeta exp(i k.x) sum_n R(tau_n), so after the
+        normalisation the incident part is zeta exp(i k.x) exactly."""
+        out = self.phi / self.inc - self.m.zeta * self.m.phase
+        return np.where(self.mask, out, 0.0)
 
 
 def run(prob, V, sphere, n_steps=None):

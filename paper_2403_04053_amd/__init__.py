@@ -15,7 +15,7 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_far_field", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -71,7 +71,9 @@ class pstd_problem(ctypes.Structure):
         ("sub_core", ctypes.c_int32 * 3),
         ("sub_halo", ctypes.c_int32),
         ("sub_taper", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("surface_kind", ctypes.c_int32),
+        ("sphere_nodes", ctypes.c_int32 * 2),
+        ("sphere_radius", ctypes.c_double),
     ]
 
 
@@ -99,6 +101,11 @@ def problem_from(obj) -> pstd_problem:
             p.sub_core[a] = int(sub[a])
         p.sub_halo = int(obj.sub_halo)
         p.sub_taper = int(obj.sub_taper)
+    p.surface_kind = int(getattr(obj, "surface_kind", 0))
+    nodes = getattr(obj, "sphere_nodes", (0, 0))
+    p.sphere_nodes[0] = int(nodes[0])
+    p.sphere_nodes[1] = int(nodes[1])
+    p.sphere_radius = float(getattr(obj, "sphere_radius", 0.0))
     return p
 
 
@@ -124,6 +131,8 @@ _SIGS = {
     "pstd_misfit_forward": [_vp, _i64, _vp, _i64, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pstd_misfit_backward": [_vp, _vp, _i64],
     "pstd_state_size": [_vp, ctypes.POINTER(_i64)],
+    "pstd_sphere_size": [_vp, ctypes.POINTER(_i64)],
+    "pstd_get_sphere_phasors": [_vp, _vp, _i64],
     "pstd_save_state": [_vp, _vp, _i64],
     "pstd_load_state": [_vp, _vp, _i64],
     "pstd_destroy": [_vp],
@@ -253,6 +262,16 @@ def pstd_project(solver, obs_dev, n_obs, out_dev):
 
 def pstd_far_field(solver, dir_dev, n_dir, out_dev):
     _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
+
+
+def pstd_sphere_size(solver):
+    out = _i64()
+    _check(lib.pstd_sphere_size(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
+def pstd_get_sphere_phasors(solver, out_dev, n):
+    _check(lib.pstd_get_sphere_phasors(solver, _ptr(out_dev), int(n)), solver)
 
 
 def pstd_state_size(solver):
@@ -446,6 +465,13 @@ class Solver:
         pstd_far_field(self.handle, d, d.shape[0], out)
         return out
 
+
+    def sphere_phasors(self):
+        """(psi, d psi/d n) at the sphere's nodes (complex128 CUDA tensors)."""
+        n = pstd_sphere_size(self.handle)
+        out = self.torch.empty(2 * n, dtype=self.torch.complex128, device=self.device)
+        pstd_get_sphere_phasors(self.handle, out, 2 * n)
+        return out[:n], out[n:]
 
     def save_state(self):
         """The solver state as a uint8 CUDA tensor (pstd_save_state)."""

@@ -127,6 +127,30 @@ void plane_local(const pstd_problem& p, int a, int side, int* seg, int* pos) {
     }
 }
 
+// taper factor of axis a at grid index i and its derivatives in reduced
+// length (Eq. zeta_y with Eq. xi)
+void taper(const pstd_problem& p, int a, double dxb, int i, double* z, double* z1, double* z2) {
+    const int* y = p.tfsf[a];
+    *z = 0;
+    *z1 = 0;
+    *z2 = 0;
+    if (i > y[0] && i < y[3]) {
+        if (i >= y[1] && i <= y[2]) {
+            *z = 1.0;
+        } else if (i < y[1]) {
+            const double w = (y[1] - y[0]) * dxb, r = double(i - y[0]) / (y[1] - y[0]);
+            *z = xi(r);
+            *z1 = dxi(r) / w;
+            *z2 = d2xi(r) / (w * w);
+        } else {
+            const double w = (y[3] - y[2]) * dxb, r = double(i - y[2]) / (y[3] - y[2]);
+            *z = 1.0 - xi(r);
+            *z1 = -dxi(r) / w;
+            *z2 = -d2xi(r) / (w * w);
+        }
+    }
+}
+
 pstd_status build_tables(pstd_solver* s) {
     const pstd_problem& p = s->prob;
     // per axis: kk[Nl] f, wloc[Nl] f, tw[Nl] f2, dlo[Nl] f2, dhi[Nl] f2 (local length Nl),
@@ -165,24 +189,8 @@ pstd_status build_tables(pstd_solver* s) {
                 g = p.abc_U0 / (c * c);
             }
             gam[i] = (float)std::exp(-g * s->dtau);
-            // taper factor and its derivatives (Eq. zeta_y with Eq. xi)
-            const int* y = p.tfsf[a];
-            double z = 0, z1 = 0, z2 = 0;
-            if (i > y[0] && i < y[3]) {
-                if (i >= y[1] && i <= y[2]) {
-                    z = 1.0;
-                } else if (i < y[1]) {
-                    const double w = (y[1] - y[0]) * dxb, r = double(i - y[0]) / (y[1] - y[0]);
-                    z = xi(r);
-                    z1 = dxi(r) / w;
-                    z2 = d2xi(r) / (w * w);
-                } else {
-                    const double w = (y[3] - y[2]) * dxb, r = double(i - y[2]) / (y[3] - y[2]);
-                    z = 1.0 - xi(r);
-                    z1 = -dxi(r) / w;
-                    z2 = -d2xi(r) / (w * w);
-                }
-            }
+            double z, z1, z2;
+            taper(p, a, dxb, i, &z, &z1, &z2);
             const double x = (i - N / 2) * dxb;
             const double ph = s->kh[a] * x;
             const double er = std::cos(ph), ei = std::sin(ph);
@@ -262,6 +270,11 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
     }
+    if (s->sphere) {
+        // psi^n stays in its buffer until the next step's z pass
+        hipError_t e = pstd::sphere_launch_dft(s, koff, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "shell DFT launch");
+    }
     return PSTD_OK;
 }
 
@@ -302,6 +315,17 @@ pstd_status build_graph(pstd_solver* s) {
 namespace pstd {
 
 pstd_status solver_fail(pstd_solver* s, pstd_status st, const std::string& msg) { return fail(s, st, msg); }
+
+void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out) {
+    const int N = s->prob.n[a];
+    out.resize(N);
+    for (int i = 0; i < N; ++i) {
+        double z, z1, z2;
+        taper(s->prob, a, s->dxb[a], i, &z, &z1, &z2);
+        const double ph = s->kh[a] * (i - N / 2) * s->dxb[a];
+        out[i] = make_double2(z * std::cos(ph), z * std::sin(ph));
+    }
+}
 pstd_status solver_hip_fail(pstd_solver* s, hipError_t e, const char* what) { return hip_fail(s, e, what); }
 
 void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
@@ -422,6 +446,9 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
         if ((e = hipMalloc(&s->acc[a], 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMalloc acc"));
     for (int a = 0; a < 3; ++a) pass_variants(local_len(*p, a), p->sub_core[a] > 0, &s->variant[a], 1);
     if ((st = build_tables(s))) return cleanup(st);
+    if (ext_ctr && p->surface_kind != 0)
+        return cleanup(fail(s, PSTD_EUNSUPPORTED, "batch instances integrate over the box surface only"));
+    if ((st = sphere_create(s))) return cleanup(st);
     const int64_t c0[2] = {0, std::numeric_limits<int64_t>::max()};
     if ((e = hipMemcpy(s->ctr, c0, sizeof(c0), hipMemcpyHostToDevice))) return cleanup(hip_fail(s, e, "counters"));
     if ((e = hipMemset(s->buf[0], 0, s->cells * sizeof(float2))) || (e = hipMemset(s->buf[1], 0, s->cells * sizeof(float2))) ||
@@ -625,6 +652,8 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
     HIP_TRY(s, hipMemcpy(s->buf[(step + 1) & 1], prev, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
     HIP_TRY(s, hipMemcpy(s->buf[step & 1], cur, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
     for (int a = 0; a < 3; ++a) HIP_TRY(s, hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)));
+    sphere_clear(s, s->stream);
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
     const int64_t c[2] = {step, std::numeric_limits<int64_t>::max()};
     HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
     HIP_TRY(s, hipDeviceSynchronize());
@@ -756,7 +785,7 @@ constexpr int64_t kStateMagic = 0x3176534454535050LL;  // "PPSTDSv1"
 static int64_t state_bytes(const pstd_solver* s) {
     int64_t b = (int64_t)sizeof(StateHeader) + 2 * s->cells * (int64_t)sizeof(float2);
     for (int a = 0; a < 3; ++a) b += 8 * s->points[a] * (int64_t)sizeof(double2);
-    return b;
+    return b + sphere_state_bytes(s);
 }
 
 pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out) {
@@ -783,6 +812,7 @@ pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
         HIP_TRY(s, hipMemcpyAsync(d, s->acc[a], ab, hipMemcpyDeviceToDevice, s->stream));
         d += ab;
     }
+    HIP_TRY(s, sphere_save(s, d, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return PSTD_OK;
 }
@@ -811,6 +841,7 @@ pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) 
         HIP_TRY(s, hipMemcpyAsync(s->acc[a], d, ab, hipMemcpyDeviceToDevice, s->stream));
         d += ab;
     }
+    HIP_TRY(s, sphere_load(s, d, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const int64_t c[2] = {h.step, std::numeric_limits<int64_t>::max()};
     HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
@@ -836,9 +867,38 @@ pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n)
     return PSTD_OK;
 }
 
+pstd_status pstd_sphere_size(const pstd_solver* s, int64_t* n_nodes_out) {
+    if (!s || !n_nodes_out) return PSTD_EINVAL;
+    *n_nodes_out = sphere_nodes(s);
+    return PSTD_OK;
+}
+
+pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+    if (!s || !out_dev) return PSTD_EINVAL;
+    if (!s->sphere) return fail(s, PSTD_ESTATE, "the problem has no spherical surface");
+    if (n != 2 * sphere_nodes(s)) return fail(s, PSTD_EINVAL, "output size must be twice pstd_sphere_size");
+    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    hipError_t e = sphere_phasors(s, (double2*)out_dev, s->stream);
+    if (e) return hip_fail(s, e, "sphere phasors");
+    return PSTD_OK;
+}
+
 pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
     if (!s || !obs_dev || !out_dev || n_obs < 0) return PSTD_EINVAL;
     if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (s->sphere) {
+        // the Kirchhoff integral holds outside the sphere only
+        std::vector<double> h(3 * n_obs);
+        HIP_TRY(s, hipMemcpyAsync(h.data(), obs_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        for (int64_t o = 0; o < n_obs; ++o) {
+            const double r = std::sqrt(h[3 * o] * h[3 * o] + h[3 * o + 1] * h[3 * o + 1] + h[3 * o + 2] * h[3 * o + 2]);
+            if (!(r > s->prob.sphere_radius)) return fail(s, PSTD_EINVAL, "observation point inside the sphere or not finite");
+        }
+        hipError_t e = sphere_project(s, (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream);
+        if (e) return hip_fail(s, e, "sphere projection");
+        return PSTD_OK;
+    }
     std::string msg;
     hipError_t e = project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
                                   (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
@@ -849,6 +909,11 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, d
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
     if (!s || !dir_dev || !out_dev || n_dir < 0) return PSTD_EINVAL;
     if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (s->sphere) {
+        hipError_t e = sphere_far_field(s, (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream);
+        if (e) return hip_fail(s, e, "sphere far field");
+        return PSTD_OK;
+    }
     std::string msg;
     hipError_t e = far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
                              (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
@@ -876,6 +941,7 @@ pstd_status pstd_destroy(pstd_solver* s) {
     for (int a = 0; a < 3; ++a) (void)hipFree(s->acc[a]);
     project_free(s->proj);
     adjoint_free(s);
+    sphere_free(s->sphere);
     delete s;
     return PSTD_OK;
 }

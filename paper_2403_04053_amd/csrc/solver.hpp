@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/pstd.h"
 #include "internal.hpp"
@@ -12,6 +13,7 @@
 
 namespace pstd {
 struct AdjointState;  // misfit checkpoints and adjoint buffers
+struct SphereState;   // spherical equivalence surface
 }
 
 struct pstd_solver {
@@ -50,6 +52,7 @@ struct pstd_solver {
     hipGraphExec_t graph = nullptr;
     pstd::ProjectState* proj = nullptr;
     pstd::AdjointState* adj = nullptr;
+    pstd::SphereState* sphere = nullptr;
     std::string err;
     bool in_batch = false;
 };
@@ -70,5 +73,22 @@ void solver_drop_graph(pstd_solver* s);
 // the misfit forward run no longer matches the solver state
 void adjoint_invalidate(pstd_solver* s);
 void adjoint_free(pstd_solver* s);
+// zeta_a(i) exp(i khat_a xbar_i) for every grid index of axis a, FP64
+void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out);
+
+// spherical equivalence surface (sphere.hip)
+pstd_status sphere_create(pstd_solver* s);
+void sphere_free(SphereState* sp);
+// running DFT of psi^{ctr[0] + koff} on the shell cells (inside the window)
+hipError_t sphere_launch_dft(const pstd_solver* s, int koff, hipStream_t stream);
+void sphere_clear(pstd_solver* s, hipStream_t stream);
+int64_t sphere_state_bytes(const pstd_solver* s);
+hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream);
+hipError_t sphere_load(pstd_solver* s, const char* src, hipStream_t stream);
+int64_t sphere_nodes(const pstd_solver* s);
+// node phasors (psi, d_n psi; scattered part, normalised by 1 / inc_sum)
+hipError_t sphere_phasors(pstd_solver* s, double2* out, hipStream_t stream);
+hipError_t sphere_project(pstd_solver* s, const double3* obs, int64_t n_obs, double2* out, hipStream_t stream);
+hipError_t sphere_far_field(pstd_solver* s, const double3* dirs, int64_t n_dir, double2* out, hipStream_t stream);
 
 }  // namespace pstd

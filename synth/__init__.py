@@ -60,6 +60,9 @@ class Problem:
     sub_core: tuple = ()
     sub_halo: int = 0
     sub_taper: int = 0
+    surface_kind: int = 0          # 0: box faces; 1: sphere (an addition, not in the paper)
+    sphere_radius: float = 0.0     # physical, centred at the origin
+    sphere_nodes: tuple = (64, 128)
 
     def replace(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)

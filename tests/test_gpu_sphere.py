@@ -1,0 +1,158 @@
+"""GPU parity of the spherical equivalence surface against the FP64 oracle
+(shell DFT with the incident part removed, interpolation to the nodes,
+Kirchhoff sums), its validation errors, and the 160^3 square-barrier
+workload's far field from the sphere against the box and the partial-wave
+series."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import partial_waves as pw
+from oracle import sphere as osph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available()
+    import paper_2403_04053_amd as mod
+    return mod
+
+
+def small_problem(v0=1.0, theta=0.5, phi=0.8):
+    """48^3, 8 points per wavelength, taper walls 16..19 / 29..32, sphere of
+    radius 1.2 whose stencils reach into the taper walls near the axes."""
+    h = 0.1
+    k0 = 2 * math.pi / (8 * h)
+    E0 = k0 * k0 / 2
+    P_ = 4
+    alpha = 4.0 / P_
+    prob = synth.Problem(n=(48, 48, 48), h=(h,) * 3, k0=k0, theta=theta, phi=phi, abc_cells=(P_,) * 3,
+                         abc_alpha=alpha, abc_U0=synth.paper_u0(alpha, k0 * h, P_), tfsf=((16, 19, 29, 32),) * 3,
+                         v_max=max(abs(v0), 1e-9) * E0, ramp_periods=0.5, n_steps=160, dft_begin=80, dft_end=160,
+                         surf_lo=(14,) * 3, surf_hi=(34,) * 3, surface_kind=1, sphere_radius=0.95,
+                         sphere_nodes=(16, 32))
+    V = np.zeros((48, 48, 48))
+    x = (np.arange(48) - 24)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    V[X * X + Y * Y + Z * Z <= 9] = v0 * E0
+    return prob, V.astype(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def small(P):
+    prob, V = small_problem()
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(prob.n_steps)
+    sph = osph.Sphere(prob, prob.sphere_radius, n_theta=16, n_phi=32)
+    _, _, sd = osph.run(prob, V, sph)
+    ref_v, ref_d = sph.node_values(sd.normalized())
+    return prob, V, s, sph, ref_v, ref_d
+
+
+def test_sphere_phasors_match_oracle(P, small):
+    prob, V, s, sph, ref_v, ref_d = small
+    v, d = (x.cpu().numpy() for x in s.sphere_phasors())
+    ev = np.linalg.norm(v - ref_v) / np.linalg.norm(ref_v)
+    ed = np.linalg.norm(d - ref_d) / np.linalg.norm(ref_d)
+    print(f"sphere phasors rel-L2: psi {ev:.2e}, d psi/dn {ed:.2e}", flush=True)
+    assert ev < 1e-4 and ed < 1e-4
+
+
+def test_sphere_projection_same_phasors(P, small):
+    prob, V, s, sph, _, _ = small
+    v, d = (x.cpu().numpy() for x in s.sphere_phasors())
+    rng = np.random.default_rng(3)
+    pts = rng.normal(size=(20, 3))
+    pts = pts / np.linalg.norm(pts, axis=1, keepdims=True) * rng.uniform(1.5, 6.0, size=(20, 1))
+    got = s.project(pts).cpu().numpy()
+    ref = sph.project(v, d, pts * prob.k0)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    dirs = rng.normal(size=(30, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    gf = s.far_field(dirs).cpu().numpy()
+    rf = sph.far_field(v, d, dirs)
+    assert np.abs(gf - rf).max() <= 1e-10 * np.abs(rf).max()
+
+
+def test_incident_part_removed(P):
+    """Steady state (ramp over, window the last 4 periods): with no scatterer
+    the scattered phasors on the sphere stay at the level of the TF/SF
+    leakage although the stencils reach into the taper walls and the total
+    field region; with the barrier they are an order of magnitude larger."""
+    out = []
+    for v0 in (0.0, 1.0):
+        prob, V = small_problem(v0=v0)
+        dtau = 0.9 / (math.pi ** 2 * 3 / (prob.k0 * prob.h[0]) ** 2 + max(v0, 1e-9))
+        win = int(round(4 * 2 * math.pi / dtau))
+        steps = 3 * win
+        prob = prob.replace(tfsf=((14, 19, 29, 34),) * 3, surf_lo=(12,) * 3, surf_hi=(36,) * 3,
+                            n_steps=steps, dft_begin=steps - win, dft_end=steps)
+        s = P.Solver(prob)
+        s.set_potential(V)
+        s.run(prob.n_steps)
+        v, d = (x.cpu().numpy() for x in s.sphere_phasors())
+        out.append(np.abs(v).max())
+        s.close()
+    print(f"steady state: max |psi_s| on the sphere, V = 0: {out[0]:.2e}, barrier: {out[1]:.2e}", flush=True)
+    assert out[0] < 0.1 * out[1]
+
+
+def test_sphere_validation(P):
+    prob, V = small_problem()
+    with pytest.raises(P.PstdError) as e:       # does not enclose the core
+        P.Solver(prob.replace(sphere_radius=0.7))
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:       # shell in the absorber
+        P.Solver(prob.replace(sphere_radius=1.9))
+    assert e.value.name == "PSTD_EINVAL"
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(prob.n_steps)
+    with pytest.raises(P.PstdError) as e:       # a point inside the sphere
+        s.project(np.array([[0.0, 0.0, 0.5]]))
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:
+        s.misfit(prob.n_steps, np.array([[0.0, 0.0, 3.0]]), np.ones(1))
+    assert e.value.name == "PSTD_EUNSUPPORTED"
+    with pytest.raises(P.PstdError) as e:
+        P.Batch([prob])
+    assert e.value.name == "PSTD_EUNSUPPORTED"
+    s.close()
+
+
+def test_square_barrier_sphere_far_field(P):
+    """The 160^3 square-barrier workload run in full with the sphere of
+    radius 5: the far field from the sphere against the box and the
+    partial-wave series of the barrier."""
+    prob, V = synth.cfg2()
+    prob = prob.replace(surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
+    print(f"square barrier with sphere: grid {prob.n}, {prob.n_steps} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(prob.n_steps)
+    th = np.deg2rad(np.arange(0, 181, 3.0))
+    ph = np.deg2rad(np.arange(0, 360, 30.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3)
+    f_s = s.far_field(d).cpu().numpy().reshape(T.shape)
+    box = P.Solver(prob.replace(surface_kind=0))
+    box.set_potential(V)
+    box.run(prob.n_steps)
+    f_b = box.far_field(d).cpu().numpy().reshape(T.shape)
+    ref = pw.amplitude(prob.k0, 2.4, 0.5 * prob.k0 ** 2 / 2, th)[:, None] * np.ones_like(F)
+    w = np.sin(T) + 1e-3
+
+    def rel(a, b):
+        return math.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2))
+    r_sb, r_sp, r_bp = rel(f_s, f_b), rel(f_s, ref), rel(f_b, ref)
+    print(f"  sphere vs box {r_sb:.4f}, sphere vs partial waves {r_sp:.4f}, box vs partial waves {r_bp:.4f}",
+          flush=True)
+    assert r_sb < 0.02 and r_sp < 0.05
+    s.close()
+    box.close()
