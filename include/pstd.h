@@ -88,9 +88,9 @@ typedef struct pstd_problem {
      * nodes (0, 0: 64 x 128): the running DFT is taken on the shell of grid
      * cells that 8-point Lagrange stencils around the nodes touch, the
      * incident part zeta psi_inc is removed, and the Kirchhoff integral with
-     * G = exp(ikR)/(4 pi R) is summed over the nodes.  The box faces are
-     * accumulated in both cases.  The sphere must enclose the region where
-     * the taper is one and its shell must stay outside the absorber. */
+     * G = exp(ikR)/(4 pi R) is summed over the nodes; the box faces are then
+     * not accumulated.  The sphere must enclose the region where the taper is
+     * one and its shell must stay outside the absorber. */
     int32_t surface_kind;
     int32_t sphere_nodes[2];
     double  sphere_radius;
@@ -136,9 +136,10 @@ pstd_status pstd_set_state(pstd_solver* s, const void* psi_prev_dev, const void*
  * DFT for the steps inside [dft_begin, dft_end).  Asynchronous. */
 pstd_status pstd_run(pstd_solver* s, int64_t n_steps);
 
-/* Like pstd_run, and also times every pass kernel with HIP events on the
- * solver's stream.  pass_ms_host[3] receives the summed milliseconds of the
- * x, y and z passes.  Synchronises. */
+/* Like pstd_run (without the graph), and also times every pass kernel with
+ * a pair of HIP events around its launch on the solver's stream; the steps
+ * are queued back to back and the events read at the end.  pass_ms_host[3]
+ * receives the summed milliseconds of the x, y and z passes.  Synchronises. */
 pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host);
 
 /* Pick, for each axis pass, the fastest compiled tile shape (FFT factor
@@ -149,6 +150,13 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host
  * noise does not flip the choice between runs.  Synchronises.  ENOMEM if the
  * scratch cannot be allocated. */
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
+
+/* Average duration (microseconds) of one launch of the pass along `axis`
+ * with its current tile shape: `reps` back-to-back launches on scratch
+ * buffers of the solver's size, bracketed by HIP events on the solver's
+ * stream (the same timing the autotuner uses).  The solver's state is not
+ * touched.  Synchronises. */
+pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* us_out_host);
 
 /* Tile shape used by the pass along axis (0, 1, 2): info_host[4] =
  * {N, N1, N2, pencils per workgroup}.  Host only. */
@@ -191,7 +199,7 @@ pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out_host);
  * over the window steps that have run since creation or pstd_set_state).  Layout: faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; per
  * face the psi plane then the d(psi)/d(x_bar_normal) plane (reduced-unit
  * derivative); x faces are [k][j], y faces [k][i], z faces [j][i].
- * ESTATE if no step of the window has run. */
+ * ESTATE if no step of the window has run, or with a spherical surface. */
 pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n);
 
 /* Number of quadrature nodes of the spherical surface (0 for the box). */

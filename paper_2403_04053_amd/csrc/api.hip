@@ -342,7 +342,7 @@ void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
     a.ctr = s->ctr;
     a.sigma_tab = s->sigma_tab;
     a.w_tab = s->w_tab;
-    a.dft_tab = s->dft_tab;
+    a.dft_tab = s->dft_zero ? s->dft_zero : s->dft_tab;
     plane_local(p, axis, 0, &a.seg_plane[0], &a.plane_lo);
     plane_local(p, axis, 1, &a.seg_plane[1], &a.plane_hi);
     a.acc = s->acc[axis];
@@ -375,9 +375,11 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     (void)hipFree(s->sigma_tab);
     (void)hipFree(s->w_tab);
     (void)hipFree(s->dft_tab);
+    (void)hipFree(s->dft_zero);
     s->sigma_tab = nullptr;
     s->w_tab = nullptr;
     s->dft_tab = nullptr;
+    s->dft_zero = nullptr;
     s->tab_cap = 0;
     HIP_TRY(s, hipMalloc(&s->sigma_tab, cap * sizeof(float2)));
     HIP_TRY(s, hipMalloc(&s->w_tab, cap * sizeof(double2)));
@@ -385,6 +387,10 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     HIP_TRY(s, hipMemcpy(s->sigma_tab, sig.data(), cap * sizeof(float2), hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemcpy(s->w_tab, w.data(), cap * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemcpy(s->dft_tab, on.data(), cap * sizeof(int), hipMemcpyHostToDevice));
+    if (s->prob.surface_kind == 1) {
+        HIP_TRY(s, hipMalloc(&s->dft_zero, cap * sizeof(int)));
+        HIP_TRY(s, hipMemset(s->dft_zero, 0, cap * sizeof(int)));
+    }
     s->tab_cap = cap;
     s->tab_gen += 1;
     solver_drop_graph(s);  // the graph's launches hold the old table addresses
@@ -462,89 +468,82 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     return PSTD_OK;
 }
 
-pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
-    // time every compiled tile shape of each axis on scratch state (the
-    // solver's own state is left untouched) and keep the fastest
+// Time `reps` back-to-back launches of each given tile shape of one axis on
+// scratch state of the solver's size (the solver's own state is untouched);
+// ms_out[k] receives the average milliseconds per launch of shape ids[k].
+pstd_status time_shapes(pstd_solver* s, int axis, const int* ids, int n, int32_t reps, float* ms_out) {
     float2 *tb0 = nullptr, *tb1 = nullptr, *tL = nullptr;
-    double2* tacc[3] = {nullptr, nullptr, nullptr};
-    pstd::PassArgs* tdesc = nullptr;
-    int* toff = nullptr;
+    double2* tacc = nullptr;
     int64_t* tctr = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    pstd_status st = PSTD_OK;
     auto release = [&]() {
         (void)hipFree(tb0);
         (void)hipFree(tb1);
         (void)hipFree(tL);
-        (void)hipFree(tdesc);
-        (void)hipFree(toff);
+        (void)hipFree(tacc);
         (void)hipFree(tctr);
-        for (int a = 0; a < 3; ++a) (void)hipFree(tacc[a]);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
     hipError_t e;
     if ((e = hipMalloc(&tb0, s->cells * sizeof(float2))) || (e = hipMalloc(&tb1, s->cells * sizeof(float2))) ||
-        (e = hipMalloc(&tL, s->cells * sizeof(float2))) || (e = hipMalloc(&tdesc, sizeof(pstd::PassArgs))) ||
-        (e = hipMalloc(&toff, 2 * sizeof(int))) || (e = hipMalloc(&tctr, 2 * sizeof(int64_t))) ||
-        (e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+        (e = hipMalloc(&tL, s->cells * sizeof(float2))) || (e = hipMalloc(&tctr, 2 * sizeof(int64_t))) ||
+        (e = hipMalloc(&tacc, 8 * s->points[axis] * sizeof(double2))) || (e = hipEventCreate(&e0)) ||
+        (e = hipEventCreate(&e1)) || (e = hipMemset(tb0, 0, s->cells * sizeof(float2))) ||
+        (e = hipMemset(tb1, 0, s->cells * sizeof(float2))) ||
+        (e = hipMemset(tacc, 0, 8 * s->points[axis] * sizeof(double2)))) {
         release();
-        return hip_fail(s, e, "autotune scratch");
+        return hip_fail(s, e, "timing scratch");
     }
-    for (int a = 0; a < 3 && !e; ++a) e = hipMalloc(&tacc[a], 8 * s->points[a] * sizeof(double2));
-    if (!e) e = hipMemset(tb0, 0, s->cells * sizeof(float2));
-    if (!e) e = hipMemset(tb1, 0, s->cells * sizeof(float2));
-    for (int a = 0; a < 3 && !e; ++a) e = hipMemset(tacc[a], 0, 8 * s->points[a] * sizeof(double2));
     // a step inside the DFT window: the slower form of every pass
     int64_t win = s->prob.dft_end > s->prob.dft_begin ? s->prob.dft_begin : 0;
     if (win >= s->tab_cap) win = 0;
     const int64_t c0[2] = {win, std::numeric_limits<int64_t>::max()};
-    if (!e) e = hipMemcpy(tctr, c0, sizeof(c0), hipMemcpyHostToDevice);
-    if (e) {
+    if ((e = hipMemcpy(tctr, c0, sizeof(c0), hipMemcpyHostToDevice))) {
         release();
-        return hip_fail(s, e, "autotune scratch");
+        return hip_fail(s, e, "timing scratch");
     }
-    for (int axis = 0; axis < 3 && !st; ++axis) {
-        const bool seg = s->prob.sub_core[axis] > 0;
-        int ids[16];
-        const int nv = std::min(16, pass_variants(local_len(s->prob, axis), seg, ids, 16));
-        if (nv <= 1) continue;
-        float best = 1e30f;
-        int best_id = s->variant[axis];
-        for (int k = 0; k < nv && !st; ++k) {
-            PassArgs a;
-            const int keep = s->variant[axis];
-            s->variant[axis] = ids[k];
-            solver_args(s, axis, a);
-            s->variant[axis] = keep;
-            a.buf[0] = tb0;
-            a.buf[1] = tb1;
-            a.L = tL;
-            a.acc = tacc[axis];
-            a.ctr = tctr;
-            const int off[2] = {0, a.tiles};
-            float ms = 0;
-            if (!e) e = hipMemcpy(tdesc, &a, sizeof(a), hipMemcpyHostToDevice);
-            if (!e) e = hipMemcpy(toff, off, sizeof(off), hipMemcpyHostToDevice);
-            if (!e) e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
-            if (!e) e = hipEventRecord(e0, s->stream);
-            for (int r = 0; r < reps && !e; ++r) e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
-            if (!e) e = hipEventRecord(e1, s->stream);
-            if (!e) e = hipEventSynchronize(e1);
-            if (!e) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e) {
-                st = hip_fail(s, e, "autotune");
-                break;
-            }
-            if (ms < 0.97f * best) {  // a later shape must win clearly: stable choices
-                best = ms;
-                best_id = ids[k];
-            }
-        }
-        s->variant[axis] = best_id;
+    const bool seg = s->prob.sub_core[axis] > 0;
+    for (int k = 0; k < n && !e; ++k) {
+        PassArgs a;
+        const int keep = s->variant[axis];
+        s->variant[axis] = ids[k];
+        solver_args(s, axis, a);
+        s->variant[axis] = keep;
+        a.buf[0] = tb0;
+        a.buf[1] = tb1;
+        a.L = tL;
+        a.acc = tacc;
+        a.ctr = tctr;
+        float ms = 0;
+        e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
+        if (!e) e = hipEventRecord(e0, s->stream);
+        for (int r = 0; r < reps && !e; ++r) e = launch_variant_single(ids[k], seg, axis, a, 0, s->stream);
+        if (!e) e = hipEventRecord(e1, s->stream);
+        if (!e) e = hipEventSynchronize(e1);
+        if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+        ms_out[k] = ms / reps;
     }
     release();
-    if (st) return st;
+    if (e) return hip_fail(s, e, "pass timing");
+    return PSTD_OK;
+}
+
+pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
+    // time every compiled tile shape of each axis and keep the fastest
+    for (int axis = 0; axis < 3; ++axis) {
+        const bool seg = s->prob.sub_core[axis] > 0;
+        int ids[16];
+        float ms[16];
+        const int nv = std::min(16, pass_variants(local_len(s->prob, axis), seg, ids, 16));
+        if (nv <= 1) continue;
+        pstd_status st = time_shapes(s, axis, ids, nv, reps, ms);
+        if (st) return st;
+        int best = 0;
+        for (int k = 1; k < nv; ++k)
+            if (ms[k] < 0.97f * ms[best]) best = k;  // a later shape must win clearly: stable choices
+        s->variant[axis] = ids[best];
+    }
     solver_drop_graph(s);
     return upload_descs(s);
 }
@@ -685,29 +684,48 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     adjoint_invalidate(s);
     pstd_status st = solver_ensure_tables(s, s->step + n_steps);
     if (st) return st;
-    hipEvent_t ev[6];
-    for (int i = 0; i < 6; ++i) HIP_TRY(s, hipEventCreate(&ev[i]));
+    // one pair of events around every pass launch, all steps queued back to
+    // back (as pstd_run does), read after the last one
+    std::vector<hipEvent_t> ev(6 * (size_t)n_steps, nullptr);
+    auto destroy = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev)
+        if (hipError_t r = hipEventCreate(&e)) {
+            destroy();
+            return hip_fail(s, r, "hipEventCreate");
+        }
     double sum[3] = {0, 0, 0};
     int64_t done = 0;
-    for (; done < n_steps && !st; ++done) {
-        st = launch_steps(s, s->stream, 1, ev);
+    for (; done < n_steps; ++done) {
+        st = launch_steps(s, s->stream, 1, &ev[6 * (size_t)done]);
         if (st) break;
-        hipError_t e = hipEventSynchronize(ev[5]);
-        if (e) {
-            st = hip_fail(s, e, "event sync");
-            break;
-        }
+    }
+    if (!st && done > 0) {
+        hipError_t e = hipEventSynchronize(ev[6 * (size_t)(done - 1) + 5]);
+        if (e) st = hip_fail(s, e, "event sync");
+    }
+    for (int64_t k = 0; k < done && !st; ++k)
         for (int a = 0; a < 3; ++a) {
             float ms = 0;
-            (void)hipEventElapsedTime(&ms, ev[2 * a], ev[2 * a + 1]);
+            (void)hipEventElapsedTime(&ms, ev[6 * (size_t)k + 2 * a], ev[6 * (size_t)k + 2 * a + 1]);
             sum[a] += ms;
         }
-    }
-    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    destroy();
     solver_account_steps(s, s->step, s->step + done);
     s->step += done;
     for (int a = 0; a < 3; ++a) pass_ms[a] = sum[a];
     return st;
+}
+
+pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* us_out) {
+    if (!s || !us_out || axis < 0 || axis > 2 || reps < 1) return PSTD_EINVAL;
+    float ms = 0;
+    pstd_status st = time_shapes(s, axis, &s->variant[axis], 1, reps, &ms);
+    if (st) return st;
+    *us_out = 1e3 * ms;
+    return PSTD_OK;
 }
 
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps) {
@@ -861,6 +879,7 @@ pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n)
     int64_t need;
     pstd_surface_size(s, &need);
     if (n != need) return fail(s, PSTD_EINVAL, "output size must equal pstd_surface_size");
+    if (s->sphere) return fail(s, PSTD_ESTATE, "the problem integrates over the sphere (pstd_get_sphere_phasors)");
     if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     hipError_t e = finalize_phasors(s->acc, s->points, 1.0 / s->inc_sum, (double2*)out_dev, s->stream);
     if (e) return hip_fail(s, e, "finalize_phasors");
@@ -937,6 +956,7 @@ pstd_status pstd_destroy(pstd_solver* s) {
     (void)hipFree(s->sigma_tab);
     (void)hipFree(s->w_tab);
     (void)hipFree(s->dft_tab);
+    (void)hipFree(s->dft_zero);
     if (s->owns_ctr) (void)hipFree(s->ctr);
     for (int a = 0; a < 3; ++a) (void)hipFree(s->acc[a]);
     project_free(s->proj);

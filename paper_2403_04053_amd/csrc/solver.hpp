@@ -39,6 +39,7 @@ struct pstd_solver {
     float2* sigma_tab = nullptr;
     double2* w_tab = nullptr;
     int* dft_tab = nullptr;
+    int* dft_zero = nullptr;  // all zeros: the passes' box DFT is off with a spherical surface
     int64_t tab_cap = 0;
     int tab_gen = 0;       // bumped whenever the tables move
     // device counters (step, end); owned unless the solver belongs to a batch
