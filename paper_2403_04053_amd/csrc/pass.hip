@@ -216,19 +216,26 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     const int pA = AXIS == 0 ? t / N2 : t % P;
     const int n2 = AXIS == 0 ? t % N2 : t / P;
 
+    // Workgroups are dealt round-robin to the 8 XCDs (blockIdx mod 8); give
+    // each XCD a contiguous run of tiles instead, so that neighbouring tiles,
+    // which share cache lines (the 4-byte potential of a 16-pencil tile is
+    // half a 128-byte line), meet in the same L2.  A bijection of [0, G).
+    const int G = (int)gridDim.x, gb = (int)blockIdx.x, xcd = gb & 7;
+    const int gt = xcd * (G >> 3) + min(xcd, G & 7) + (gb >> 3);
+
     // instance of this workgroup (uniform), its tile, its step: the base
     // counter plus this launch's offset in its group of steps
     Fields f;
     int tile;
     if constexpr (!MULTI) {
         f = fields<AXIS>(single);
-        tile = (int)blockIdx.x;
+        tile = gt;
     } else {
         int inst = 0;
         for (int i = 1; i < ninst; ++i)
-            if ((int)blockIdx.x >= off[i]) inst = i;
+            if (gt >= off[i]) inst = i;
         f = fields<AXIS>(descs[inst]);
-        tile = (int)blockIdx.x - off[inst];
+        tile = gt - off[inst];
     }
     const int64_t nstep = f.ctr[0] + koff;
     if (nstep >= f.ctr[1]) return;  // whole workgroup, before any barrier
