@@ -105,7 +105,7 @@ def main():
     if args.workload == "subdomain":
         return bench_subdomain(args)
 
-    prob, V = synth.cfg2(n_fft=args.n)
+    prob, V = synth.square_barrier_160(n_fft=args.n)
     # spherical equivalence surface of radius 5; the whole timed region sits
     # inside the surface-DFT window
     prob = prob.replace(dft_begin=0, dft_end=10 ** 12, surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
@@ -194,7 +194,7 @@ def bench_batch(args):
 
     import paper_2403_04053_amd as P
     import synth
-    inst = synth.cfg4_instances()
+    inst = synth.uneven_batch()
     stream = torch.cuda.current_stream()
     b = P.Batch([p for p, _ in inst], stream=stream)
     for i, (_, V) in enumerate(inst):
@@ -241,7 +241,7 @@ def bench_adjoint(args):
 
     import paper_2403_04053_amd as P
     import synth
-    prob, V0, Vh = synth.cfg5()
+    prob, V0, Vh = synth.voxel_potential_160()
     N = args.adj_steps
     prob = prob.replace(dft_end=N)
     n_ck = max(1, math.ceil(math.sqrt(N)))
@@ -342,7 +342,7 @@ def bench_subdomain(args):
 
     import paper_2403_04053_amd as P
     import synth
-    prob, V = synth.cfg3_global()
+    prob, V = synth.bumps_288()
     stream = torch.cuda.current_stream()
     s = P.Solver(prob, stream=stream)
     s.set_potential(V.astype(np.float32))
@@ -393,7 +393,7 @@ def bench_project(args):
 
     import paper_2403_04053_amd as P
     import synth
-    prob, V = synth.cfg2()
+    prob, V = synth.square_barrier_160()
     prob = prob.replace(dft_begin=0, dft_end=10 ** 12)
     stream = torch.cuda.current_stream()
     s = P.Solver(prob, stream=stream)

@@ -52,7 +52,6 @@ struct AdjointState {
     double2* seed = nullptr;     // g_o = (|T_o|^2 - I_o) T_o
     double* J = nullptr;
     float2* inj = nullptr;       // conj(G^H g) / Phi_inc, phasor layout
-    int64_t inj_n = 0;
     // step tables
     int* dft_off = nullptr;              // [N] zeros: recompute steps skip the DFT
     float2** stash = nullptr;            // [N] recompute: where psi^{n+1} goes
@@ -60,7 +59,6 @@ struct AdjointState {
     int* dft_adj = nullptr;              // [N] m inside the window
     const float2** fwd_adj = nullptr;    // [N] psi^{m-1}
     int64_t* ctr_adj = nullptr;
-    int64_t tab_n = 0;
     bool valid = false;                  // a forward run matches the solver state
 };
 
@@ -271,7 +269,6 @@ pstd_status pstd_misfit_forward(pstd_solver* s, int64_t n_steps, const double* o
         a->n_obs = n_obs;
         int64_t inj_n = 0;
         for (int f = 0; f < 6; ++f) inj_n += 2 * s->points[f / 2];
-        a->inj_n = inj_n;
         hipError_t e;
         if ((e = alloc(&a->ck, (size_t)nck * 2 * cells)) || (e = alloc(&a->last, (size_t)2 * cells)) ||
             (e = alloc(&a->store, (size_t)std::max<int64_t>(S - 1, 1) * cells)) ||
@@ -286,7 +283,6 @@ pstd_status pstd_misfit_forward(pstd_solver* s, int64_t n_steps, const double* o
             pstd::adjoint_free(s);
             return hfail(s, e, "hipMalloc adjoint state");
         }
-        a->tab_n = n_steps;
     }
     a->valid = false;
     ADJ_TRY(s, hipMemcpyAsync(a->obs, obs_dev, n_obs * sizeof(double3), hipMemcpyDeviceToDevice, s->stream));

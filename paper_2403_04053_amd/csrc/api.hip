@@ -243,21 +243,8 @@ pstd_status build_tables(pstd_solver* s) {
 
 
 // ---------------------------------------------------------------------------
-// per-step tables and descriptors
+// per-step launches
 // ---------------------------------------------------------------------------
-
-pstd_status upload_descs(pstd_solver* s) {
-    pstd::PassArgs a[3];
-    int off[6];
-    for (int axis = 0; axis < 3; ++axis) {
-        pstd::solver_args(s, axis, a[axis]);
-        off[2 * axis] = 0;
-        off[2 * axis + 1] = a[axis].tiles;
-    }
-    HIP_TRY(s, hipMemcpy(s->desc, a, sizeof(a), hipMemcpyHostToDevice));
-    HIP_TRY(s, hipMemcpy(s->off, off, sizeof(off), hipMemcpyHostToDevice));
-    return PSTD_OK;
-}
 
 // launch the three passes of step ctr[0] + koff on `stream`
 pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent_t* ev) {
@@ -394,7 +381,7 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     s->tab_cap = cap;
     s->tab_gen += 1;
     solver_drop_graph(s);  // the graph's launches hold the old table addresses
-    return upload_descs(s);
+    return PSTD_OK;
 }
 
 void solver_account_steps(pstd_solver* s, int64_t from, int64_t to) {
@@ -438,8 +425,7 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     };
     hipError_t e;
     if ((e = hipMalloc(&s->buf[0], s->cells * sizeof(float2))) || (e = hipMalloc(&s->buf[1], s->cells * sizeof(float2))) ||
-        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))) ||
-        (e = hipMalloc(&s->desc, 3 * sizeof(pstd::PassArgs))) || (e = hipMalloc(&s->off, 6 * sizeof(int))))
+        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))))
         return cleanup(hip_fail(s, e, "hipMalloc state"));
     if (ext_ctr) {
         s->ctr = ext_ctr;
@@ -545,7 +531,7 @@ pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
         s->variant[axis] = ids[best];
     }
     solver_drop_graph(s);
-    return upload_descs(s);
+    return PSTD_OK;
 }
 
 }  // namespace pstd
@@ -754,7 +740,7 @@ pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t penc
             HIP_TRY(s, hipStreamSynchronize(s->stream));
             s->variant[axis] = ids[k];
             solver_drop_graph(s);
-            return upload_descs(s);
+            return PSTD_OK;
         }
     }
     return fail(s, PSTD_EUNSUPPORTED, "no compiled tile shape with that factor and pencil count");
@@ -951,8 +937,6 @@ pstd_status pstd_destroy(pstd_solver* s) {
     (void)hipFree(s->L);
     (void)hipFree(s->v2);
     (void)hipFree(s->tables);
-    (void)hipFree(s->desc);
-    (void)hipFree(s->off);
     (void)hipFree(s->sigma_tab);
     (void)hipFree(s->w_tab);
     (void)hipFree(s->dft_tab);

@@ -45,9 +45,6 @@ struct pstd_solver {
     // device counters (step, end); owned unless the solver belongs to a batch
     int64_t* ctr = nullptr;
     bool owns_ctr = true;
-    // pass descriptors in device memory: desc[3], then off[3][2]
-    pstd::PassArgs* desc = nullptr;
-    int* off = nullptr;
     // graph of kGraphSteps steps, replayed on `stream`
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;

@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "square_barrier", "gaussian_bumps", "smoothed_prior",
-    "cfg1", "cfg1_refined", "cfg2", "cfg3_global", "cfg4_instances", "cfg5", "tiny", "fresnel_plane", "fd_voxels",
+    "plain_barrier", "plain_barrier_refined", "square_barrier_160", "bumps_288", "uneven_batch", "voxel_potential_160", "tiny", "fresnel_plane", "fd_voxels",
     "paper_u0",
 ]
 
@@ -181,7 +181,7 @@ def smoothed_prior(n, core_lo, core_hi, std, sigma_cells, seed):
 # workloads
 # ----------------------------------------------------------------------------
 
-def cfg1():
+def plain_barrier():
     """Square barrier r = 0.6, V0 = 0.5 E0, k0 = pi/(4h) along +z; 32^3 cells
     inside an 8-cell absorber (FFT grid 48^3).  6649 steps at 0.9 of the
     critical step cover T = 4.0; the phasor window is the last 4 periods."""
@@ -199,7 +199,7 @@ def cfg1():
     return prob, V
 
 
-def cfg1_refined():
+def plain_barrier_refined():
     """The plain-method barrier (r = 0.6, V0 = E0/2, k0 = pi/(4h0), h0 = 0.1)
     at half the spacing, h = 0.05, with an absorber twice as wide (32 cells,
     1.6 length units) and the same time T = 4.0: FFT grid 128^3, TF/SF walls
@@ -221,7 +221,7 @@ def cfg1_refined():
     return prob, V
 
 
-def cfg2(n_fft=160):
+def square_barrier_160(n_fft=160):
     """Square barrier r = 2.4, V0 = 0.5 E0; 128^3 cells inside a 16-cell absorber
     (FFT grid 160^3); box surface at i = 40, 120."""
     h = 0.1
@@ -240,7 +240,7 @@ def cfg2(n_fft=160):
     return prob, V
 
 
-def cfg3_global(n_fft=288, seed=3):
+def bumps_288(n_fft=288, seed=3):
     """32 anisotropic Gaussian bumps (centres in a radius-8 ball, sigma in
     U[0.3, 1.2], heights N(0, 0.3 E0)) on a 256^3 interior (FFT grid 288^3)."""
     h = 0.1
@@ -260,10 +260,10 @@ def cfg3_global(n_fft=288, seed=3):
     return prob, V
 
 
-CFG4_LENGTHS = (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192)
+BATCH_LENGTHS = (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192)
 
 
-def cfg4_instances(count=64, seed=4, lengths=CFG4_LENGTHS):
+def uneven_batch(count=64, seed=4, lengths=BATCH_LENGTHS):
     """Uneven batched instances: per-axis FFT lengths drawn from `lengths`,
     isotropic incident directions, k0 ~ U[pi/(8h), pi/(3h)], Gaussian bumps
     scaled to each instance's TF core."""
@@ -295,7 +295,7 @@ def cfg4_instances(count=64, seed=4, lengths=CFG4_LENGTHS):
     return out
 
 
-def cfg5(seed_prior=5, seed_hidden=55, n_fft=160):
+def voxel_potential_160(seed_prior=5, seed_hidden=55, n_fft=160):
     """Voxel potential on the TF core of a 128^3 interior (FFT grid 160^3):
     smoothed N(0, 0.1 E0) prior and a hidden potential from the same recipe."""
     h = 0.1

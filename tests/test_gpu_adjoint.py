@@ -173,7 +173,7 @@ def test_full_size_gradient_finite_differences(P):
     voxels with the largest gradient.  FD in FP32 has a noise floor near
     5e-7 in J differences, so the step is large (5e-2 E0) and the bar 1e-2."""
     import math
-    prob, V0, Vh = synth.cfg5()
+    prob, V0, Vh = synth.voxel_potential_160()
     N = 600
     prob = prob.replace(dft_end=N)
     pts = synth.fresnel_plane(128, prob.h[0], 39.2)

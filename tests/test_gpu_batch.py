@@ -98,7 +98,7 @@ def _sampled_check(prob, V, got, prev, cur, step, seed):
 
 @pytest.mark.parametrize("mode", ["single", "single_tuned", "batch_of_one"])
 def test_uneven_instance_alone(P, mode):
-    prob, V = synth.cfg4_instances(count=1)[0]
+    prob, V = synth.uneven_batch(count=1)[0]
     Vf = V.astype(np.float32).astype(np.float64)
     prev = synth.random_state(prob.n, 100).astype(np.complex64)
     cur = synth.random_state(prob.n, 200).astype(np.complex64)
@@ -125,7 +125,7 @@ def test_uneven_batch_full_size_sampled(P):
     """The uneven-grid workload at its real size (64 instances, grid lengths
     96..192): three instances start from random states; one batched step is
     checked on sampled cells against the oracle."""
-    inst = synth.cfg4_instances()
+    inst = synth.uneven_batch()
     batch = P.Batch([p for p, _ in inst])
     for i, (_, V) in enumerate(inst):
         batch.set_potential(i, V.astype(np.float32))

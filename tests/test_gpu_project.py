@@ -87,7 +87,7 @@ def test_points_inside_box_rejected(P, run_small):
 def test_plain_method_against_partial_waves(P):
     """The square barrier of radius 0.6, V0 = E0/2 at 8 points per wavelength
     (FFT grid 48^3): far-field amplitude against the partial-wave series."""
-    prob, V = synth.cfg1()
+    prob, V = synth.plain_barrier()
     s = P.Solver(prob)
     s.set_potential(V)
     s.run(prob.n_steps)
@@ -111,7 +111,7 @@ def test_refined_plain_method_within_one_percent(P):
     wavelength spacing of the plain-method workload the same measure is 3.5 %,
     which is the method's discretisation error at that spacing (the error
     falls by about h^3 once the absorber is wide enough)."""
-    prob, V = synth.cfg1_refined()
+    prob, V = synth.plain_barrier_refined()
     print(f"refined plain method: grid {prob.n}, {prob.n_steps} steps", flush=True)
     s = P.Solver(prob)
     s.set_potential(V)

@@ -130,7 +130,7 @@ def test_square_barrier_sphere_far_field(P):
     """The 160^3 square-barrier workload run in full with the sphere of
     radius 5: the far field from the sphere against the box and the
     partial-wave series of the barrier."""
-    prob, V = synth.cfg2()
+    prob, V = synth.square_barrier_160()
     prob = prob.replace(surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
     print(f"square barrier with sphere: grid {prob.n}, {prob.n_steps} steps", flush=True)
     s = P.Solver(prob)

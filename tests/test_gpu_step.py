@@ -106,7 +106,7 @@ def test_full_size_single_step_sampled(P, n):
     """At the benchmark size, one GPU step against the oracle evaluated on the
     three pencils through each sampled cell (plus the plane phasors there)."""
     if n == (160, 160, 160):
-        prob, V = synth.cfg2()
+        prob, V = synth.square_barrier_160()
     else:
         prob, V = synth.tiny(n=n, P=16, transition=4, v0=0.5, radius_cells=10)
     prob = prob.replace(ramp_periods=0.5, dft_begin=0, dft_end=10 ** 9)

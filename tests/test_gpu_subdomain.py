@@ -86,7 +86,7 @@ def test_subdomain_run_and_phasors(P):
 def test_subdomain_full_size_sampled(P):
     """The non-central workload at its real size: 288^3 global grid as
     216 subdomains of 64^3 (core 48, halo 8)."""
-    prob, V = synth.cfg3_global()
+    prob, V = synth.bumps_288()
     prob = prob.replace(ramp_periods=0.5)
     V = V.astype(np.float32).astype(np.float64)
     s = P.Solver(prob)

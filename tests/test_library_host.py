@@ -32,9 +32,9 @@ def test_status_strings():
         assert lib_mod.pstd_status_string(code) == name
 
 
-@pytest.mark.parametrize("cfg", [synth.cfg1, lambda: synth.tiny(n=(24, 20, 32), P=3, transition=2)])
-def test_reduced_step_matches_oracle(cfg):
-    prob = cfg()[0]
+@pytest.mark.parametrize("make", [synth.plain_barrier, lambda: synth.tiny(n=(24, 20, 32), P=3, transition=2)])
+def test_reduced_step_matches_oracle(make):
+    prob = make()[0]
     p = lib_mod.problem_from(prob)
     dtau, eta = lib_mod.pstd_reduced_step(p)
     assert dtau == pytest.approx(opstd.dtau_of(prob), rel=1e-14)
@@ -57,7 +57,7 @@ def _expect(status_name, prob):
 
 
 def test_create_rejects_bad_geometry_before_touching_the_device():
-    prob, _ = synth.cfg1()
+    prob, _ = synth.plain_barrier()
     _expect("PSTD_EINVAL", prob.replace(n=(47, 48, 48)))
     _expect("PSTD_EINVAL", prob.replace(surf_lo=(13, 10, 10)))       # face inside the taper
     _expect("PSTD_EINVAL", prob.replace(surf_hi=(38, 35, 38)))
@@ -70,14 +70,14 @@ def test_create_rejects_bad_geometry_before_touching_the_device():
 def test_create_rejects_unstable_step():
     """The plain-method workload's literal dt = 0.1 dx^2 is above the bound of
     Eq. PSTDstability and is refused unless forced."""
-    prob, _ = synth.cfg1()
+    prob, _ = synth.plain_barrier()
     _expect("PSTD_EUNSTABLE", prob.replace(dt=0.1 * 0.1 ** 2))
     ok = lib_mod.problem_from(prob.replace(dt=0.99 * opstd.critical_dt(prob, prob.v_max)))
     assert lib_mod.pstd_reduced_step(ok)[0] > 0
 
 
 def test_subdomain_validation():
-    prob, _ = synth.cfg3_global()
+    prob, _ = synth.bumps_288()
     p = lib_mod.problem_from(prob)
     assert list(p.sub_core) == [48, 48, 48] and p.sub_halo == 8 and p.sub_taper == 3
     _expect("PSTD_EINVAL", prob.replace(sub_taper=4))                       # halo < taper + 5

@@ -100,7 +100,7 @@ def test_growth_above_the_bound(factor):
 def test_growth_at_the_literal_workload_step():
     """dt = 0.1 dx^2 (the plain-method workload's literal step) exceeds the
     bound: the corner mode grows by about 2.6 per step."""
-    prob, _ = synth.cfg1()
+    prob, _ = synth.plain_barrier()
     E0 = pstd.central_energy(prob)
     dtau = E0 * 0.1 * 0.1 ** 2
     lam = math.pi ** 2 * float(np.sum(1 / pstd.dxbar(prob) ** 2)) + 0.5

@@ -33,7 +33,7 @@ def test_lagrange_reproduces_polynomials():
 
 @pytest.fixture(scope="module")
 def sph():
-    prob, _ = synth.cfg2()
+    prob, _ = synth.square_barrier_160()
     return prob, osph.Sphere(prob, 5.0, n_theta=64, n_phi=128)
 
 
@@ -99,3 +99,20 @@ def test_grid_interpolation_at_benchmark_spacing(sph):
     ff = s.far_field(v, dn, dirs)
     ref = np.exp(-1j * dirs @ x0) / prob.k0
     assert np.abs(ff - ref).max() < 2e-3 * np.abs(ref).max()
+
+
+def test_shell_dft_removes_the_incident_part_exactly():
+    """Feeding the shell DFT the incident part zeta psi_inc alone (ramped,
+    oblique) leaves zero scattered phasor."""
+    from oracle import pstd as opstd
+    prob, _ = synth.tiny(n=(24, 24, 32), P=3, transition=3, theta=0.5, phi=0.8, steps=60, dft=(0, 60))
+    prob = prob.replace(ramp_periods=0.5)
+    V = np.zeros((prob.n[2], prob.n[1], prob.n[0]))
+    m = opstd.build(prob, V)
+    s = osph.Sphere(prob, 0.6, n_theta=8, n_phi=16, order=4)
+    sd = osph.ShellDFT(m, s)
+    for n in range(60):
+        tau = n * m.dtau
+        sd.accumulate(m.zeta * m.phase * opstd.ramp(tau, m.tau_r) * np.exp(-1j * tau), n)
+    assert np.abs(sd.normalized()).max() < 1e-13
+    assert (m.zeta[s.shell_mask()] > 0).any()   # the stencils do reach into the taper

@@ -107,7 +107,7 @@ def test_pstd_bound_smaller_than_fdtd8():
 
 
 def test_physical_and_reduced_bounds_agree():
-    prob, _ = synth.cfg1()
+    prob, _ = synth.plain_barrier()
     E0 = pstd.central_energy(prob)
     dt = pstd.critical_dt(prob, prob.v_max)
     dtau = pstd.critical_dtau(pstd.dxbar(prob), prob.v_max / E0)
