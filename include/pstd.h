@@ -151,6 +151,12 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host
  * scratch cannot be allocated. */
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
 
+/* Failure detection: *norm2_out_host = sum over the cells of |psi^step|^2
+ * (FP64; compare it between calls to watch for growth).  ENONFINITE if
+ * psi^step or psi^{step-1} holds a NaN or Inf (e.g. a step forced above the
+ * bound of Eq. PSTDstability with force_dt).  Synchronises. */
+pstd_status pstd_check_state(pstd_solver* s, double* norm2_out_host);
+
 /* Average duration (microseconds) of one launch of the pass along `axis`
  * with its current tile shape: `reps` back-to-back launches on scratch
  * buffers of the solver's size, bracketed by HIP events on the solver's

@@ -15,7 +15,7 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_pass_time", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_far_field", "pstd_pass_time", "pstd_check_state", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -138,6 +138,7 @@ _SIGS = {
     "pstd_destroy": [_vp],
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_pass_time": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "pstd_check_state": [_vp, ctypes.POINTER(ctypes.c_double)],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "pstd_set_tile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "pstd_tile_variants": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
@@ -300,6 +301,12 @@ def pstd_misfit_backward(solver, out_dev, n_cells):
     _check(lib.pstd_misfit_backward(solver, _ptr(out_dev), int(n_cells)), solver)
 
 
+def pstd_check_state(solver):
+    out = ctypes.c_double()
+    _check(lib.pstd_check_state(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
 def pstd_pass_time(solver, axis, reps=50):
     out = ctypes.c_double()
     _check(lib.pstd_pass_time(solver, int(axis), int(reps), ctypes.byref(out)), solver)
@@ -428,6 +435,10 @@ class Solver:
 
     def tiles(self):
         return [pstd_tile_info(self.handle, a) for a in range(3)]
+
+    def check_state(self):
+        """sum |psi|^2 (FP64); raises PstdError ENONFINITE on NaN / Inf."""
+        return pstd_check_state(self.handle)
 
     def pass_time(self, axis, reps=50):
         """Average microseconds per launch of one axis pass (pstd_pass_time)."""

@@ -705,6 +705,25 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     return st;
 }
 
+pstd_status pstd_check_state(pstd_solver* s, double* norm2_out) {
+    if (!s || !norm2_out) return PSTD_EINVAL;
+    const int m = norm_scratch_doubles();
+    double* d = nullptr;
+    HIP_TRY(s, hipMalloc(&d, 2 * m * sizeof(double)));
+    double h[2] = {0, 0};
+    hipError_t e = launch_norm(s->buf[s->step & 1], s->cells, d, s->stream);          // psi^n
+    if (!e) e = launch_norm(s->buf[(s->step + 1) & 1], s->cells, d + m, s->stream);   // psi^{n-1}
+    if (!e) e = hipMemcpyAsync(&h[0], d, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (!e) e = hipMemcpyAsync(&h[1], d + m, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (!e) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e) return hip_fail(s, e, "state check");
+    *norm2_out = h[0];
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+        return fail(s, PSTD_ENONFINITE, "the wave function holds NaN or Inf values");
+    return PSTD_OK;
+}
+
 pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* us_out) {
     if (!s || !us_out || axis < 0 || axis > 2 || reps < 1) return PSTD_EINVAL;
     float ms = 0;

@@ -79,6 +79,10 @@ hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs
 hipError_t launch_variant_adjoint(int v, int axis, const PassArgs& args, int koff, hipStream_t stream);
 // acc64[i] += acc32[i]; acc32[i] = 0
 hipError_t launch_fold(double* acc64, float* acc32, int64_t n, hipStream_t stream);
+// scratch[0] = sum |psi[i]|^2 (FP64) over n cells; scratch holds
+// norm_scratch_doubles() doubles
+int norm_scratch_doubles();
+hipError_t launch_norm(const float2* psi, int64_t n, double* scratch, hipStream_t stream);
 // out[i] = (float)(scale * acc64[i])
 hipError_t launch_scale_out(const double* acc64, double scale, float* out, int64_t n, hipStream_t stream);
 // advance the step counters of count instances by `by` steps, never past

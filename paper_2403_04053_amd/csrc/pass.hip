@@ -26,6 +26,8 @@
 // into segments of C core points; each segment is transformed as a local
 // array of N = C + 2H points read from the global array with the halo
 // weights, and only its core points are written.
+#include <algorithm>
+
 #include "dft.hpp"
 #include "internal.hpp"
 
@@ -616,6 +618,51 @@ hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs
 hipError_t launch_variant_adjoint(int v, int axis, const PassArgs& args, int koff, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants) return hipErrorInvalidValue;
     return kVariants[v].adj(axis, args, koff, stream);
+}
+
+// sum |psi|^2 in FP64: per-workgroup partial sums, then one workgroup adds
+// them (no atomics; a NaN or Inf anywhere makes the sum non-finite)
+constexpr int kNormThreads = 256;
+constexpr int kNormBlocks = 1024;
+
+__global__ __launch_bounds__(kNormThreads) void norm_partial_kernel(const float2* __restrict__ psi, int64_t n,
+                                                                    double* __restrict__ part) {
+    __shared__ double red[kNormThreads];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNormThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNormThreads) {
+        const float2 v = psi[i];
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kNormThreads) void norm_final_kernel(const double* __restrict__ part, int n,
+                                                                  double* __restrict__ out) {
+    __shared__ double red[kNormThreads];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kNormThreads) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+int norm_scratch_doubles() { return kNormBlocks + 1; }
+
+hipError_t launch_norm(const float2* psi, int64_t n, double* scratch, hipStream_t stream) {
+    const int blocks = (int)std::min<int64_t>(kNormBlocks, (n + kNormThreads - 1) / kNormThreads);
+    hipLaunchKernelGGL(norm_partial_kernel, dim3(blocks), dim3(kNormThreads), 0, stream, psi, n, scratch + 1);
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormThreads), 0, stream, scratch + 1, blocks, scratch);
+    return hipGetLastError();
 }
 
 __global__ void fold_kernel(double* __restrict__ acc64, float* __restrict__ acc32, int64_t n) {

@@ -188,3 +188,34 @@ def test_rerun_is_bitwise_deterministic(P):
         outs.append((s.psi(0).cpu().numpy(), s.phasors().cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_check_state_norm_and_blow_up(P):
+    """pstd_check_state: the FP64 norm of psi^n against the oracle's, and
+    ENONFINITE once a run forced above the stability bound of Eq.
+    PSTDstability has blown up (forced from the host: dt = 1.2 dt_crit)."""
+    prob, V = synth.tiny(n=(24, 24, 24), steps=40)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(40)
+    got = s.check_state()
+    _, _, ref, _ = opstd.run(prob, V)
+    assert got == pytest.approx(float(np.sum(np.abs(ref) ** 2)), rel=1e-5)
+    s.close()
+    dt = 1.2 * opstd.critical_dt(prob, prob.v_max)
+    bad = P.Solver(prob.replace(dt=dt, force_dt=True))
+    bad.set_potential(V)
+    bad.set_state(synth.random_state(prob.n, 1).astype(np.complex64),
+                  synth.random_state(prob.n, 2).astype(np.complex64), 0)
+    norms = []
+    for _ in range(40):
+        bad.run(50)
+        try:
+            norms.append(bad.check_state())
+        except P.PstdError as e:
+            assert e.name == "PSTD_ENONFINITE"
+            break
+    else:
+        pytest.fail(f"no blow-up detected, norms {norms[-3:]}")
+    assert len(norms) == 0 or norms[-1] > 1e6 * norms[0]
+    bad.close()
