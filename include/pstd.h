@@ -147,8 +147,9 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host
  * candidate on scratch buffers of the solver's size; the solver's state is
  * not touched.  Candidates are tried in compiled order and a later one
  * replaces the current choice only when it is at least 3 % faster, so timing
- * noise does not flip the choice between runs.  Synchronises.  ENOMEM if the
- * scratch cannot be allocated. */
+ * noise does not flip the choice between runs.  Also captures the step graph
+ * of the chosen shapes, so that the next pstd_run does not.  Synchronises.
+ * ENOMEM if the scratch cannot be allocated. */
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
 
 /* Failure detection: *norm2_out_host = sum over the cells of |psi^step|^2
@@ -224,13 +225,15 @@ pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n);
  * relative to a unit-amplitude incident wave.  Points must lie outside the
  * box (outside the sphere with surface_kind 1, which sums the Kirchhoff
  * integral over the sphere's nodes instead).  ESTATE before any window
- * step. */
+ * step.  n_obs = 0 does nothing and returns PSTD_OK (the pointers may then
+ * be null). */
 pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_obs, double* psi_out_dev);
 
 /* Far-field amplitude f(r_hat) = lim r e^{-ikr} Psi (physical length units)
  * for n_dir unit directions (double[3] each): the cell formula in the limit
  * of Eq. FDTDfarfieldapprox (with surface_kind 1, the limit of the sphere's
- * Kirchhoff sum).  Output complex128. */
+ * Kirchhoff sum).  Output complex128.  n_dir = 0 does nothing and returns
+ * PSTD_OK (the pointers may then be null). */
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
 
 /*

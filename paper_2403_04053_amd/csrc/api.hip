@@ -448,7 +448,10 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
         return cleanup(hip_fail(s, e, "hipMemset"));
     for (int a = 0; a < 3; ++a)
         if ((e = hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMemset acc"));
-    if ((st = solver_ensure_tables(s, 1024))) return cleanup(st);
+    // per-step tables through the end of the DFT window (up to 2^18 steps),
+    // so a run of that length never reallocates them (and re-captures the graph)
+    const int64_t tab_steps = std::min<int64_t>(std::max<int64_t>(p->dft_end, 1024), int64_t(1) << 18);
+    if ((st = solver_ensure_tables(s, tab_steps))) return cleanup(st);
     if ((e = hipDeviceSynchronize())) return cleanup(hip_fail(s, e, "sync"));
     *out = s;
     return PSTD_OK;
@@ -735,7 +738,10 @@ pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* u
 
 pstd_status pstd_autotune(pstd_solver* s, int32_t reps) {
     if (!s || reps < 1) return PSTD_EINVAL;
-    return solver_autotune(s, reps);
+    pstd_status st = solver_autotune(s, reps);
+    // capture the step graph of the chosen shapes now, not in the next run
+    if (!st && !s->in_batch) st = build_graph(s);
+    return st;
 }
 
 pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host) {
@@ -908,7 +914,8 @@ pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n) 
 }
 
 pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
-    if (!s || !obs_dev || !out_dev || n_obs < 0) return PSTD_EINVAL;
+    if (!s || n_obs < 0 || (n_obs > 0 && (!obs_dev || !out_dev))) return PSTD_EINVAL;
+    if (n_obs == 0) return PSTD_OK;  // nothing to evaluate
     if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     if (s->sphere) {
         // the Kirchhoff integral holds outside the sphere only
@@ -931,7 +938,8 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, d
 }
 
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
-    if (!s || !dir_dev || !out_dev || n_dir < 0) return PSTD_EINVAL;
+    if (!s || n_dir < 0 || (n_dir > 0 && (!dir_dev || !out_dev))) return PSTD_EINVAL;
+    if (n_dir == 0) return PSTD_OK;  // nothing to evaluate
     if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     if (s->sphere) {
         hipError_t e = sphere_far_field(s, (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream);

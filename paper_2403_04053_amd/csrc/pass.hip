@@ -510,7 +510,9 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     X(180, 12, 15, 16, 0)       \
     X(192, 12, 16, 16, 0)       \
     X(256, 16, 16, 16, 0)       \
-    X(288, 16, 18, 16, 0)
+    X(288, 16, 18, 16, 0)       \
+    X(288, 18, 16, 16, 0)       \
+    X(288, 16, 18, 32, 0)
 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);

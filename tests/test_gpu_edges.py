@@ -1,0 +1,126 @@
+"""Edge cases of the stepping and projection calls through the C ABI: empty
+runs and empty observation sets, the split of a run into graph replays and
+single launches, and the step counter across calls."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pstd as opstd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available()
+    import paper_2403_04053_amd as mod
+    return mod
+
+
+def solver(P, prob, V):
+    s = P.Solver(prob)
+    s.set_potential(V)
+    return s
+
+
+def test_zero_steps_change_nothing(P):
+    prob, V = synth.tiny(n=(24, 20, 32), P=3, transition=2, v0=0.5, radius_cells=3, steps=40, dft=(0, 40))
+    print(f"zero steps: grid {prob.n}", flush=True)
+    s = solver(P, prob, V)
+    s.run(23)
+    psi0, psi1, ph = s.psi(0).clone(), s.psi(1).clone(), s.phasors().clone()
+    s.run(0)
+    assert s.step == 23
+    assert torch.equal(s.psi(0), psi0) and torch.equal(s.psi(1), psi1)
+    assert torch.equal(s.phasors(), ph)
+    s.close()
+
+
+@pytest.mark.parametrize("split", [(37,), (5, 16, 16), (1,) * 37, (16, 5, 16), (17, 20)])
+def test_any_split_of_a_run_is_bit_identical(P, split):
+    """Runs of 16 or more steps replay captured graphs, shorter remainders are
+    launched one step at a time; the device step counter makes every split
+    of the same 37 steps produce the same bits."""
+    prob, V = synth.tiny(n=(24, 24, 24), P=4, transition=3, v0=0.5, radius_cells=3, steps=37,
+                         theta=0.9, phi=0.3, dft=(10, 30))
+    print(f"split {split}: grid {prob.n}", flush=True)
+    ref = solver(P, prob, V)
+    ref.run(37)
+    s = solver(P, prob, V)
+    for k in split:
+        s.run(k)
+    assert s.step == ref.step == 37
+    assert torch.equal(s.psi(0), ref.psi(0))
+    assert torch.equal(s.psi(1), ref.psi(1))
+    assert torch.equal(s.phasors(), ref.phasors())
+    ref.close()
+    s.close()
+
+
+def test_autotune_keeps_state_and_results(P):
+    """The autotuner times shapes on scratch buffers and captures the step
+    graph: the state is untouched, and a run after it equals, bit for bit, a
+    run that switches to the same shapes by hand at the same step."""
+    prob, V = synth.tiny(n=(48, 40, 32), P=4, transition=4, v0=0.5, radius_cells=4, steps=40, dft=(0, 40))
+    V = V.astype(np.float32).astype(np.float64)
+    print(f"autotune: grid {prob.n}", flush=True)
+    a = solver(P, prob, V)
+    a.run(7)
+    before = a.psi(0).clone()
+    tiles = a.autotune(reps=2)
+    assert torch.equal(a.psi(0), before) and a.step == 7
+    a.run(33)
+    b = solver(P, prob, V)
+    b.run(7)
+    for ax, t in enumerate(tiles):
+        b.set_tile(ax, t[1], t[3])
+    b.run(33)
+    assert torch.equal(a.psi(0), b.psi(0))
+    _, _, cur, _ = opstd.run(prob, V)
+    got = a.psi(0).cpu().numpy()
+    assert np.linalg.norm(got - cur) / np.linalg.norm(cur) < 1e-4
+    a.close()
+    b.close()
+
+
+def _window_done(P, prob, V):
+    s = solver(P, prob, V)
+    s.run(prob.n_steps)
+    return s
+
+
+def test_empty_observation_sets(P):
+    prob, V = synth.tiny(n=(24, 24, 24), P=4, transition=3, v0=0.5, radius_cells=3, steps=30, dft=(10, 30))
+    print(f"empty sets (box): grid {prob.n}", flush=True)
+    s = _window_done(P, prob, V)
+    assert s.project(np.zeros((0, 3))).shape == (0,)
+    assert s.far_field(np.zeros((0, 3))).shape == (0,)
+    # null pointers with a zero count are accepted; a negative count is not
+    P.pstd_project(s.handle, None, 0, None)
+    P.pstd_far_field(s.handle, None, 0, None)
+    with pytest.raises(P.PstdError) as e:
+        P.pstd_project(s.handle, None, -1, None)
+    assert e.value.name == "PSTD_EINVAL"
+    with pytest.raises(P.PstdError) as e:
+        P.pstd_far_field(s.handle, None, 3, None)
+    assert e.value.name == "PSTD_EINVAL"
+    s.close()
+
+
+def test_empty_observation_sets_sphere(P):
+    h = 0.1
+    k0 = 2 * math.pi / (8 * h)
+    prob = synth.Problem(n=(48, 48, 48), h=(h,) * 3, k0=k0, abc_cells=(4,) * 3, abc_alpha=1.0,
+                         abc_U0=synth.paper_u0(1.0, k0 * h, 4), tfsf=((16, 19, 29, 32),) * 3,
+                         v_max=k0 * k0 / 2, ramp_periods=0.5, n_steps=40, dft_begin=20, dft_end=40,
+                         surf_lo=(14,) * 3, surf_hi=(34,) * 3, surface_kind=1, sphere_radius=0.95,
+                         sphere_nodes=(16, 32))
+    V = np.zeros((48, 48, 48))
+    print(f"empty sets (sphere): grid {prob.n}", flush=True)
+    s = _window_done(P, prob, V)
+    assert s.project(np.zeros((0, 3))).shape == (0,)
+    assert s.far_field(np.zeros((0, 3))).shape == (0,)
+    s.close()

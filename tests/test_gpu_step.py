@@ -101,12 +101,14 @@ def test_eta_on_source_flag(P):
     assert np.linalg.norm(got - cur) / np.linalg.norm(cur) < 1e-4
 
 
-@pytest.mark.parametrize("n", [(160, 160, 160), (100, 96, 108)])
+@pytest.mark.parametrize("n", [(160, 160, 160), (100, 96, 108), (288, 288, 288)])
 def test_full_size_single_step_sampled(P, n):
-    """At the benchmark size, one GPU step against the oracle evaluated on the
-    three pencils through each sampled cell (plus the plane phasors there)."""
-    if n == (160, 160, 160):
-        prob, V = synth.square_barrier_160()
+    """At the benchmark size (and at the largest compiled length on every
+    axis, in each of its tile shapes), one GPU step against the oracle
+    evaluated on the three pencils through each sampled cell (plus the plane
+    phasors there)."""
+    if n[0] in (160, 288):
+        prob, V = synth.square_barrier_160(n_fft=n[0])
     else:
         prob, V = synth.tiny(n=n, P=16, transition=4, v0=0.5, radius_cells=10)
     prob = prob.replace(ramp_periods=0.5, dft_begin=0, dft_end=10 ** 9)
@@ -127,10 +129,14 @@ def test_full_size_single_step_sampled(P, n):
     tf = prob.tfsf
     pts += [(tf[0][0] + 1, ny // 2, nz // 2), (nx // 2, tf[1][3] - 1, nz // 2), (nx // 2, ny // 2, tf[2][0] + 2)]
     ref = opstd.step_at(m, prev.astype(np.complex128), cur.astype(np.complex128), step, pts)
-    g = np.array([got[k, j, i] for (i, j, k) in pts])
     scale = np.abs(cur).max()
-    err = np.abs(g - ref).max() / scale
-    print(n, "sampled single-step max err / max|psi|", err)
+
+    def sampled_err(psi):
+        g = np.array([psi[k, j, i] for (i, j, k) in pts])
+        return np.abs(g - ref).max() / scale
+
+    err = sampled_err(got)
+    print(n, "sampled single-step max err / max|psi|", err, flush=True)
     assert err < 1e-5
     # surface DFT of psi^step: psi on the planes and the spectral normal derivative
     flat = s.phasors().cpu().numpy()
@@ -154,6 +160,16 @@ def test_full_size_single_step_sampled(P, n):
             d = offt.ifft(1j * m.kb[a] * offt.fft(pen))[idx]
             assert abs(gphi[f][v, u] - w * pen[idx]) <= 1e-6 * scale / R
             assert abs(gdphi[f][v, u] - w * d) <= 2e-5 * scale * np.abs(m.kb[a]).max() / R
+    if n[0] == 288:
+        # every compiled tile shape of the largest length, on all three axes
+        for (n1, n2, pencils) in P.pstd_tile_variants(288):
+            for ax in range(3):
+                s.set_tile(ax, n1, pencils)
+            s.set_state(prev, cur, step)
+            s.run(1)
+            e = sampled_err(s.psi(0).cpu().numpy())
+            print(n, "tile", (n1, n2, pencils), "sampled max err", e, flush=True)
+            assert e < 1e-5
 
 
 def test_potential_validation(P):
