@@ -246,8 +246,17 @@ pstd_status build_tables(pstd_solver* s) {
 // per-step launches
 // ---------------------------------------------------------------------------
 
-// launch the three passes of step ctr[0] + koff on `stream`
-pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent_t* ev) {
+// launch step ctr[0] + koff, step koff of a group of `count` launched
+// together, on `stream`
+pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int count, hipEvent_t* ev) {
+    if (s->sphere) {
+        // shell DFT in pairs of steps of the group (the odd step adds the even
+        // one before it; a last even step goes alone), before this step's z
+        // pass overwrites psi^{n-1}
+        const int k = (koff & 1) ? 2 : (koff == count - 1 ? 1 : 0);
+        hipError_t e = pstd::sphere_launch_dft(s, koff, k, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "shell DFT launch");
+    }
     for (int axis = 0; axis < 3; ++axis) {
         pstd::PassArgs a;
         pstd::solver_args(s, axis, a);
@@ -257,18 +266,13 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, hipEvent
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
     }
-    if (s->sphere) {
-        // psi^n stays in its buffer until the next step's z pass
-        hipError_t e = pstd::sphere_launch_dft(s, koff, stream);
-        if (e != hipSuccess) return hip_fail(s, e, "shell DFT launch");
-    }
     return PSTD_OK;
 }
 
 // `count` consecutive steps, then one counter advance
 pstd_status launch_steps(pstd_solver* s, hipStream_t stream, int count, hipEvent_t* ev) {
     for (int k = 0; k < count; ++k) {
-        pstd_status st = launch_passes(s, stream, k, ev);
+        pstd_status st = launch_passes(s, stream, k, count, ev);
         if (st) return st;
     }
     hipError_t e = pstd::launch_advance(s->ctr, 1, count, stream);

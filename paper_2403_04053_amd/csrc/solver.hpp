@@ -78,7 +78,9 @@ void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out
 pstd_status sphere_create(pstd_solver* s);
 void sphere_free(SphereState* sp);
 // running DFT of psi^{ctr[0] + koff} on the shell cells (inside the window)
-hipError_t sphere_launch_dft(const pstd_solver* s, int koff, hipStream_t stream);
+// shell DFT of the `count` (1 or 2) steps ending at ctr[0] + koff, launched
+// before that step's passes
+hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStream_t stream);
 void sphere_clear(pstd_solver* s, hipStream_t stream);
 int64_t sphere_state_bytes(const pstd_solver* s);
 hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream);

@@ -98,20 +98,32 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
     s = t;
 }
 
-__global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, const int* __restrict__ dft_tab,
+// Eq. psiphasor on the shell cells for `count` (1 or 2) consecutive steps
+// ending at ctr[0] + koff, each with its own weight and window flag.  Run
+// before that step's z pass, when both psi^{n-1} and psi^n are in place, so
+// a pair of steps costs one read-modify-write of the FP64 sums; the terms
+// are added in step order, as one launch per step would.
+__global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int count, const int* __restrict__ dft_tab,
                                  const double2* __restrict__ w_tab, const float2* __restrict__ buf0,
                                  const float2* __restrict__ buf1, const int* __restrict__ list, int64_t n,
                                  double2* __restrict__ sum, double2* __restrict__ comp) {
-    const int64_t nstep = ctr[0] + koff;
-    if (nstep >= ctr[1] || !dft_tab[nstep]) return;
+    const int64_t last = ctr[0] + koff;
+    const int64_t first = last - (count - 1);
+    bool any = false;
+    for (int64_t m = first; m <= last; ++m) any |= m < ctr[1] && dft_tab[m] != 0;
+    if (!any) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const float2 x = ((nstep & 1) ? buf1 : buf0)[list[c]];
-    const double2 w = w_tab[nstep];
-    const double zr = w.x * x.x - w.y * x.y, zi = w.x * x.y + w.y * x.x;
+    const int cell = list[c];
     double2 s = sum[c], e = comp[c];
-    neumaier(s.x, e.x, zr);
-    neumaier(s.y, e.y, zi);
+    for (int64_t m = first; m <= last; ++m) {
+        if (m >= ctr[1] || !dft_tab[m]) continue;
+        const float2 x = ((m & 1) ? buf1 : buf0)[cell];
+        const double2 w = w_tab[m];
+        const double zr = w.x * x.x - w.y * x.y, zi = w.x * x.y + w.y * x.x;
+        neumaier(s.x, e.x, zr);
+        neumaier(s.y, e.y, zi);
+    }
     sum[c] = s;
     comp[c] = e;
 }
@@ -353,11 +365,13 @@ pstd_status sphere_create(pstd_solver* s) {
     return PSTD_OK;
 }
 
-hipError_t sphere_launch_dft(const pstd_solver* s, int koff, hipStream_t stream) {
+hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStream_t stream) {
     const SphereState* sp = s->sphere;
-    if (!sp || sp->n_shell == 0) return hipSuccess;
+    if (!sp || sp->n_shell == 0 || count < 1) return hipSuccess;
+    if (count > 2 || koff < count - 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(shell_dft_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
-                       koff, s->dft_tab, s->w_tab, s->buf[0], s->buf[1], sp->list, sp->n_shell, sp->sum, sp->comp);
+                       koff, count, s->dft_tab, s->w_tab, s->buf[0], s->buf[1], sp->list, sp->n_shell, sp->sum,
+                       sp->comp);
     return hipGetLastError();
 }
 

@@ -110,17 +110,49 @@ def test_empty_observation_sets(P):
     s.close()
 
 
-def test_empty_observation_sets_sphere(P):
+def sphere_problem(steps=40, dft=(20, 40), v0=1.0):
+    """48^3, 8 points per wavelength, sphere of radius 0.95 around a barrier
+    of radius 3 cells (the stencils reach into the taper walls)."""
     h = 0.1
     k0 = 2 * math.pi / (8 * h)
-    prob = synth.Problem(n=(48, 48, 48), h=(h,) * 3, k0=k0, abc_cells=(4,) * 3, abc_alpha=1.0,
-                         abc_U0=synth.paper_u0(1.0, k0 * h, 4), tfsf=((16, 19, 29, 32),) * 3,
-                         v_max=k0 * k0 / 2, ramp_periods=0.5, n_steps=40, dft_begin=20, dft_end=40,
+    E0 = k0 * k0 / 2
+    prob = synth.Problem(n=(48, 48, 48), h=(h,) * 3, k0=k0, theta=0.5, phi=0.8, abc_cells=(4,) * 3,
+                         abc_alpha=1.0, abc_U0=synth.paper_u0(1.0, k0 * h, 4), tfsf=((16, 19, 29, 32),) * 3,
+                         v_max=E0, ramp_periods=0.5, n_steps=steps, dft_begin=dft[0], dft_end=dft[1],
                          surf_lo=(14,) * 3, surf_hi=(34,) * 3, surface_kind=1, sphere_radius=0.95,
                          sphere_nodes=(16, 32))
-    V = np.zeros((48, 48, 48))
+    x = np.arange(48) - 24
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    V = np.where(X * X + Y * Y + Z * Z <= 9, v0 * E0, 0.0)
+    return prob, V.astype(np.float32).astype(np.float64)
+
+
+def test_empty_observation_sets_sphere(P):
+    prob, V = sphere_problem(v0=0.0)
     print(f"empty sets (sphere): grid {prob.n}", flush=True)
     s = _window_done(P, prob, V)
     assert s.project(np.zeros((0, 3))).shape == (0,)
     assert s.far_field(np.zeros((0, 3))).shape == (0,)
+    s.close()
+
+
+@pytest.mark.parametrize("split", [(37,), (1,) * 37, (5, 16, 16), (16, 5, 16), (17, 20), (2, 3, 32)])
+def test_any_split_of_a_run_is_bit_identical_sphere(P, split):
+    """The shell DFT adds the steps of a launch group in pairs, the odd step
+    taking the even one before it; however the run is split, every window
+    step is added once and in step order, so the sums agree bit for bit (the
+    window starts on an odd step and ends on an even one to exercise both
+    ends)."""
+    prob, V = sphere_problem(steps=37, dft=(9, 34))
+    print(f"sphere split {split}: grid {prob.n}", flush=True)
+    ref = solver(P, prob, V)
+    ref.run(37)
+    s = solver(P, prob, V)
+    for k in split:
+        s.run(k)
+    assert s.step == ref.step == 37
+    assert torch.equal(s.psi(0), ref.psi(0))
+    for a, b in zip(s.sphere_phasors(), ref.sphere_phasors()):
+        assert torch.equal(a, b)
+    ref.close()
     s.close()
