@@ -32,12 +32,12 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # 512 MiB: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # sources whose SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported
 # as null.  Key: (N, N1, N2, pencils per workgroup, axis).
-TRAFFIC_SRC_SHA256 = "29c4415059b8820b349c283e58825f19ad54620487159ad8a81abc046a9810e1"
+TRAFFIC_SRC_SHA256 = "c754e79ffd12474048cfb94ccee28be133ae5eeaa7a985c93141eb2ec617402a"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch; this workload's passes carry no surface DFT
-    (160, 10, 16, 16, 0): (32143, 32000), (160, 10, 16, 16, 1): (64159, 32000), (160, 10, 16, 16, 2): (112309, 32000),
-    (160, 10, 16, 32, 0): (32133, 32000), (160, 10, 16, 32, 1): (64157, 32000), (160, 10, 16, 32, 2): (112313, 32000),
-    (160, 10, 16, 8, 0): (32133, 32000), (160, 10, 16, 8, 1): (64162, 32002), (160, 10, 16, 8, 2): (112376, 32272),
-    (160, 16, 10, 16, 0): (32147, 32000), (160, 16, 10, 16, 1): (64171, 32000), (160, 16, 10, 16, 2): (112384, 32000),
+    (160, 10, 16, 16, 0): (32121, 32000), (160, 10, 16, 16, 1): (64150, 32000), (160, 10, 16, 16, 2): (112309, 32000),
+    (160, 10, 16, 32, 0): (32136, 32000), (160, 10, 16, 32, 1): (64157, 32000), (160, 10, 16, 32, 2): (112318, 32000),
+    (160, 10, 16, 8, 0): (32139, 32000), (160, 10, 16, 8, 1): (64163, 32003), (160, 10, 16, 8, 2): (112358, 32235),
+    (160, 16, 10, 16, 0): (32155, 32000), (160, 16, 10, 16, 1): (64171, 32000), (160, 16, 10, 16, 2): (112372, 32000),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")
