@@ -15,12 +15,12 @@
 // tables (twiddles, kbar^2, derivative rows) are staged in LDS once per
 // workgroup.
 //
-// Epilogues: x pass writes L; y pass adds to L; z pass adds its term and
-// applies the leapfrog update with potential, TF/SF source and absorber,
-// writing psi^{n+1} over psi^{n-1}.  Inside the DFT window each pass also
-// accumulates, in FP64 with Neumaier compensation, the DFT of psi and of its
-// spectral normal derivative on the two planes normal to its axis
-// (Eqs. psiphasor, dpsiphasor).
+// Epilogues: x pass writes L; y pass adds to L (which it reads at the start,
+// with the field); z pass adds its term and applies the leapfrog update with
+// potential, TF/SF source and absorber, writing psi^{n+1} over psi^{n-1}.
+// Inside the DFT window each pass also accumulates, in FP64 with Neumaier
+// compensation, the DFT of psi and of its spectral normal derivative on the
+// two planes normal to its axis (Eqs. psiphasor, dpsiphasor).
 //
 // Segmented mode (overlapping subdomains, Section 2.6): a pencil is split
 // into segments of C core points; each segment is transformed as a local
@@ -259,6 +259,21 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
         float2 raw[N1];
         load_tile<N, N1, N2, SEG>(psi, geo, n2, raw);
+        // the y pass's epilogue operand (L from the x pass), issued with the
+        // field loads so that its latency hides behind the transforms; the
+        // same elements the epilogue writes, read by the thread that writes them
+        float2 Lin[N1];
+        if constexpr (AXIS == 1) {
+            const int C = SEG ? f.seg_core : N;
+            const int H = SEG ? f.seg_halo : 0;
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                const int e = n2 + N2 * n1;
+                Lin[n1] = make_float2(0.f, 0.f);
+                if (geo.valid && e < N && (!SEG || (e >= H && e < H + C)))
+                    Lin[n1] = f.L[geo.base + (int64_t)e * geo.estride];
+            });
+        }
 
         GMEM const float* __restrict__ wloc = f.wloc;
         const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
@@ -380,7 +395,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     const int e = n2 + N2 * n1;
                     if (e < N && (!SEG || (e >= H && e < H + C))) {
                         const int64_t ad = geo.base + (int64_t)e * geo.estride;
-                        Lbuf[ad] = cadd(Lbuf[ad], v[n1]);
+                        Lbuf[ad] = cadd(Lin[n1], v[n1]);
                     }
                 });
             } else {
