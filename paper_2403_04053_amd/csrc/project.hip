@@ -255,9 +255,13 @@ struct FaceGeo {
 };
 
 // Q layout: [cell][field(0 psi, 1 dpsi)][p][q]
+// One thread per point; workgroup row blockIdx.y sums the cells
+// [y * cells_per_split, (y + 1) * cells_per_split), so that few points still
+// fill the chip.  Each row writes its partial sum (times the face prefactor)
+// to part[y * n_obs + point]; add_splits_kernel adds the rows in order.
 __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __restrict__ obs, int64_t n_obs, double k0,
                                                             FaceGeo g, const double2* __restrict__ Q,
-                                                            double2* __restrict__ out) {
+                                                            int64_t cells_per_split, double2* __restrict__ part) {
     __shared__ double2 sq[kCellChunk * 2 * kTerms * kTerms];
     const int64_t pi = (int64_t)blockIdx.x * kNearThreads + threadIdx.x;
     const bool live = pi < n_obs;
@@ -272,9 +276,11 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
     const double Ra = ra_ - g.xa;
     double2 acc = make_double2(0, 0);
     const int64_t ncell = (int64_t)g.L * g.M;
+    const int64_t c_lo = (int64_t)blockIdx.y * cells_per_split;
+    const int64_t c_hi = min<int64_t>(ncell, c_lo + cells_per_split);
     constexpr int per_cell = 2 * kTerms * kTerms;
-    for (int64_t c0 = 0; c0 < ncell; c0 += kCellChunk) {
-        const int nc = (int)min<int64_t>(kCellChunk, ncell - c0);
+    for (int64_t c0 = c_lo; c0 < c_hi; c0 += kCellChunk) {
+        const int nc = (int)min<int64_t>(kCellChunk, c_hi - c0);
         __syncthreads();
         for (int e = threadIdx.x; e < nc * per_cell; e += kNearThreads) sq[e] = Q[c0 * per_cell + e];
         __syncthreads();
@@ -317,7 +323,18 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
             acc = zadd(acc, zmul(make_double2(cs * inv, sn * inv), inner));
         }
     }
-    if (live) out[pi] = zadd(out[pi], make_double2(acc.x * g.pref, acc.y * g.pref));
+    if (live) part[(int64_t)blockIdx.y * n_obs + pi] = make_double2(acc.x * g.pref, acc.y * g.pref);
+}
+
+// out[i] (+)= sum over the split rows k = 0, 1, ... of part[k * n + i], in
+// row order
+__global__ void add_splits_kernel(const double2* __restrict__ part, int splits, int64_t n, bool accumulate,
+                                  double2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 acc = part[i];
+    for (int k = 1; k < splits; ++k) acc = zadd(acc, part[(int64_t)k * n + i]);
+    out[i] = accumulate ? zadd(out[i], acc) : acc;
 }
 
 // Adjoint of the per-point cell sums: for one cell and one p,
@@ -325,9 +342,12 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
 // coef = (i - 1/R) R_a / R for the psi field (fld 0), 1 for dpsi (fld 1).
 constexpr int kAdjObsChunk = 256;
 
+// Workgroup row blockIdx.y sums the points [y * obs_per_split, (y + 1) *
+// obs_per_split) into its own copy of Qbar (Qbar + y * 2 kTerms^2 ncell);
+// add_splits_kernel adds the copies in order.
 __global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __restrict__ obs, const double2* __restrict__ gv,
                                                            int64_t n_obs, double k0, FaceGeo g,
-                                                           double2* __restrict__ Qbar) {
+                                                           int64_t obs_per_split, double2* __restrict__ Qbar) {
     __shared__ double3 so[kAdjObsChunk];
     __shared__ double2 sg[kAdjObsChunk];
     const int64_t ncell = (int64_t)g.L * g.M;
@@ -340,8 +360,10 @@ __global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __rest
     double2 acc[2][kTerms];
     for (int f = 0; f < 2; ++f)
         for (int q = 0; q < kTerms; ++q) acc[f][q] = make_double2(0, 0);
-    for (int64_t o0 = 0; o0 < n_obs; o0 += kAdjObsChunk) {
-        const int no = (int)min<int64_t>(kAdjObsChunk, n_obs - o0);
+    const int64_t o_lo = (int64_t)blockIdx.y * obs_per_split;
+    const int64_t o_hi = min<int64_t>(n_obs, o_lo + obs_per_split);
+    for (int64_t o0 = o_lo; o0 < o_hi; o0 += kAdjObsChunk) {
+        const int no = (int)min<int64_t>(kAdjObsChunk, o_hi - o0);
         __syncthreads();
         for (int e = threadIdx.x; e < no; e += blockDim.x) {
             so[e] = obs[o0 + e];
@@ -379,8 +401,9 @@ __global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __rest
         }
     }
     if (!live) return;
+    double2* __restrict__ dst = Qbar + (int64_t)blockIdx.y * 2 * kTerms * kTerms * ncell;
     for (int f = 0; f < 2; ++f)
-        for (int q = 0; q < kTerms; ++q) Qbar[(((int64_t)f * kTerms + p) * kTerms + q) * ncell + cell] = acc[f][q];
+        for (int q = 0; q < kTerms; ++q) dst[(((int64_t)f * kTerms + p) * kTerms + q) * ncell + cell] = acc[f][q];
 }
 
 // out = conj(x) * scale as complex64
@@ -423,6 +446,8 @@ struct ProjectState {
     double2* spectra = nullptr;   // [face][2][plane]
     double2* work = nullptr;      // scratch
     size_t work_bytes = 0;
+    double2* part = nullptr;      // per-split partial sums of the point kernels
+    size_t part_bytes = 0;
     double2* tw = nullptr;        // per axis: twiddles exp(-2 pi i j / N)
     double2* twc = nullptr;       // per axis: conjugate twiddles
     int64_t face_off[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -443,6 +468,16 @@ hipError_t ensure(T** ptr, size_t* have, size_t need) {
     hipError_t e = hipMalloc((void**)ptr, need);
     if (e == hipSuccess) *have = need;
     return e;
+}
+
+// Rows of workgroups a point kernel is split into: enough for about eight
+// waves per SIMD (256 CUs x 4 SIMDs) when the points alone give fewer, at
+// most `cap` (the number of independent pieces of the summed range)
+constexpr int64_t kTargetWaves = 8 * 1024;
+int split_count(int64_t waves, int64_t cap) {
+    int64_t k = (kTargetWaves + waves - 1) / std::max<int64_t>(waves, 1);
+    k = std::min<int64_t>(k, std::min<int64_t>(cap, 64));
+    return (int)std::max<int64_t>(k, 1);
 }
 
 #define TRY(x)                                \
@@ -655,8 +690,14 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
         g.xb0 = (p.surf_lo[b] - Nb / 2 + 0.5) * dxb[b];
         g.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
         g.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
-        hipLaunchKernelGGL(near_kernel, dim3((unsigned)((n_obs + kNearThreads - 1) / kNearThreads)),
-                           dim3(kNearThreads), 0, stream, obs, n_obs, p.k0, g, dQ, out);
+        const int64_t bx = (n_obs + kNearThreads - 1) / kNearThreads;
+        const int splits = split_count(bx * (kNearThreads / 64), (ncell + kCellChunk - 1) / kCellChunk);
+        const int64_t per = (ncell + splits - 1) / splits;
+        TRY(ensure(&s->part, &s->part_bytes, (size_t)splits * n_obs * sizeof(double2)));
+        hipLaunchKernelGGL(near_kernel, dim3((unsigned)bx, (unsigned)splits), dim3(kNearThreads), 0, stream, obs, n_obs,
+                           p.k0, g, dQ, per, s->part);
+        hipLaunchKernelGGL(add_splits_kernel, dim3((unsigned)((n_obs + 255) / 256)), dim3(256), 0, stream, s->part, splits,
+                           n_obs, true, out);
         // the scratch is reused by the next face: wait for this face's kernels
         TRY(hipStreamSynchronize(stream));
     }
@@ -720,8 +761,20 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
         geo.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
         geo.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
         const int64_t nthr = ncell * kTerms;
-        hipLaunchKernelGGL(near_adjoint_kernel, dim3((unsigned)((nthr + 127) / 128)), dim3(128), 0, stream, obs, g,
-                           n_obs, p.k0, geo, dQ);
+        const int64_t bx = (nthr + 127) / 128;
+        const int splits = split_count(bx * 2, std::min<int64_t>((n_obs + kAdjObsChunk - 1) / kAdjObsChunk, 16));
+        const int64_t per = (n_obs + splits - 1) / splits;
+        const int64_t nq = 2 * kTerms * kTerms * ncell;
+        double2* qdst = dQ;
+        if (splits > 1) {
+            TRY(ensure(&s->part, &s->part_bytes, (size_t)splits * nq * sizeof(double2)));
+            qdst = s->part;
+        }
+        hipLaunchKernelGGL(near_adjoint_kernel, dim3((unsigned)bx, (unsigned)splits), dim3(128), 0, stream, obs, g,
+                           n_obs, p.k0, geo, per, qdst);
+        if (splits > 1)
+            hipLaunchKernelGGL(add_splits_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, stream, s->part,
+                               splits, nq, false, dQ);
         for (int fld = 0; fld < 2; ++fld) {
             // Wbar[c'][p L + l] = sum_q Vh_q [Nc x M] Qbar[fld][p][q] [M x L]
             TRY(zgemm(Nc, L, kTerms * M, dVh, (int64_t)kTerms * M, 0, dQ + (size_t)fld * kTerms * kTerms * ncell, L,
@@ -745,6 +798,7 @@ void project_free(ProjectState* s) {
     (void)hipFree(s->phasors);
     (void)hipFree(s->spectra);
     (void)hipFree(s->work);
+    (void)hipFree(s->part);
     (void)hipFree(s->tw);
     (void)hipFree(s->twc);
     delete s;
