@@ -448,6 +448,13 @@ struct ProjectState {
     size_t work_bytes = 0;
     double2* part = nullptr;      // per-split partial sums of the point kernels
     size_t part_bytes = 0;
+    // sinc-Taylor expansion tables of the cell sums, built once per solver
+    // (they depend on the grid and the box only): per face, U_p^T and V_q for
+    // the points, and their conjugates in the adjoint's layout
+    double2* fwd_tab = nullptr;
+    double2* adj_tab = nullptr;
+    int64_t fwd_off[7] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t adj_off[7] = {0, 0, 0, 0, 0, 0, 0};
     double2* tw = nullptr;        // per axis: twiddles exp(-2 pi i j / N)
     double2* twc = nullptr;       // per axis: conjugate twiddles
     int64_t face_off[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -554,6 +561,77 @@ hipError_t finalize_phasors(double2* const acc[3], const int64_t points[3], doub
     return hipGetLastError();
 }
 
+namespace {
+
+// Expansion of the cell integral along one face axis (axis ax, `cells` cells
+// from grid index lo, FFT length N): for spectral index m (signed m') and
+// cell l, the Taylor coefficients t = 0..kOrder of the sinc factor times the
+// phase of the cell centre, conjugated when `conj`: put(t, l, m, value).
+template <class Put>
+void expansion(const double dxb[3], int ax, int lo, int cells, int N, bool conj, Put put) {
+    const double d = dxb[ax], Lp = N * d;
+    double sp[kTerms];
+    for (int m = 0; m < N; ++m) {
+        const int bp = m < N / 2 ? m : m - N;
+        sinc_taylor(kPi * bp / N, sp);
+        for (int l = 0; l < cells; ++l) {
+            const double xc = (lo + l - N / 2 + 0.5) * d;
+            const double ph = 2 * kPi * bp * xc / Lp;
+            const double sg = (bp & 1) ? -1.0 : 1.0;
+            const double cs = std::cos(ph), sn = conj ? -std::sin(ph) : std::sin(ph);
+            for (int t = 0; t < kTerms; ++t) put(t, l, m, make_double2(sg * sp[t] * cs, sg * sp[t] * sn));
+        }
+    }
+}
+
+// The tables of all six faces in one device array, built on first use:
+// forward (adjoint = false): U_p^T[p][b'][l] then V_q[q][m][c'];
+// adjoint: Vh[c'][q][m] = conj V_q[m][c'] then Uc[p][l][b'] = conj U_p[l][b'].
+hipError_t near_tables(ProjectState* s, const pstd_problem& p, const double dxb[3], bool adjoint) {
+    double2*& tab = adjoint ? s->adj_tab : s->fwd_tab;
+    int64_t* off = adjoint ? s->adj_off : s->fwd_off;
+    if (tab) return hipSuccess;
+    int64_t total = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2, b = face_axis_b(a), c = face_axis_c(a);
+        const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
+        off[f] = total;
+        total += (int64_t)kTerms * (p.n[b] * L + M * p.n[c]);
+    }
+    off[6] = total;
+    std::vector<double2> h((size_t)total);
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2, b = face_axis_b(a), c = face_axis_c(a);
+        const int Nb = p.n[b], Nc = p.n[c];
+        const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
+        double2* t0 = h.data() + off[f];
+        double2* t1 = t0 + (size_t)kTerms * Nb * L;
+        if (!adjoint) {
+            expansion(dxb, b, p.surf_lo[b], L, Nb, false,
+                      [&](int t, int l, int m, double2 v) { t0[((size_t)t * Nb + m) * L + l] = v; });
+            expansion(dxb, c, p.surf_lo[c], M, Nc, false,
+                      [&](int t, int l, int m, double2 v) { t1[((size_t)t * M + l) * Nc + m] = v; });
+        } else {
+            // Vh first (Nc x kTerms M), then Uc (kTerms L x Nb): the same total
+            double2* vh = t0;
+            double2* uc = t0 + (size_t)Nc * kTerms * M;
+            expansion(dxb, c, p.surf_lo[c], M, Nc, true,
+                      [&](int t, int l, int m, double2 v) { vh[((size_t)m * kTerms + t) * M + l] = v; });
+            expansion(dxb, b, p.surf_lo[b], L, Nb, true,
+                      [&](int t, int l, int m, double2 v) { uc[((size_t)t * L + l) * Nb + m] = v; });
+        }
+    }
+    hipError_t e = hipMalloc(&tab, (size_t)total * sizeof(double2));
+    if (e == hipSuccess) e = hipMemcpy(tab, h.data(), (size_t)total * sizeof(double2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(tab);
+        tab = nullptr;
+    }
+    return e;
+}
+
+}  // namespace
+
 hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
                      const int64_t points[3], double scale, const double3* dirs, int64_t n_dir, double2* out,
                      hipStream_t stream, std::string* msg) {
@@ -625,6 +703,7 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
     }
     TRY(prepare(pst, p, acc, points, scale, stream));
     ProjectState* s = *pst;
+    TRY(near_tables(s, p, dxb, false));
     TRY(hipMemsetAsync(out, 0, n_obs * sizeof(double2), stream));
     for (int f = 0; f < 6; ++f) {
         const int a = f / 2, side = f % 2, b = face_axis_b(a), c = face_axis_c(a);
@@ -632,38 +711,15 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
         const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
         const int64_t ncell = (int64_t)L * M;
         // expansion tables U_p^T[b'][l] (batched over p) and V_q[m][c'] (batched over q)
-        std::vector<double2> Ut((size_t)kTerms * Nb * L), V((size_t)kTerms * M * Nc);
-        auto fill = [&](int ax, int lo, int cells, int N, bool transpose, std::vector<double2>& dst) {
-            const double d = dxb[ax], Lp = N * d;
-            double sp[kTerms];
-            for (int m = 0; m < N; ++m) {
-                const int bp = m < N / 2 ? m : m - N;
-                sinc_taylor(kPi * bp / N, sp);
-                for (int l = 0; l < cells; ++l) {
-                    const double xc = (lo + l - N / 2 + 0.5) * d;
-                    const double ph = 2 * kPi * bp * xc / Lp;
-                    const double sg = (bp & 1) ? -1.0 : 1.0;
-                    for (int q = 0; q < kTerms; ++q) {
-                        const double2 v = make_double2(sg * sp[q] * std::cos(ph), sg * sp[q] * std::sin(ph));
-                        if (transpose) dst[((size_t)q * N + m) * cells + l] = v;   // [p][b'][l]
-                        else dst[((size_t)q * cells + l) * N + m] = v;             // [q][m][c']
-                    }
-                }
-            }
-        };
-        fill(b, p.surf_lo[b], L, Nb, true, Ut);
-        fill(c, p.surf_lo[c], M, Nc, false, V);
-        // scratch: Ut, V, W [p][Nc][L], Qg [p][q][M][L], Q [cell][2][p][q]
-        const size_t nUt = Ut.size(), nV = V.size(), nW = (size_t)kTerms * Nc * L,
-                     nQg = (size_t)kTerms * kTerms * ncell, nQ = (size_t)2 * kTerms * kTerms * ncell;
-        TRY(ensure(&s->work, &s->work_bytes, (nUt + nV + nW + nQg + nQ) * sizeof(double2)));
-        double2* dUt = s->work;
-        double2* dV = dUt + nUt;
-        double2* dW = dV + nV;
+        const double2* dUt = s->fwd_tab + s->fwd_off[f];
+        const double2* dV = dUt + (size_t)kTerms * Nb * L;
+        // scratch: W [p][Nc][L], Qg [p][q][M][L], Q [cell][2][p][q]
+        const size_t nW = (size_t)kTerms * Nc * L, nQg = (size_t)kTerms * kTerms * ncell,
+                     nQ = (size_t)2 * kTerms * kTerms * ncell;
+        TRY(ensure(&s->work, &s->work_bytes, (nW + nQg + nQ) * sizeof(double2)));
+        double2* dW = s->work;
         double2* dQg = dW + nW;
         double2* dQ = dQg + nQg;
-        TRY(hipMemcpyAsync(dUt, Ut.data(), nUt * sizeof(double2), hipMemcpyHostToDevice, stream));
-        TRY(hipMemcpyAsync(dV, V.data(), nV * sizeof(double2), hipMemcpyHostToDevice, stream));
         for (int fld = 0; fld < 2; ++fld) {
             const double2* F = s->spectra + s->face_off[f] + (int64_t)fld * Nb * Nc;
             // W_p = F [Nc x Nb] * Ut_p [Nb x L]
@@ -698,8 +754,7 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
                            p.k0, g, dQ, per, s->part);
         hipLaunchKernelGGL(add_splits_kernel, dim3((unsigned)((n_obs + 255) / 256)), dim3(256), 0, stream, s->part, splits,
                            n_obs, true, out);
-        // the scratch is reused by the next face: wait for this face's kernels
-        TRY(hipStreamSynchronize(stream));
+        // the next face reuses the scratch after these kernels, in stream order
     }
     return hipGetLastError();
 }
@@ -710,6 +765,7 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
     // the state (twiddles, offsets) is shared with the forward projection
     TRY(prepare(pst, p, acc, points, 1.0, stream));
     ProjectState* s = *pst;
+    TRY(near_tables(s, p, dxb, true));
     const double2* twc[3] = {s->twc, s->twc + p.n[0], s->twc + p.n[0] + p.n[1]};
     for (int f = 0; f < 6; ++f) {
         const int a = f / 2, side = f % 2, b = face_axis_b(a), c = face_axis_c(a);
@@ -717,35 +773,14 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
         const int L = p.surf_hi[b] - p.surf_lo[b], M = p.surf_hi[c] - p.surf_lo[c];
         const int64_t ncell = (int64_t)L * M, np_ = (int64_t)Nb * Nc;
         // conjugated expansion tables: Vh[c'][q M + m] = conj V_q[m][c'], Uc[p L + l][b'] = conj U_p[l][b']
-        std::vector<double2> Vh((size_t)Nc * kTerms * M), Uc((size_t)kTerms * L * Nb);
-        auto table = [&](int ax, int lo, int cells, int N, auto put) {
-            const double d = dxb[ax], Lp = N * d;
-            double sp[kTerms];
-            for (int mm = 0; mm < N; ++mm) {
-                const int bp = mm < N / 2 ? mm : mm - N;
-                sinc_taylor(kPi * bp / N, sp);
-                for (int l = 0; l < cells; ++l) {
-                    const double xc = (lo + l - N / 2 + 0.5) * d;
-                    const double ph = 2 * kPi * bp * xc / Lp;
-                    const double sg = (bp & 1) ? -1.0 : 1.0;
-                    for (int q = 0; q < kTerms; ++q)
-                        put(q, l, mm, make_double2(sg * sp[q] * std::cos(ph), -sg * sp[q] * std::sin(ph)));
-                }
-            }
-        };
-        table(c, p.surf_lo[c], M, Nc, [&](int q, int m, int cc, double2 v) { Vh[((size_t)cc * kTerms + q) * M + m] = v; });
-        table(b, p.surf_lo[b], L, Nb, [&](int pp, int l, int bb, double2 v) { Uc[((size_t)pp * L + l) * Nb + bb] = v; });
-        const size_t nVh = Vh.size(), nUc = Uc.size(), nQ = (size_t)2 * kTerms * kTerms * ncell,
-                     nW = (size_t)Nc * kTerms * L, nF = (size_t)np_;
-        TRY(ensure(&s->work, &s->work_bytes, (nVh + nUc + nQ + nW + 2 * nF) * sizeof(double2)));
-        double2* dVh = s->work;
-        double2* dUc = dVh + nVh;
-        double2* dQ = dUc + nUc;
+        const double2* dVh = s->adj_tab + s->adj_off[f];
+        const double2* dUc = dVh + (size_t)Nc * kTerms * M;
+        const size_t nQ = (size_t)2 * kTerms * kTerms * ncell, nW = (size_t)Nc * kTerms * L, nF = (size_t)np_;
+        TRY(ensure(&s->work, &s->work_bytes, (nQ + nW + 2 * nF) * sizeof(double2)));
+        double2* dQ = s->work;
         double2* dW = dQ + nQ;
         double2* dF = dW + nW;
         double2* dT = dF + nF;
-        TRY(hipMemcpyAsync(dVh, Vh.data(), nVh * sizeof(double2), hipMemcpyHostToDevice, stream));
-        TRY(hipMemcpyAsync(dUc, Uc.data(), nUc * sizeof(double2), hipMemcpyHostToDevice, stream));
         FaceGeo geo;
         geo.a = a;
         geo.b = b;
@@ -788,7 +823,7 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
             hipLaunchKernelGGL(conj_scale_kernel, dim3(blocks), dim3(256), 0, stream, dF, np_, scale,
                                inj + s->face_off[f] + fld * np_);
         }
-        TRY(hipStreamSynchronize(stream));  // the scratch is reused by the next face
+        // the next face reuses the scratch after these kernels, in stream order
     }
     return hipGetLastError();
 }
@@ -799,6 +834,8 @@ void project_free(ProjectState* s) {
     (void)hipFree(s->spectra);
     (void)hipFree(s->work);
     (void)hipFree(s->part);
+    (void)hipFree(s->fwd_tab);
+    (void)hipFree(s->adj_tab);
     (void)hipFree(s->tw);
     (void)hipFree(s->twc);
     delete s;
