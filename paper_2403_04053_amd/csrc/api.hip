@@ -644,7 +644,7 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
     HIP_TRY(s, hipMemcpy(s->buf[(step + 1) & 1], prev, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
     HIP_TRY(s, hipMemcpy(s->buf[step & 1], cur, n_cells * sizeof(float2), hipMemcpyDeviceToDevice));
     for (int a = 0; a < 3; ++a) HIP_TRY(s, hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)));
-    sphere_clear(s, s->stream);
+    HIP_TRY(s, sphere_clear(s, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const int64_t c[2] = {step, std::numeric_limits<int64_t>::max()};
     HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));

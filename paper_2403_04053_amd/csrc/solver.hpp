@@ -81,7 +81,7 @@ void sphere_free(SphereState* sp);
 // shell DFT of the `count` (1 or 2) steps ending at ctr[0] + koff, launched
 // before that step's passes
 hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStream_t stream);
-void sphere_clear(pstd_solver* s, hipStream_t stream);
+hipError_t sphere_clear(pstd_solver* s, hipStream_t stream);
 int64_t sphere_state_bytes(const pstd_solver* s);
 hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream);
 hipError_t sphere_load(pstd_solver* s, const char* src, hipStream_t stream);

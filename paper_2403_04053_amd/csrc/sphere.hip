@@ -375,11 +375,12 @@ hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStrea
     return hipGetLastError();
 }
 
-void sphere_clear(pstd_solver* s, hipStream_t stream) {
+hipError_t sphere_clear(pstd_solver* s, hipStream_t stream) {
     SphereState* sp = s->sphere;
-    if (!sp) return;
-    (void)hipMemsetAsync(sp->sum, 0, sp->n_shell * sizeof(double2), stream);
-    (void)hipMemsetAsync(sp->comp, 0, sp->n_shell * sizeof(double2), stream);
+    if (!sp) return hipSuccess;
+    hipError_t e = hipMemsetAsync(sp->sum, 0, sp->n_shell * sizeof(double2), stream);
+    if (e == hipSuccess) e = hipMemsetAsync(sp->comp, 0, sp->n_shell * sizeof(double2), stream);
+    return e;
 }
 
 int64_t sphere_state_bytes(const pstd_solver* s) {
