@@ -32,12 +32,12 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # 512 MiB: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # sources whose SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported
 # as null.  Key: (N, N1, N2, pencils per workgroup, axis).
-TRAFFIC_SRC_SHA256 = "7202bad93e082cc48c6c4d1243155ef4cd70713e529ab0a755322e9f5c667ed1"
+TRAFFIC_SRC_SHA256 = "8c30fe897317f2748e6845ea1b685cc1a31040b3f6115928f0c82df3bc42b25d"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch; this workload's passes carry no surface DFT
-    (160, 10, 16, 16, 0): (32140, 32000), (160, 10, 16, 16, 1): (64164, 32000), (160, 10, 16, 16, 2): (112308, 32000),
-    (160, 10, 16, 32, 0): (32131, 32000), (160, 10, 16, 32, 1): (64161, 32000), (160, 10, 16, 32, 2): (112304, 32000),
-    (160, 10, 16, 8, 0): (32129, 32000), (160, 10, 16, 8, 1): (64166, 32147), (160, 10, 16, 8, 2): (112379, 32276),
-    (160, 16, 10, 16, 0): (32148, 32000), (160, 16, 10, 16, 1): (64175, 32000), (160, 16, 10, 16, 2): (112383, 32000),
+    (160, 10, 16, 16, 0): (32140, 32000), (160, 10, 16, 16, 1): (64155, 32000), (160, 10, 16, 16, 2): (112301, 32000),
+    (160, 10, 16, 32, 0): (32136, 32000), (160, 10, 16, 32, 1): (64164, 32000), (160, 10, 16, 32, 2): (112312, 32000),
+    (160, 10, 16, 8, 0): (32139, 32000), (160, 10, 16, 8, 1): (64182, 32150), (160, 10, 16, 8, 2): (112373, 32250),
+    (160, 16, 10, 16, 0): (32145, 32000), (160, 16, 10, 16, 1): (64169, 32000), (160, 16, 10, 16, 2): (112387, 32000),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")

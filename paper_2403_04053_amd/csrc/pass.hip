@@ -517,12 +517,15 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     X(128, 8, 16, 32, 0)        \
     X(144, 12, 12, 16, 0)       \
     X(150, 10, 15, 16, 0)       \
+    X(150, 15, 10, 16, 0)       \
     X(160, 10, 16, 16, 0)       \
     X(160, 16, 10, 16, 0)       \
     X(160, 10, 16, 32, 0)       \
     X(160, 10, 16, 8, 0)        \
     X(162, 9, 18, 16, 0)        \
+    X(162, 9, 18, 32, 0)        \
     X(180, 12, 15, 16, 0)       \
+    X(180, 15, 12, 16, 0)       \
     X(192, 12, 16, 16, 0)       \
     X(256, 16, 16, 16, 0)       \
     X(288, 16, 18, 16, 0)       \
