@@ -1,8 +1,8 @@
 """FP64 oracle of the spherical equivalence surface.
 
 The paper integrates over the six faces of a box (Sections 3.1-3.2); a
-sphere is an addition of this build for the 160^3 square-barrier workload.
-Test infrastructure only: imported by tests, never by the product.
+sphere (the paper allows any closed surface) serves the 160^3 square-barrier
+workload.  Test infrastructure only: imported by tests, never by the product.
 
 Definition (reduced units, k = 1, x_bar = k0 x):
   * nodes s_q on the sphere of radius R: Gauss-Legendre in cos(theta)
