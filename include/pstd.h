@@ -110,8 +110,10 @@ pstd_status pstd_critical_dt(const pstd_problem* p, double vmax, double* dt_out_
 pstd_status pstd_reduced_step(const pstd_problem* p, double* dtau_out_host, double* eta_out_host);
 
 /* Validate p, allocate the solver's device state on the current device and
- * build its tables (FP64 on the host, rounded once).  psi^{-1} = psi^0 = 0,
- * V = 0, step index 0.  hip_stream: a hipStream_t or 0.  Synchronises.
+ * build its tables (FP64 on the host, rounded once; the per-step tables
+ * cover max(1024, dft_end) steps, at most 2^18, and grow when a run goes
+ * further).  psi^{-1} = psi^0 = 0, V = 0, step index 0.  hip_stream: a
+ * hipStream_t or 0.  Synchronises.
  * EINVAL: odd or tiny n, taper indices out of order, a box face that is not
  * wholly in the scattered-field region (zeta = 0 on the whole plane) or
  * inside the absorber.  EUNSTABLE: dt above the bound and force_dt = 0.
