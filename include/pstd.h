@@ -94,6 +94,15 @@ typedef struct pstd_problem {
     int32_t surface_kind;
     int32_t sphere_nodes[2];
     double  sphere_radius;
+    /* Complex absorbing potential (Section 2.1: the absorbing potential may be
+     * complex while its imaginary part stays non-positive).  The imaginary
+     * part is the mask above; abc_UR (units of E0) adds the real part
+     * w(d) = abc_UR / cosh^2(abc_alphaR d) inside the layer of every axis,
+     * summed over the axes, to the potential of the step.  abc_alphaR = 0
+     * takes abc_alpha.  The step bound then uses max(v_max / E0, |abc_UR|
+     * times the number of axes with a layer).  0, 0: the mask alone. */
+    double  abc_UR;
+    double  abc_alphaR;
 } pstd_problem;
 
 typedef struct pstd_solver pstd_solver;  /* opaque; owns all its device memory */

@@ -56,11 +56,14 @@ def critical_dt(prob, vmax):
 
 
 def dtau_of(prob):
-    """Reduced step: the given dt, or 0.9 of the critical one for |V| <= v_max."""
+    """Reduced step: the given dt, or 0.9 of the critical one for the largest
+    |v| of the model, max(v_max / E0, the real part of the absorbing potential
+    where the layers of all axes overlap); V vanishes in the layers, so the
+    two never add."""
     E0 = central_energy(prob)
     if prob.dt > 0:
         return E0 * prob.dt / prob.hbar
-    return 0.9 * critical_dtau(dxbar(prob), prob.v_max / E0)
+    return 0.9 * critical_dtau(dxbar(prob), max(prob.v_max / E0, absorber_real_max(prob)))
 
 
 def eta_of(dtau):
@@ -145,6 +148,28 @@ def mask_1d(N, width, U0, alpha, dtau):
     return np.exp(-absorber_gamma(N, width, U0, alpha) * dtau)
 
 
+def absorber_real(N, width, UR, alphaR):
+    """Real part of a complex absorbing potential along one axis (the remark
+    after Eq. Poshcl-Teller: the absorbing potential may be complex as long as
+    its imaginary part, here -gamma, stays non-positive).  Same shape as
+    gamma, in units of E0: w(d) = UR / cosh^2(alphaR d) inside the layer.
+    It enters the step like v, summed over the axes."""
+    return absorber_gamma(N, width, UR, alphaR)
+
+
+def absorber_alpha_real(prob):
+    """Decay of the real part: abc_alphaR, or abc_alpha when that is 0."""
+    a = getattr(prob, "abc_alphaR", 0.0)
+    return a if a > 0 else prob.abc_alpha
+
+
+def absorber_real_max(prob):
+    """max |sum_a w_a| over the grid: at the corners where the layers of all
+    axes with a layer meet, |UR| per such axis."""
+    UR = getattr(prob, "abc_UR", 0.0)
+    return abs(UR) * sum(1 for a in range(3) if prob.abc_cells[a] > 0)
+
+
 def khat(theta, phi):
     """Unit incident direction, Eq. khat."""
     return np.array([math.sin(theta) * math.cos(phi),
@@ -180,7 +205,7 @@ class Model:
     dtau: float
     eta: float
     dxb: np.ndarray
-    v: np.ndarray          # V / E0, [k][j][i]
+    v: np.ndarray          # V / E0 plus the absorber's real part, [k][j][i]
     kb2: list              # per axis kbar^2
     kb: list               # per axis kbar
     Gamma: np.ndarray      # 3D mask, Eq. Gamma
@@ -198,6 +223,18 @@ def _bcast(vec, a):
     return vec.reshape(shape)
 
 
+def absorber_real_3d(prob):
+    """sum_a w_a(d_a) broadcast to [k][j][i] (0.0 without a real part)."""
+    UR = getattr(prob, "abc_UR", 0.0)
+    if UR == 0.0:
+        return 0.0
+    aR = absorber_alpha_real(prob)
+    w = np.zeros((prob.n[2], prob.n[1], prob.n[0]))
+    for a in range(3):
+        w = w + _bcast(absorber_real(prob.n[a], prob.abc_cells[a], UR, aR), a)
+    return w
+
+
 def build(prob, V):
     """All step-invariant quantities of Eq. PSTDupdating (plain 3D arrays)."""
     E0 = central_energy(prob)
@@ -206,6 +243,7 @@ def build(prob, V):
     eta = eta_of(dtau)
     n = prob.n
     v = np.asarray(V, dtype=np.float64) / E0
+    v = v + absorber_real_3d(prob)
     kb = [kbar(n[a], dxb[a]) for a in range(3)]
     kb2 = [k * k for k in kb]
     G = np.ones((n[2], n[1], n[0]))
@@ -229,8 +267,9 @@ def build(prob, V):
 
 def check_potential(model, tol=0.0):
     """(zeta - 1) V = 0 everywhere (Section 2.2.2): V must vanish wherever the
-    taper is below 1."""
-    return bool(np.all(np.abs((model.zeta - 1.0) * model.v) <= tol))
+    taper is below 1 (the absorber's real part is not part of V)."""
+    V = model.v - absorber_real_3d(model.prob)
+    return bool(np.all(np.abs((model.zeta - 1.0) * V) <= tol))
 
 
 def incident(model, n):

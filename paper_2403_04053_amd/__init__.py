@@ -74,6 +74,8 @@ class pstd_problem(ctypes.Structure):
         ("surface_kind", ctypes.c_int32),
         ("sphere_nodes", ctypes.c_int32 * 2),
         ("sphere_radius", ctypes.c_double),
+        ("abc_UR", ctypes.c_double),
+        ("abc_alphaR", ctypes.c_double),
     ]
 
 
@@ -91,6 +93,8 @@ def problem_from(obj) -> pstd_problem:
         p.surf_hi[a] = int(obj.surf_hi[a])
     for name in ("hbar", "mass", "k0", "theta", "phi", "abc_U0", "abc_alpha", "v_max", "dt", "ramp_periods"):
         setattr(p, name, float(getattr(obj, name)))
+    p.abc_UR = float(getattr(obj, "abc_UR", 0.0))
+    p.abc_alphaR = float(getattr(obj, "abc_alphaR", 0.0))
     p.force_dt = int(bool(getattr(obj, "force_dt", False)))
     p.eta_on_source = int(bool(getattr(obj, "eta_on_source", False)))
     p.dft_begin = int(obj.dft_begin)

@@ -61,7 +61,12 @@ pstd_status reduced(const pstd_problem* p, double* E0, double* dxb, double* dtau
         dxb[a] = p->k0 * p->h[a];
         s += 1.0 / (dxb[a] * dxb[a]);
     }
-    *dtau_crit = 1.0 / (kPi * kPi * s + p->v_max / *E0);
+    // largest |v|: the potential (inside the taper core) or the absorber's
+    // real part (inside the layers; largest where the layers of all axes meet)
+    int layers = 0;
+    for (int a = 0; a < 3; ++a) layers += p->abc_cells[a] > 0;
+    const double vmax = std::max(p->v_max / *E0, std::fabs(p->abc_UR) * layers);
+    *dtau_crit = 1.0 / (kPi * kPi * s + vmax);
     *dtau = p->dt > 0 ? *E0 * p->dt / p->hbar : 0.9 * *dtau_crit;
     *eta = std::sin(*dtau) / *dtau;
     return PSTD_OK;
@@ -72,6 +77,8 @@ pstd_status validate(const pstd_problem* p) {
     if (!(p->hbar > 0 && p->mass > 0 && p->k0 > 0)) return fail(nullptr, PSTD_EINVAL, "hbar, mass and k0 must be positive");
     if (!(p->v_max >= 0)) return fail(nullptr, PSTD_EINVAL, "v_max must be >= 0");
     if (!(p->dt >= 0)) return fail(nullptr, PSTD_EINVAL, "dt must be >= 0");
+    if (!std::isfinite(p->abc_UR) || !(p->abc_alphaR >= 0))
+        return fail(nullptr, PSTD_EINVAL, "abc_UR must be finite and abc_alphaR >= 0");
     for (int a = 0; a < 3; ++a) {
         const int N = p->n[a];
         if (N < 8 || (N & 1)) return fail(nullptr, PSTD_EINVAL, "grid lengths must be even and >= 8");
@@ -102,6 +109,40 @@ pstd_status validate(const pstd_problem* p) {
     }
     if (p->dft_begin < 0 || p->dft_end < p->dft_begin) return fail(nullptr, PSTD_EINVAL, "bad DFT window");
     return PSTD_OK;
+}
+
+// Real part of the complex absorbing potential along axis a (units of E0):
+// abc_UR / cosh^2(alpha d) inside the layer, the shape of the mask's rate
+std::vector<double> absorber_real(const pstd_problem& p, int a) {
+    const int N = p.n[a], P = p.abc_cells[a];
+    const double al = p.abc_alphaR > 0 ? p.abc_alphaR : p.abc_alpha;
+    std::vector<double> w(N, 0.0);
+    if (p.abc_UR == 0.0) return w;
+    for (int i = 0; i < N; ++i) {
+        const int d = std::min(i, N - 1 - i);
+        if (d < P) {
+            const double c = std::cosh(al * d);
+            w[i] = p.abc_UR / (c * c);
+        }
+    }
+    return w;
+}
+
+// v2 = 2 dtau (V / E0 + sum_a w_a) per cell, V in energy units (null: V = 0)
+std::vector<float> scaled_potential(const pstd_solver* s, const float* V) {
+    const pstd_problem& p = s->prob;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const std::vector<double> wx = absorber_real(p, 0), wy = absorber_real(p, 1), wz = absorber_real(p, 2);
+    const double scale = 2.0 * s->dtau / s->E0, sw = 2.0 * s->dtau;
+    std::vector<float> v2((size_t)s->cells);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t id = i + (int64_t)nx * (j + (int64_t)ny * k);
+                const double v = V ? (double)V[id] : 0.0;
+                v2[id] = (float)(scale * v + sw * (wx[i] + wy[j] + wz[k]));
+            }
+    return v2;
 }
 
 template <class T>
@@ -447,9 +488,11 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     if ((st = sphere_create(s))) return cleanup(st);
     const int64_t c0[2] = {0, std::numeric_limits<int64_t>::max()};
     if ((e = hipMemcpy(s->ctr, c0, sizeof(c0), hipMemcpyHostToDevice))) return cleanup(hip_fail(s, e, "counters"));
-    if ((e = hipMemset(s->buf[0], 0, s->cells * sizeof(float2))) || (e = hipMemset(s->buf[1], 0, s->cells * sizeof(float2))) ||
-        (e = hipMemset(s->v2, 0, s->cells * sizeof(float))))
+    if ((e = hipMemset(s->buf[0], 0, s->cells * sizeof(float2))) || (e = hipMemset(s->buf[1], 0, s->cells * sizeof(float2))))
         return cleanup(hip_fail(s, e, "hipMemset"));
+    if (p->abc_UR == 0.0) e = hipMemset(s->v2, 0, s->cells * sizeof(float));
+    else e = hipMemcpy(s->v2, scaled_potential(s, nullptr).data(), s->cells * sizeof(float), hipMemcpyHostToDevice);
+    if (e) return cleanup(hip_fail(s, e, "potential"));
     for (int a = 0; a < 3; ++a)
         if ((e = hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMemset acc"));
     // per-step tables through the end of the DFT window (up to 2^18 steps),
@@ -609,8 +652,6 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const pstd_problem& p = s->prob;
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    std::vector<float> v2(n_cells);
-    const double scale = 2.0 * s->dtau / s->E0;
     double vmax = 0;
     for (int k = 0; k < nz; ++k) {
         const bool ck = k >= p.tfsf[2][1] && k <= p.tfsf[2][2];
@@ -624,12 +665,12 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
                 if (v != 0.0 && !(ci && cj && ck))
                     return fail(s, PSTD_EINVAL, "potential must vanish where the taper is below one");
                 vmax = std::max(vmax, std::fabs(v));
-                v2[id] = (float)(scale * v);
             }
         }
     }
     if (vmax > p.v_max * (1 + 1e-6) && !p.force_dt)
         return fail(s, PSTD_EUNSTABLE, "max |V| exceeds v_max used to size the step");
+    const std::vector<float> v2 = scaled_potential(s, V.data());
     HIP_TRY(s, hipMemcpy(s->v2, v2.data(), n_cells * sizeof(float), hipMemcpyHostToDevice));
     return PSTD_OK;
 }

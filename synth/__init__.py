@@ -46,6 +46,8 @@ class Problem:
     abc_cells: tuple = (8, 8, 8)
     abc_U0: float = 10.0
     abc_alpha: float = 0.5
+    abc_UR: float = 0.0            # real part of a complex absorbing potential (units of E0)
+    abc_alphaR: float = 0.0        # its decay per cell; 0: abc_alpha
     tfsf: tuple = ((12, 18, 30, 36),) * 3
     v_max: float = 0.0
     dt: float = 0.0
@@ -197,6 +199,34 @@ def plain_barrier():
                    surf_lo=(10, 10, 10), surf_hi=(38, 38, 38))
     V = square_barrier(n, prob.h, 0.6, 0.5 * E0)
     return prob, V
+
+
+# Absorber parameters for an 8-cell layer at 8 points per wavelength (k0 h =
+# pi/4), found by minimising the far-field difference between the plain-
+# method workload and the same problem with a 32-cell layer on a 96^3 grid
+# (wide_layer_reference).  The mask alone, and the mask with a real part
+# (a complex absorbing potential).
+TUNED_MASK_8 = dict(abc_U0=9.835, abc_alpha=0.3386)
+TUNED_COMPLEX_8 = dict(abc_U0=23.71, abc_alpha=0.3959, abc_UR=-0.6635, abc_alphaR=0.2705)
+
+
+def wide_layer_reference(prob, V, n_fft=96, width=32):
+    """The same problem (spacing, taper, box planes and potential about the
+    grid centre, steps, window) on a cubic grid of n_fft points with a
+    `width`-cell layer of the paper's profile (alpha = 4 / width, U0 from the
+    paper's one-way absorption): its far field stands for the thin-layer
+    problem's without absorber reflections."""
+    n0 = prob.n[0]
+    assert prob.n == (n0, n0, n0) and (n_fft - n0) % 2 == 0 and n_fft > n0
+    sh = (n_fft - n0) // 2
+    alpha = 4.0 / width
+    p = prob.replace(n=(n_fft,) * 3, abc_cells=(width,) * 3, abc_alpha=alpha,
+                     abc_U0=paper_u0(alpha, prob.k0 * prob.h[0], width), abc_UR=0.0, abc_alphaR=0.0,
+                     tfsf=tuple(tuple(y + sh for y in t) for t in prob.tfsf),
+                     surf_lo=tuple(x + sh for x in prob.surf_lo), surf_hi=tuple(x + sh for x in prob.surf_hi))
+    W = np.zeros((n_fft,) * 3)
+    W[sh:sh + n0, sh:sh + n0, sh:sh + n0] = V
+    return p, W
 
 
 def plain_barrier_refined():

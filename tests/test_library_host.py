@@ -32,7 +32,12 @@ def test_status_strings():
         assert lib_mod.pstd_status_string(code) == name
 
 
-@pytest.mark.parametrize("make", [synth.plain_barrier, lambda: synth.tiny(n=(24, 20, 32), P=3, transition=2)])
+@pytest.mark.parametrize("make", [
+    synth.plain_barrier, lambda: synth.tiny(n=(24, 20, 32), P=3, transition=2),
+    # complex absorbing potentials: a shallow real part (the bound keeps v_max)
+    # and a deep one (the layers' |UR| x 3 sets the bound)
+    lambda: (synth.plain_barrier()[0].replace(abc_UR=-0.1, abc_alphaR=0.4), None),
+    lambda: (synth.tiny(n=(24, 20, 32), P=3)[0].replace(abc_UR=-30.0), None)])
 def test_reduced_step_matches_oracle(make):
     prob = make()[0]
     p = lib_mod.problem_from(prob)
@@ -48,6 +53,14 @@ def test_defaults_are_valid_plain_method_geometry():
     dtau, eta = lib_mod.pstd_reduced_step(p)
     # 0.9 of Eq. dtau_stability at dxb = pi/4, |V|max = E0/2
     assert dtau == pytest.approx(0.9 / (3 * 16 + 0.5), rel=1e-12)
+
+
+def test_complex_absorber_fields_are_validated():
+    prob, _ = synth.plain_barrier()
+    for bad in (dict(abc_UR=float("inf")), dict(abc_UR=float("nan")), dict(abc_alphaR=-0.1)):
+        with pytest.raises(lib_mod.PstdError) as e:
+            lib_mod.pstd_reduced_step(lib_mod.problem_from(prob.replace(**bad)))
+        assert e.value.name == "PSTD_EINVAL"
 
 
 def _expect(status_name, prob):
