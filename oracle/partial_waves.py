@@ -133,6 +133,25 @@ def amplitude(k, a, V0, theta, lmax=None, hbar=1.0, mass=1.0):
     return np.tensordot(coef, P, axes=(0, 0))
 
 
+def scattered_wave(k, a, V0, r, theta, lmax=None, hbar=1.0, mass=1.0):
+    """Exact scattered wave at radius r > a and polar angle theta (from the
+    incident direction) for a unit incident wave e^{ikz}.  Outside the
+    potential the total field is sum_l (2l+1) i^l e^{i d_l} [cos d_l j_l(kr)
+    - sin d_l y_l(kr)] P_l; subtracting the incident sum_l (2l+1) i^l j_l P_l
+    leaves
+        psi_sc = sum_l (2l+1) i^{l+1} e^{i d_l} sin d_l h_l(kr) P_l(cos theta),
+    h_l = j_l + i y_l, whose large-r limit is f(theta) e^{ikr} / r."""
+    if lmax is None:
+        lmax = int(math.ceil(k * a)) + 25
+    d = phase_shifts(k, a, V0, lmax, hbar, mass)
+    l = np.arange(lmax + 1)
+    x = k * r
+    h = np.asarray(sph_jn(lmax, x))[:lmax + 1] + 1j * np.asarray(sph_yn(lmax, x))[:lmax + 1]
+    coef = (2 * l + 1) * (1j ** (l + 1)) * np.exp(1j * d) * np.sin(d) * h
+    P = legendre(lmax, np.cos(np.asarray(theta, dtype=np.float64)))
+    return np.tensordot(coef, P, axes=(0, 0))
+
+
 def total_cross_section(k, a, V0, lmax=None, hbar=1.0, mass=1.0):
     """sigma = (4 pi / k^2) sum (2l+1) sin^2 d_l."""
     if lmax is None:

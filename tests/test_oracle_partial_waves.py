@@ -61,3 +61,45 @@ def test_equal_energy_branch_is_continuous():
     d0 = pw.phase_shifts(k, a, E, 8)
     for V0 in (E * (1 - 1e-9), E * (1 + 1e-9)):
         assert np.allclose(np.tan(pw.phase_shifts(k, a, V0, 8)), np.tan(d0), rtol=1e-6, atol=1e-8)
+
+
+def test_scattered_wave_tends_to_the_amplitude():
+    """r e^{-ikr} psi_sc(r) -> f(theta) at large kr (the neglected terms are
+    of order l^2 / kr for the partial waves that carry the amplitude)."""
+    k, a, V0 = 1.0, 2.0, 0.3
+    th = np.linspace(0.0, math.pi, 13)
+    r = 4.0e5
+    lim = r * np.exp(-1j * k * r) * pw.scattered_wave(k, a, V0, r, th)
+    f = pw.amplitude(k, a, V0, th)
+    assert np.abs(lim - f).max() <= 2e-4 * np.abs(f).max()
+
+
+def test_scattered_wave_is_the_born_integral_for_a_weak_potential():
+    """At finite r (kr = 6, outside the ball) and weak V0 the exact scattered
+    wave equals the first-Born integral -(2m/hbar^2)(V0 / 4 pi) int_ball
+    e^{ik|r - r'|} / |r - r'| e^{ikz'} d^3r', evaluated here by a product
+    Gauss-Legendre rule over the ball, to O(V0)."""
+    k, a = 1.0, 1.5
+    E = 0.5 * k * k
+    V0 = 1e-3 * E
+    rr = 6.0
+    th = np.array([0.0, 0.7, 1.6, 2.5, math.pi])
+    xr, wr = np.polynomial.legendre.leggauss(28)
+    xc, wc = np.polynomial.legendre.leggauss(36)
+    rp = 0.5 * a * (xr + 1)
+    wrp = 0.5 * a * wr * rp ** 2
+    nph = 48
+    php = 2 * math.pi * np.arange(nph) / nph
+    R, C, Ph = np.meshgrid(rp, xc, php, indexing="ij")
+    W = wrp[:, None, None] * wc[None, :, None] * (2 * math.pi / nph)
+    S = np.sqrt(1 - C * C)
+    Xp, Yp, Zp = R * S * np.cos(Ph), R * S * np.sin(Ph), R * C
+    born = []
+    for t in th:
+        x, z = rr * math.sin(t), rr * math.cos(t)
+        dist = np.sqrt((x - Xp) ** 2 + Yp ** 2 + (z - Zp) ** 2)
+        integ = np.sum(W * np.exp(1j * k * dist) / dist * np.exp(1j * k * Zp))
+        born.append(-(2 * V0) / (4 * math.pi) * integ)
+    born = np.array(born)
+    exact = pw.scattered_wave(k, a, V0, rr, th)
+    assert np.abs(exact - born).max() <= 5e-3 * np.abs(born).max()
