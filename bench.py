@@ -71,7 +71,7 @@ def main():
                     help="single: equivalence surface (sphere r = 5 with a shell DFT, or the box planes at "
                          "N/2 -+ 40 with the plane sums inside the passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3"], default="single",
                     help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
                          "adjoint: misfit gradient of the 160^3 voxel potential (6000 steps)")
     ap.add_argument("--fd-voxels", type=int, default=64, help="adjoint: finite-difference check voxels")
@@ -107,6 +107,8 @@ def main():
         return bench_project(args)
     if args.workload == "subdomain":
         return bench_subdomain(args)
+    if args.workload == "x3":
+        return bench_x3(args)
 
     prob, V = synth.square_barrier_160(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window
@@ -386,6 +388,81 @@ def bench_subdomain(args):
         "local_gcell_per_s": round(local * args.steps / (ms / 1e3) / 1e9, 3),
         "pass_ms_in_steps": {k: round(pass_ms[i] / min(args.steps, 50), 5) for i, k in enumerate("xyz")},
         "tiles": [list(t) for t in tiles],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_x3(args):
+    """The paper's Section-4 run at its scale on one grid: central square
+    potentials of radius 4 pi with s = 1, 0.5, -0.5, -1 at 20 points per
+    wavelength (288^3, dtau = pi/1000, incidence along y; 36000 steps, 60000
+    for the deep well), each solve timed whole; the far field, Psi at r_bar =
+    2e4 and at r_bar = 100 against the exact partial-wave solution
+    (solid-angle weighted rel-L2 over the x-y and y-z planes)."""
+    import numpy as np
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+
+    # the exact partial-wave solution, stored by tests/golden/make_square_potential_reference.py
+    root = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(root, "tests", "golden", "square_potential_reference.json")) as fh:
+        gold = json.load(fh)
+
+    def exact(sv, key):
+        re_, im_ = gold["potentials"][str(sv)][key]
+        v = np.asarray(re_) + 1j * np.asarray(im_)
+        return np.concatenate([v, v])   # x-y and y-z planes
+
+    g = np.deg2rad(np.asarray(gold["angles_deg"]))
+    dirs = np.concatenate([np.stack([np.sin(g), np.cos(g), 0 * g], -1), np.stack([0 * g, np.cos(g), np.sin(g)], -1)])
+    gam = np.concatenate([g, g])
+    w = np.sin(gam) + 1e-2
+
+    def rel(a, b):
+        return math.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2))
+
+    stream = torch.cuda.current_stream()
+    total_cells, total_s, acc = 0, 0.0, {}
+    for sv, steps in ((1.0, 36000), (0.5, 36000), (-0.5, 36000), (-1.0, 60000)):
+        prob, V = synth.x3_square_potential(sv, n_steps=steps)
+        k = prob.k0
+        sol = P.Solver(prob, stream=stream)
+        sol.set_potential(V)
+        sol.autotune(reps=5)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sol.run(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_s += e0.elapsed_time(e1) / 1e3
+        total_cells += prob.cells * steps
+        err = {"far": rel(sol.far_field(dirs).cpu().numpy(), exact(sv, "far"))}
+        for rb in (2e4, 100.0):
+            err[f"r{int(rb)}"] = rel(sol.project(dirs * (rb / k)).cpu().numpy(), exact(sv, f"r{int(rb)}"))
+        acc[f"s={sv}"] = {kk: round(vv, 5) for kk, vv in err.items()}
+        sol.close()
+        print(f"x3 s={sv}: {steps} steps, {acc[f's={sv}']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "PSTD Gcell-updates/s, the paper's square potentials at its scale (288^3, 20 points per wavelength)",
+        "value": round(total_cells / total_s / 1e9, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": 168000,
+        "warmup": 0,
+        "ms_per_step": round(1e3 * total_s / 168000, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "central square potential r_bar <= 4 pi, s = 1, 0.5, -0.5, -1; 288^3 FFT grid, dxb = "
+                               "pi/10, dtau = pi/1000, 40-cell absorber, 41 SF cells, 12-cell taper, box on the SF "
+                               "mid planes, incidence along y", "cells": 288 ** 3},
+        "rel_l2_vs_partial_waves": acc,
+        "solve_s": round(total_s, 2),
     }
     print(json.dumps(out), flush=True)
 

@@ -229,6 +229,35 @@ def wide_layer_reference(prob, V, n_fft=96, width=32):
     return p, W
 
 
+def x3_square_potential(s, n_fft=288, n_steps=36000, ramp_periods=2.0):
+    """The paper's own run of Section 4 at its scale on one grid: central
+    square potential V = s E0 for r_bar <= 4 pi (Eq. sphericalV), 20 points
+    per wavelength (dxb = pi/10), dtau = pi/1000, incident along +y; per axis
+    a 40-cell absorber (U0 = 5, alpha = 0.1 per cell), 41 scattered-field
+    cells, a 12-cell taper, box planes on the middle planes of the
+    scattered-field region.  The paper's 288 x 290 x 288 (two overlapping
+    y subdomains) becomes one n_fft^3 grid; the window is the last 4
+    periods.  36000 steps settle s = 1, 0.5, -0.5; the deep well s = -1
+    holds a slowly decaying quasi-bound state and needs about 60000."""
+    h = 0.1
+    k0 = math.pi / (10 * h)
+    E0 = k0 * k0 / 2
+    N = n_fft
+    P = 40
+    y0, y1 = P + 41, P + 41 + 12
+    tf = (y0, y1, N - 1 - y1, N - 1 - y0)
+    mid = P + 20
+    dtau = math.pi / 1000
+    window = int(round(4 * 2 * math.pi / dtau))
+    prob = Problem(n=(N,) * 3, h=(h, h, h), k0=k0, theta=math.pi / 2, phi=math.pi / 2,
+                   abc_cells=(P,) * 3, abc_U0=5.0, abc_alpha=0.1, tfsf=(tf,) * 3,
+                   v_max=abs(s) * E0, dt=dtau / E0, ramp_periods=ramp_periods, n_steps=n_steps,
+                   dft_begin=n_steps - window, dft_end=n_steps,
+                   surf_lo=(mid,) * 3, surf_hi=(N - 1 - mid,) * 3)
+    V = square_barrier(prob.n, prob.h, 4 * math.pi / k0, s * E0)
+    return prob, V
+
+
 def plain_barrier_refined():
     """The plain-method barrier (r = 0.6, V0 = E0/2, k0 = pi/(4h0), h0 = 0.1)
     at half the spacing, h = 0.05, with an absorber twice as wide (32 cells,

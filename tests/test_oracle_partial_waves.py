@@ -103,3 +103,22 @@ def test_scattered_wave_is_the_born_integral_for_a_weak_potential():
     born = np.array(born)
     exact = pw.scattered_wave(k, a, V0, rr, th)
     assert np.abs(exact - born).max() <= 5e-3 * np.abs(born).max()
+
+
+def test_stored_square_potential_reference_is_the_oracle():
+    """tests/golden/square_potential_reference.json (read by the benchmark)
+    holds what the oracle gives now."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "square_potential_reference.json")
+    gold = json.load(open(path))
+    th = np.deg2rad(np.asarray(gold["angles_deg"]))
+    k, a = gold["k0"], gold["radius"]
+    for s in ("1.0", "-1.0"):
+        V0 = float(s) * k * k / 2
+        f = pw.amplitude(k, a, V0, th)
+        re_, im_ = gold["potentials"][s]["far"]
+        assert np.allclose(np.asarray(re_) + 1j * np.asarray(im_), f, rtol=1e-12, atol=1e-14)
+        v = pw.scattered_wave(k, a, V0, 100.0 / k, th)
+        re_, im_ = gold["potentials"][s]["r100"]
+        assert np.allclose(np.asarray(re_) + 1j * np.asarray(im_), v, rtol=1e-12, atol=1e-14)
