@@ -103,6 +103,17 @@ typedef struct pstd_problem {
      * times the number of axes with a layer).  0, 0: the mask alone. */
     double  abc_UR;
     double  abc_alphaR;
+    /* Step scheme.  0: the spectral step of Eq. PSTDupdating.  1: the FDTD
+     * variant of Section 2.3: the eighth-order central stencil of Eq.
+     * y_stencil (Eq. stencil_alpha) on the periodic grid, Eq.
+     * FDTDupdatePsi with V multiplying psi^n, no eta correction, a sharp
+     * total-field box y1 <= i <= y2 per axis whose walls carry the
+     * consistency terms of Eqs. FDTDpsi_extraJminus1-FDTDpsiJplus4 (y0, y3
+     * unused), the same mask; step bound dtau <= 1 / (|alpha_0 + 2 sum_l
+     * alpha_l (-1)^l| sum_a 1/dxb_a^2 + |v|max).  Scheme 1 runs the plain
+     * solve only: an empty DFT window, surface_kind 0, no subdomains, no
+     * batch and no misfit (EUNSUPPORTED otherwise). */
+    int32_t scheme;
 } pstd_problem;
 
 typedef struct pstd_solver pstd_solver;  /* opaque; owns all its device memory */

@@ -14,8 +14,9 @@ total-field region is the box y1 <= i <= y2 of every axis with a sharp
 interface, and the incident plane wave enters through the consistency terms
 of Eqs. FDTDpsi_extraJminus1-FDTDpsiJplus4 on the four cells either side of
 each wall, accumulated wall by wall on the lines whose transverse indices lie
-in the total-field box.  The mask of Eq. expmask multiplies the update as in
-the spectral scheme.  No eta correction: the FDTD scheme has none.
+in the total-field box, at the scheme's discrete frequency for k_hat.  The
+mask of Eq. expmask multiplies the update as in the spectral scheme.  No eta
+correction: the FDTD scheme has none.
 """
 from __future__ import annotations
 
@@ -75,6 +76,18 @@ class Model:
     phase: np.ndarray      # exp(i k_hat . r_bar)
     kh: np.ndarray
     tau_r: float
+    omega: float           # discrete frequency of the incident wave (discrete_frequency)
+
+
+def discrete_frequency(kh, dxb, dtau):
+    """The frequency at which the plane wave exp(i k_hat . r_bar) solves the
+    discrete scheme exactly with v = 0: sin(W dtau) = dtau k_h^2, k_h^2 =
+    -sum_a symbol(kh_a dxb_a) / dxb_a^2 (1 + O(dtau^2) + O(dxb^8)).  The
+    walls drive the incident wave at W, so that the consistency terms cancel
+    the stencil's dispersion (the paper states no frequency; the spectral
+    scheme reaches the same end with eta)."""
+    k2 = -sum(float(stencil_symbol(kh[a] * dxb[a])) / dxb[a] ** 2 for a in range(3))
+    return math.asin(dtau * k2) / dtau
 
 
 def build(prob, V):
@@ -90,7 +103,8 @@ def build(prob, V):
     kh = _pstd.khat(prob.theta, prob.phi)
     X = [_pstd._bcast(_pstd.coords(n[a], dxb[a]), a) for a in range(3)]
     phase = np.exp(1j * (kh[0] * X[0] + kh[1] * X[1] + kh[2] * X[2])) * np.ones_like(G, dtype=np.complex128)
-    return Model(prob, dtau, dxb, v, G, box, phase, kh, 2 * math.pi * prob.ramp_periods)
+    return Model(prob, dtau, dxb, v, G, box, phase, kh, 2 * math.pi * prob.ramp_periods,
+                 discrete_frequency(kh, dxb, dtau))
 
 
 def total_field_mask(model):
@@ -106,9 +120,9 @@ def total_field_mask(model):
 
 
 def incident(model, n):
-    """R(tau_n) exp(i(k_hat . r_bar - tau_n))."""
+    """R(tau_n) exp(i(k_hat . r_bar - W tau_n)), W the discrete frequency."""
     tau = n * model.dtau
-    return _pstd.ramp(tau, model.tau_r) * np.exp(-1j * tau) * model.phase
+    return _pstd.ramp(tau, model.tau_r) * np.exp(-1j * model.omega * tau) * model.phase
 
 
 def wall_terms(model, psi_inc):

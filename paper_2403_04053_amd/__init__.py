@@ -76,6 +76,7 @@ class pstd_problem(ctypes.Structure):
         ("sphere_radius", ctypes.c_double),
         ("abc_UR", ctypes.c_double),
         ("abc_alphaR", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -95,6 +96,7 @@ def problem_from(obj) -> pstd_problem:
         setattr(p, name, float(getattr(obj, name)))
     p.abc_UR = float(getattr(obj, "abc_UR", 0.0))
     p.abc_alphaR = float(getattr(obj, "abc_alphaR", 0.0))
+    p.scheme = int(getattr(obj, "scheme", 0))
     p.force_dt = int(bool(getattr(obj, "force_dt", False)))
     p.eta_on_source = int(bool(getattr(obj, "eta_on_source", False)))
     p.dft_begin = int(obj.dft_begin)

@@ -66,7 +66,14 @@ pstd_status reduced(const pstd_problem* p, double* E0, double* dxb, double* dtau
     int layers = 0;
     for (int a = 0; a < 3; ++a) layers += p->abc_cells[a] > 0;
     const double vmax = std::max(p->v_max / *E0, std::fabs(p->abc_UR) * layers);
-    *dtau_crit = 1.0 / (kPi * kPi * s + vmax);
+    if (p->scheme == 1) {
+        // FDTD: the stencil's symbol peaks at the Nyquist corner, |alpha_0 + 2 sum_l alpha_l (-1)^l|
+        double sym = pstd::kFdtdAlpha[0];
+        for (int l = 1; l <= 4; ++l) sym += 2.0 * pstd::kFdtdAlpha[l] * ((l & 1) ? -1.0 : 1.0);
+        *dtau_crit = 1.0 / (std::fabs(sym) * s + vmax);
+    } else {
+        *dtau_crit = 1.0 / (kPi * kPi * s + vmax);
+    }
     *dtau = p->dt > 0 ? *E0 * p->dt / p->hbar : 0.9 * *dtau_crit;
     *eta = std::sin(*dtau) / *dtau;
     return PSTD_OK;
@@ -79,11 +86,19 @@ pstd_status validate(const pstd_problem* p) {
     if (!(p->dt >= 0)) return fail(nullptr, PSTD_EINVAL, "dt must be >= 0");
     if (!std::isfinite(p->abc_UR) || !(p->abc_alphaR >= 0))
         return fail(nullptr, PSTD_EINVAL, "abc_UR must be finite and abc_alphaR >= 0");
+    if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, PSTD_EINVAL, "scheme must be 0 or 1");
+    if (p->scheme == 1) {
+        if (p->sub_core[0] || p->sub_core[1] || p->sub_core[2] || p->surface_kind != 0 || p->dft_end > p->dft_begin)
+            return fail(nullptr, PSTD_EUNSUPPORTED,
+                        "the FDTD scheme runs the plain solve only (no subdomains, no surface DFT window)");
+    }
     for (int a = 0; a < 3; ++a) {
         const int N = p->n[a];
         if (N < 8 || (N & 1)) return fail(nullptr, PSTD_EINVAL, "grid lengths must be even and >= 8");
         if (!(p->h[a] > 0)) return fail(nullptr, PSTD_EINVAL, "grid spacing must be positive");
-        if (p->sub_core[a] > 0) {
+        if (p->scheme == 1) {
+            // the stencil works on any length
+        } else if (p->sub_core[a] > 0) {
             const int C = p->sub_core[a], nloc = C + 2 * p->sub_halo;
             if (N % C) return fail(nullptr, PSTD_EINVAL, "sub_core must divide the grid length");
             if (p->sub_taper < 0 || p->sub_halo < p->sub_taper + 5)
@@ -239,6 +254,22 @@ pstd_status build_tables(pstd_solver* s) {
             // (z2 + 2 i kh z1) e^{i ph}
             const double ar = z2, ai = 2.0 * s->kh[a] * z1;
             dz[i] = make_float2((float)(ar * er - ai * ei), (float)(ar * ei + ai * er));
+            if (p.scheme == 1) {
+                // sharp box T = [y1 <= i <= y2]; zt = T e^{i ph}, dz = -C e^{i ph} / dxb^2 with
+                // C = sum_l alpha_l sum_pm [T(i) - T(i pm l)] e^{pm i kh l dxb} (wall terms)
+                const int* y = p.tfsf[a];
+                auto T = [&](int j) { return (j >= y[1] && j <= y[2]) ? 1.0 : 0.0; };
+                double cr = 0, ci = 0;
+                for (int l = 1; l <= 4; ++l)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        const double w = pstd::kFdtdAlpha[l] * (T(i) - T(i + sg * l));
+                        cr += w * std::cos(sg * s->kh[a] * l * dxb);
+                        ci += w * std::sin(sg * s->kh[a] * l * dxb);
+                    }
+                const double f = -1.0 / (dxb * dxb);
+                zt[i] = make_float2((float)(T(i) * er), (float)(T(i) * ei));
+                dz[i] = make_float2((float)(f * (cr * er - ci * ei)), (float)(f * (cr * ei + ci * er)));
+            }
         }
         // spectral-derivative rows: d(e) = (1/Nl) sum_m i kbar_m exp(2 pi i m (i0 - e)/Nl)
         for (int side = 0; side < 2; ++side) {
@@ -289,7 +320,40 @@ pstd_status build_tables(pstd_solver* s) {
 
 // launch step ctr[0] + koff, step koff of a group of `count` launched
 // together, on `stream`
+// the FDTD step's arguments (scheme 1)
+pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
+    pstd::FdtdArgs a{};
+    a.buf[0] = s->buf[0];
+    a.buf[1] = s->buf[1];
+    a.v2 = s->v2;
+    a.nx = s->prob.n[0];
+    a.ny = s->prob.n[1];
+    a.nz = s->prob.n[2];
+    double kc = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.gam[ax] = s->ax[ax].gam;
+        a.zt[ax] = s->ax[ax].zt;
+        a.dz[ax] = s->ax[ax].dz;
+        const double f = -2.0 * s->dtau / (s->dxb[ax] * s->dxb[ax]);
+        kc += f * pstd::kFdtdAlpha[0];
+        for (int l = 1; l <= 4; ++l) a.k[ax][l - 1] = (float)(f * pstd::kFdtdAlpha[l]);
+    }
+    a.kc = (float)kc;
+    a.ctr = s->ctr;
+    a.sigma_tab = s->sigma_tab;
+    return a;
+}
+
 pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int count, hipEvent_t* ev) {
+    if (s->prob.scheme == 1) {
+        // one stencil kernel per step; its time goes to the x slot of the timers
+        if (ev) HIP_TRY(s, hipEventRecord(ev[0], stream));
+        hipError_t e = pstd::launch_fdtd(fdtd_args(s), koff, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "FDTD launch");
+        if (ev)
+            for (int i = 1; i < 6; ++i) HIP_TRY(s, hipEventRecord(ev[i], stream));
+        return PSTD_OK;
+    }
     if (s->sphere) {
         // shell DFT in pairs of steps of the group (the odd step adds the even
         // one before it; a last even step goes alone), before this step's z
@@ -394,11 +458,12 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     std::vector<float2> sig(cap);
     std::vector<double2> w(cap);
     std::vector<int> on(cap);
-    const double fac = 2.0 * s->dtau * (s->prob.eta_on_source ? s->eta : 1.0);
+    const double fac = 2.0 * s->dtau * (s->prob.eta_on_source && s->prob.scheme == 0 ? s->eta : 1.0);
     for (int64_t n = 0; n < cap; ++n) {
         const double tau = n * s->dtau;
         const double f = fac * ramp_of(tau, s->tau_r);
-        sig[n] = make_float2((float)(f * std::cos(tau)), (float)(-f * std::sin(tau)));
+        const double ph = s->omega * tau;
+        sig[n] = make_float2((float)(f * std::cos(ph)), (float)(-f * std::sin(ph)));
         w[n] = make_double2(std::cos(tau), std::sin(tau));
         on[n] = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
     }
@@ -457,6 +522,18 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     s->kh[0] = std::sin(th) * std::cos(ph);
     s->kh[1] = std::sin(th) * std::sin(ph);
     s->kh[2] = std::cos(th);
+    if (p->scheme == 1) {
+        // the walls drive the incident wave at the scheme's discrete frequency
+        // for k_hat: sin(W dtau) = dtau k_h^2, k_h^2 = -sum_a symbol(kh_a dxb_a) / dxb_a^2
+        double k2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double th_a = s->kh[a] * s->dxb[a];
+            double sym = pstd::kFdtdAlpha[0];
+            for (int l = 1; l <= 4; ++l) sym += 2.0 * pstd::kFdtdAlpha[l] * std::cos(l * th_a);
+            k2 -= sym / (s->dxb[a] * s->dxb[a]);
+        }
+        s->omega = std::asin(s->dtau * k2) / s->dtau;
+    }
     s->tau_r = 2 * kPi * p->ramp_periods;
     s->cells = (int64_t)p->n[0] * p->n[1] * p->n[2];
     s->points[0] = (int64_t)p->n[1] * p->n[2];
@@ -485,6 +562,8 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     if ((st = build_tables(s))) return cleanup(st);
     if (ext_ctr && p->surface_kind != 0)
         return cleanup(fail(s, PSTD_EUNSUPPORTED, "batch instances integrate over the box surface only"));
+    if (ext_ctr && p->scheme != 0)
+        return cleanup(fail(s, PSTD_EUNSUPPORTED, "batch instances run the spectral scheme only"));
     if ((st = sphere_create(s))) return cleanup(st);
     const int64_t c0[2] = {0, std::numeric_limits<int64_t>::max()};
     if ((e = hipMemcpy(s->ctr, c0, sizeof(c0), hipMemcpyHostToDevice))) return cleanup(hip_fail(s, e, "counters"));
@@ -539,6 +618,24 @@ pstd_status time_shapes(pstd_solver* s, int axis, const int* ids, int n, int32_t
         release();
         return hip_fail(s, e, "timing scratch");
     }
+    if (s->prob.scheme == 1) {
+        // the FDTD step is one kernel: time it (whatever the axis or shape)
+        FdtdArgs a = fdtd_args(s);
+        a.buf[0] = tb0;
+        a.buf[1] = tb1;
+        a.ctr = tctr;
+        float ms = 0;
+        e = launch_fdtd(a, 0, s->stream);
+        if (!e) e = hipEventRecord(e0, s->stream);
+        for (int r = 0; r < reps && !e; ++r) e = launch_fdtd(a, 0, s->stream);
+        if (!e) e = hipEventRecord(e1, s->stream);
+        if (!e) e = hipEventSynchronize(e1);
+        if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+        for (int k = 0; k < n; ++k) ms_out[k] = ms / reps;
+        release();
+        if (e) return hip_fail(s, e, "FDTD timing");
+        return PSTD_OK;
+    }
     const bool seg = s->prob.sub_core[axis] > 0;
     for (int k = 0; k < n && !e; ++k) {
         PassArgs a;
@@ -566,7 +663,9 @@ pstd_status time_shapes(pstd_solver* s, int axis, const int* ids, int n, int32_t
 }
 
 pstd_status solver_autotune(pstd_solver* s, int32_t reps) {
-    // time every compiled tile shape of each axis and keep the fastest
+    // time every compiled tile shape of each axis and keep the fastest (the
+    // FDTD step has one shape)
+    if (s->prob.scheme == 1) return PSTD_OK;
     for (int axis = 0; axis < 3; ++axis) {
         const bool seg = s->prob.sub_core[axis] > 0;
         int ids[16];

@@ -56,6 +56,25 @@ struct PassArgs {
     float2* const* stash_tab;
 };
 
+// One FDTD-variant step (eighth-order stencil, Section 2.3) for one solver:
+// psi^{n+1} = Gamma (psi^{n-1} - i q), q = kc psi + sum_a sum_l k[a][l-1]
+// (psi(-l e_a) + psi(+l e_a)) + v2 psi + sigma_n sum_a dz_a prod_{b != a} zt_b
+struct FdtdArgs {
+    float2* buf[2];
+    const float* v2;
+    int nx, ny, nz;
+    const float* gam[3];       // mask factors per axis
+    const float2* zt[3];       // T_a e^{i kh_a x_a}
+    const float2* dz[3];       // wall terms per axis (see fdtd.hip)
+    const int64_t* ctr;
+    const float2* sigma_tab;   // per step: 2 dtau R(tau_n) e^{-i tau_n}
+    float kc;                  // -2 dtau alpha_0 sum_a 1 / dxb_a^2
+    float k[3][4];             // -2 dtau alpha_l / dxb_a^2, l = 1..4
+};
+hipError_t launch_fdtd(const FdtdArgs& args, int koff, hipStream_t stream);
+// the stencil coefficients of Eq. stencil_alpha
+extern const double kFdtdAlpha[5];
+
 // FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
 struct PassShape {
     int N, N1, N2, P, threads;

@@ -21,6 +21,7 @@ struct pstd_solver {
     hipStream_t stream = nullptr;
     int device = 0;
     double E0 = 0, dtau = 0, eta = 0, tau_r = 0;
+    double omega = 1;      // frequency of the incident wave per unit tau (FDTD: the discrete one)
     double dxb[3] = {0, 0, 0};
     double kh[3] = {0, 0, 0};
     int64_t cells = 0;

@@ -48,6 +48,7 @@ class Problem:
     abc_alpha: float = 0.5
     abc_UR: float = 0.0            # real part of a complex absorbing potential (units of E0)
     abc_alphaR: float = 0.0        # its decay per cell; 0: abc_alpha
+    scheme: int = 0                # 0: spectral step; 1: the eighth-order FDTD variant
     tfsf: tuple = ((12, 18, 30, 36),) * 3
     v_max: float = 0.0
     dt: float = 0.0

@@ -134,3 +134,21 @@ def test_wall_terms_equal_the_compact_form():
                 In = np.roll(inc, -sgn * l, axis=ax)
                 compact += fdtd.ALPHA[l] * (T - Tn) * In / m.dxb[a] ** 2
     assert np.abs(fdtd.wall_terms(m, inc) - compact).max() < 1e-12 * np.abs(compact).max()
+
+
+def test_walls_hold_the_analytic_wave_at_the_discrete_frequency():
+    """Started exactly after the ramp, the incident plane wave of any
+    direction (not a grid mode) driven at the discrete frequency stays in the
+    box and out of the scattered-field region to rounding: the walls only
+    reach cells near the box, where the plane wave solves the stencil."""
+    prob, V = synth.tiny(n=(32, 32, 32), P=4, transition=2, v0=0.0, radius_cells=0, steps=400,
+                         theta=0.9, phi=0.4, dft=(0, 0))
+    prob = prob.replace(scheme=1, ramp_periods=0.5)
+    m = fdtd.build(prob, V)
+    assert m.omega == pytest.approx(1.0, abs=1e-3) and m.omega != 1.0
+    T = fdtd.total_field_mask(m)
+    n0 = int(m.tau_r / m.dtau) + 2
+    prev, cur = T * fdtd.incident(m, n0 - 1), T * fdtd.incident(m, n0)
+    for s in range(n0, n0 + 300):
+        prev, cur = cur, fdtd.step(m, prev, cur, s)
+    assert np.abs(cur - T * fdtd.incident(m, n0 + 300)).max() < 1e-12
