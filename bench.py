@@ -71,7 +71,7 @@ def main():
                     help="single: equivalence surface (sphere r = 5 with a shell DFT, or the box planes at "
                          "N/2 -+ 40 with the plane sums inside the passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3", "fdtd"], default="single",
                     help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
                          "adjoint: misfit gradient of the 160^3 voxel potential (6000 steps)")
     ap.add_argument("--fd-voxels", type=int, default=64, help="adjoint: finite-difference check voxels")
@@ -109,6 +109,8 @@ def main():
         return bench_subdomain(args)
     if args.workload == "x3":
         return bench_x3(args)
+    if args.workload == "fdtd":
+        return bench_fdtd(args)
 
     prob, V = synth.square_barrier_160(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window
@@ -388,6 +390,57 @@ def bench_subdomain(args):
         "local_gcell_per_s": round(local * args.steps / (ms / 1e3) / 1e9, 3),
         "pass_ms_in_steps": {k: round(pass_ms[i] / min(args.steps, 50), 5) for i, k in enumerate("xyz")},
         "tiles": [list(t) for t in tiles],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_fdtd(args):
+    """The eighth-order FDTD variant of the step (Section 2.3) on the 160^3
+    square-barrier grid (same physics, TF/SF box, absorber), no surface DFT:
+    one stencil kernel per step.  Its algorithmic bytes are the step's floor,
+    28 B/cell (read psi^n, psi^{n-1}, V; write psi^{n+1})."""
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+    prob, V = synth.square_barrier_160(n_fft=args.n)
+    prob = prob.replace(scheme=1, dft_begin=0, dft_end=0)
+    stream = torch.cuda.current_stream()
+    s = P.Solver(prob, stream=stream)
+    s.set_potential(V)
+    s.autotune(reps=3)
+    s.run(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = prob.cells
+    us = s.pass_time(0, reps=100)
+    achieved = STEP_BYTES * cells / (us / 1e6) / 1e9
+    finite = bool(torch.isfinite(torch.view_as_real(s.psi(0))).all().item())
+    out = {
+        "metric": "FDTD-8 Gcell-updates/s (FP32 step)",
+        "value": round(cells * args.steps / (ms / 1e3) / 1e9, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 grid, eighth-order FDTD step, TF/SF walls "
+                               "+ absorber, no surface DFT", "cells": cells},
+        "roofline": {"bound": "hbm", "kernel": "fdtd", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": STEP_BYTES, "kernel_us": round(us, 3)},
+        "finite": finite,
     }
     print(json.dumps(out), flush=True)
 

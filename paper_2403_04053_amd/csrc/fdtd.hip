@@ -13,7 +13,7 @@
 // e^{pm i kh_a l dxb_a}: the same form as the taper source of the spectral
 // scheme, so the same per-axis tables carry it.
 //
-// A workgroup owns a 32 x 8 tile of (x, y) columns and a run of z planes.
+// A workgroup owns a 32 x 8 tile of (x, y) columns and a run of 16 z planes.
 // Each thread keeps the nine values psi(z-4 .. z+4) of its column in VGPRs
 // (the z stencil) and the plane z of the tile with a 4-cell halo is staged
 // in LDS (the x and y stencils); the planes advance by one load per thread.
@@ -46,13 +46,21 @@ __global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
     if (nstep >= a.ctr[1]) return;  // whole workgroup, before any barrier
     const float2* __restrict__ psi = (nstep & 1) ? a.buf[1] : a.buf[0];
     float2* __restrict__ old = (nstep & 1) ? a.buf[0] : a.buf[1];
-    const int bx = blockIdx.x * kFX, by = blockIdx.y * kFY;
+    // Workgroups are dealt round-robin to the 8 XCDs (blockIdx mod 8); give
+    // each XCD a contiguous run of tiles (x fastest, then y, then z) instead,
+    // so that the halo rows and planes a tile shares with its neighbours meet
+    // in one L2.  A bijection of [0, G).
+    const int gx = (nx + kFX - 1) / kFX, gy = (ny + kFY - 1) / kFY;
+    const int G = (int)gridDim.x, gb = (int)blockIdx.x, xcd = gb & 7;
+    const int gt = xcd * (G >> 3) + min(xcd, G & 7) + (gb >> 3);
+    const int bx = (gt % gx) * kFX, by = ((gt / gx) % gy) * kFY;
+    const int bz = gt / (gx * gy);
     const int x = bx + tx, y = by + ty;
     const bool valid = x < nx && y < ny;
     const int xw = wrap(x, nx), yw = wrap(y, ny);
     const int64_t col = xw + (int64_t)nx * yw;
     const int64_t plane = (int64_t)nx * ny;
-    const int z0 = blockIdx.z * kFZ;
+    const int z0 = bz * kFZ;
     const int z1 = min(z0 + kFZ, nz);
 
     // the column psi(z0-4 .. z0+4)
@@ -109,9 +117,8 @@ __global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
 const double kFdtdAlpha[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 
 hipError_t launch_fdtd(const FdtdArgs& a, int koff, hipStream_t stream) {
-    const dim3 grid((unsigned)((a.nx + kFX - 1) / kFX), (unsigned)((a.ny + kFY - 1) / kFY),
-                    (unsigned)((a.nz + kFZ - 1) / kFZ));
-    hipLaunchKernelGGL(fdtd_kernel, grid, dim3(kFX, kFY), 0, stream, a, koff);
+    const int tiles = ((a.nx + kFX - 1) / kFX) * ((a.ny + kFY - 1) / kFY) * ((a.nz + kFZ - 1) / kFZ);
+    hipLaunchKernelGGL(fdtd_kernel, dim3((unsigned)tiles), dim3(kFX, kFY), 0, stream, a, koff);
     return hipGetLastError();
 }
 
