@@ -43,11 +43,19 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/cs
                   "paper_2403_04053_amd/csrc/internal.hpp")
 
 
-def kernel_src_sha256():
+# The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
+# the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
+FDTD_TRAFFIC_SRC_SHA256 = "5c5233704d2e1029c9cb09207519778cfc555ae89ab3024331f2d24a7766be19"
+FDTD_TRAFFIC_KIB = {160: (105868, 32000)}
+FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
+                "paper_2403_04053_amd/csrc/internal.hpp")
+
+
+def kernel_src_sha256(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -58,6 +66,13 @@ def measured_traffic(tile, axis):
     if TRAFFIC_SRC_SHA256 is None or kernel_src_sha256() != TRAFFIC_SRC_SHA256:
         return None
     kib = TRAFFIC_KIB.get((*tile, axis))
+    return None if kib is None else 1024 * (kib[0] + kib[1])
+
+
+def measured_fdtd_traffic(n):
+    if FDTD_TRAFFIC_SRC_SHA256 is None or kernel_src_sha256(FDTD_SOURCES) != FDTD_TRAFFIC_SRC_SHA256:
+        return None
+    kib = FDTD_TRAFFIC_KIB.get(n)
     return None if kib is None else 1024 * (kib[0] + kib[1])
 
 
@@ -438,8 +453,9 @@ def bench_fdtd(args):
         "config": {"workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 grid, eighth-order FDTD step, TF/SF walls "
                                "+ absorber, no surface DFT", "cells": cells},
         "roofline": {"bound": "hbm", "kernel": "fdtd", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_cell": STEP_BYTES, "kernel_us": round(us, 3)},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_fdtd_traffic(args.n), "bytes_per_cell": STEP_BYTES,
+                     "kernel_us": round(us, 3)},
         "finite": finite,
     }
     print(json.dumps(out), flush=True)

@@ -16,7 +16,9 @@
 // A workgroup owns a 32 x 8 tile of (x, y) columns and a run of 16 z planes.
 // Each thread keeps the nine values psi(z-4 .. z+4) of its column in VGPRs
 // (the z stencil) and the plane z of the tile with a 4-cell halo is staged
-// in LDS (the x and y stencils); the planes advance by one load per thread.
+// in LDS (the x and y stencils).  The loads of plane z + 1 (the halo cells,
+// the next column value, psi^{n-1} and V) are issued right after plane z is
+// staged, so they are in flight while plane z is computed.
 // The grid is periodic (indices wrap), like the spectral passes.
 #include "dft.hpp"
 #include "internal.hpp"
@@ -37,7 +39,9 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-__global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
+// Five waves per SIMD: the prefetched plane needs about 96 VGPRs, and the
+// register cap of six or more waves serialises its loads or spills.
+__global__ __launch_bounds__(kFX * kFY) __attribute__((amdgpu_waves_per_eu(5))) void fdtd_kernel(FdtdArgs a, int koff) {
     __shared__ float2 s[kSY][kSX + 1];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int t = ty * kFX + tx;
@@ -77,15 +81,49 @@ __global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
     const float gxy = a.gam[0][xw] * a.gam[1][yw];
     const float2 sigma = a.sigma_tab[nstep];
 
-    for (int z = z0; z < z1; ++z) {
-        // plane z of the tile and its halo
-        s[ty + kFH][tx + kFH] = q[kFH];
-        for (int e = t; e < kSY * kSX; e += kFX * kFY) {
-            const int r = e / kSX, c = e % kSX;
-            if (r >= kFH && r < kFH + kFY && c >= kFH && c < kFH + kFX) continue;
-            s[r][c] = psi[wrap(bx + c - kFH, nx) + (int64_t)nx * wrap(by + r - kFH, ny) + plane * z];
+    // this thread's halo cells of the staged tile (at most three: 384 halo
+    // cells over 256 threads), fixed for the run: LDS slot and column offset
+    constexpr int kSlots = (kSY * kSX + kFX * kFY - 1) / (kFX * kFY);
+    int hslot[kSlots];
+    int hcol[kSlots];  // a plane holds fewer than 2^31 cells
+    unroll<kSlots>([&](auto i) {
+        constexpr int j = decltype(i)::value;
+        const int e = t + j * kFX * kFY;
+        const int r = e / kSX, c = e % kSX;
+        const bool halo = e < kSY * kSX && !(r >= kFH && r < kFH + kFY && c >= kFH && c < kFH + kFX);
+        hslot[j] = halo ? e : -1;
+        hcol[j] = halo ? wrap(bx + c - kFH, nx) + nx * wrap(by + r - kFH, ny) : 0;
+    });
+    // loads of plane z, issued one plane ahead: the halo cells and the
+    // epilogue operands psi^{n-1} and V of this thread's cell
+    float2 hv[kSlots];
+    float2 po_n = make_float2(0.f, 0.f);
+    float vv_n = 0.f;
+    auto load_plane = [&](int z) {
+        unroll<kSlots>([&](auto i) {
+            constexpr int j = decltype(i)::value;
+            if (hslot[j] >= 0) hv[j] = psi[hcol[j] + plane * z];
+        });
+        if (valid) {
+            const int64_t ad = x + (int64_t)nx * y + plane * z;
+            po_n = old[ad];
+            vv_n = a.v2[ad];
         }
+    };
+    if (z0 < z1) load_plane(z0);
+
+    for (int z = z0; z < z1; ++z) {
+        // stage plane z: the own column value and the prefetched halo
+        s[ty + kFH][tx + kFH] = q[kFH];
+        unroll<kSlots>([&](auto i) {
+            constexpr int j = decltype(i)::value;
+            if (hslot[j] >= 0) s[hslot[j] / kSX][hslot[j] % kSX] = hv[j];
+        });
+        const float2 po = po_n;
+        const float vv = vv_n;
         __syncthreads();
+        if (z + 1 < z1) load_plane(z + 1);  // in flight during this plane's arithmetic
+        const float2 qn = psi[col + plane * wrap(z + kFH + 1, nz)];
         if (valid) {
             const float2 c0 = q[kFH];
             float2 k = cscale(c0, a.kc);
@@ -96,9 +134,8 @@ __global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
                 k = cadd(k, cscale(cadd(q[kFH - l], q[kFH + l]), a.k[2][l - 1]));
             });
             const int64_t ad = x + (int64_t)nx * y + plane * z;
-            const float2 po = old[ad];
             const float2 src = cadd(cmul(SA, a.zt[2][z]), cmul(SB, a.dz[2][z]));
-            const float2 qq = cadd(cadd(k, cscale(c0, a.v2[ad])), cmul(sigma, src));
+            const float2 qq = cadd(cadd(k, cscale(c0, vv)), cmul(sigma, src));
             const float g = gxy * a.gam[2][z];
             // psi^{n+1} = Gamma (psi^{n-1} - i q)
             old[ad] = make_float2(g * (po.x + qq.y), g * (po.y - qq.x));
@@ -108,7 +145,7 @@ __global__ __launch_bounds__(kFX * kFY) void fdtd_kernel(FdtdArgs a, int koff) {
             constexpr int r = decltype(i)::value;
             q[r] = q[r + 1];
         });
-        q[2 * kFH] = psi[col + plane * wrap(z + kFH + 1, nz)];
+        q[2 * kFH] = qn;
     }
 }
 
