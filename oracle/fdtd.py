@@ -183,3 +183,43 @@ def run(prob, V, n_steps=None):
     for n in range(n_steps):
         prev, cur = cur, step(model, prev, cur, n)
     return model, prev, cur
+
+
+class ShellDFT:
+    """Eq. psiphasor on the shell cells of a spherical surface, for the FDTD
+    variant: step n weighs exp(i W tau_n), W the incident wave's discrete
+    frequency, and the normalised phasor has the incident part removed.  The
+    stored field is psi_s + T psi_inc (T the total-field box, Eq.
+    psiTFvsNTF); the DFT of T R(tau_n) exp(i(k_hat . r_bar - W tau_n)) with
+    these weights is T exp(i k_hat . r_bar) sum_n R(tau_n), so after the
+    normalisation by sum_n R(tau_n) the incident part is T exp(i k_hat .
+    r_bar) exactly."""
+
+    def __init__(self, model, sphere):
+        self.m = model
+        self.mask = sphere.shell_mask()
+        self.phi = np.zeros(model.v.shape, np.complex128)
+        self.inc = 0.0
+
+    def accumulate(self, psi, n):
+        tau = n * self.m.dtau
+        self.phi[self.mask] += np.exp(1j * self.m.omega * tau) * psi[self.mask]
+        self.inc += _pstd.ramp(tau, self.m.tau_r)
+
+    def normalized(self):
+        out = self.phi / self.inc - total_field_mask(self.m) * self.m.phase
+        return np.where(self.mask, out, 0.0)
+
+
+def run_sphere(prob, V, sphere, n_steps=None):
+    """The FDTD march from rest with the shell DFT over [dft_begin, dft_end)."""
+    model = build(prob, V)
+    n_steps = prob.n_steps if n_steps is None else n_steps
+    prev = np.zeros(model.v.shape, np.complex128)
+    cur = np.zeros(model.v.shape, np.complex128)
+    sd = ShellDFT(model, sphere)
+    for n in range(n_steps):
+        if prob.dft_begin <= n < prob.dft_end:
+            sd.accumulate(cur, n)
+        prev, cur = cur, step(model, prev, cur, n)
+    return model, cur, sd

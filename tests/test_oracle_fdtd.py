@@ -152,3 +152,32 @@ def test_walls_hold_the_analytic_wave_at_the_discrete_frequency():
     for s in range(n0, n0 + 300):
         prev, cur = cur, fdtd.step(m, prev, cur, s)
     assert np.abs(cur - T * fdtd.incident(m, n0 + 300)).max() < 1e-12
+
+
+def test_shell_dft_removes_the_incident_wave_exactly():
+    """Started exactly after the ramp with no scatterer, the field is T psi_inc
+    at every step, so the normalised shell phasors vanish to rounding on a
+    sphere whose shell crosses the walls of the total-field box; weights at
+    the continuum frequency 1 instead of W leave a visible residue."""
+    from oracle import sphere as osph
+    prob, V = synth.tiny(n=(32, 32, 32), P=4, transition=2, v0=0.0, radius_cells=0, steps=400,
+                         theta=0.9, phi=0.4, dft=(0, 0))
+    prob = prob.replace(scheme=1, ramp_periods=0.5)
+    m = fdtd.build(prob, V)
+    # total-field box 8..24 around the centre 16: a sphere of 9 cells crosses its walls
+    assert m.box == ((8, 24),) * 3
+    sph = osph.Sphere(prob, 9 * prob.h[0], n_theta=8, n_phi=16)
+    sd = fdtd.ShellDFT(m, sph)
+    T = fdtd.total_field_mask(m)
+    assert T[sph.shell_mask()].min() == 0.0 and T[sph.shell_mask()].max() == 1.0
+    n0 = int(m.tau_r / m.dtau) + 2
+    prev, cur = T * fdtd.incident(m, n0 - 1), T * fdtd.incident(m, n0)
+    raw1 = np.zeros_like(sd.phi)
+    for s in range(n0, n0 + 300):
+        sd.accumulate(cur, s)
+        raw1[sd.mask] += np.exp(1j * s * m.dtau) * cur[sd.mask]
+        prev, cur = cur, fdtd.step(m, prev, cur, s)
+    out = sd.normalized()
+    assert np.abs(out).max() < 1e-12
+    resid1 = np.abs(np.where(sd.mask, raw1 / sd.inc - T * m.phase, 0.0)).max()
+    assert resid1 > 1e-4
