@@ -32,12 +32,12 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # 512 MiB: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # sources whose SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported
 # as null.  Key: (N, N1, N2, pencils per workgroup, axis).
-TRAFFIC_SRC_SHA256 = "8c30fe897317f2748e6845ea1b685cc1a31040b3f6115928f0c82df3bc42b25d"
+TRAFFIC_SRC_SHA256 = "e7bed74c77851615ec5e1b0faa5b5ae0b3f95cb0245201300b7632867a3bcaf3"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch; this workload's passes carry no surface DFT
-    (160, 10, 16, 16, 0): (32140, 32000), (160, 10, 16, 16, 1): (64155, 32000), (160, 10, 16, 16, 2): (112301, 32000),
-    (160, 10, 16, 32, 0): (32136, 32000), (160, 10, 16, 32, 1): (64164, 32000), (160, 10, 16, 32, 2): (112312, 32000),
-    (160, 10, 16, 8, 0): (32139, 32000), (160, 10, 16, 8, 1): (64182, 32150), (160, 10, 16, 8, 2): (112373, 32250),
-    (160, 16, 10, 16, 0): (32145, 32000), (160, 16, 10, 16, 1): (64169, 32000), (160, 16, 10, 16, 2): (112387, 32000),
+    (160, 10, 16, 16, 0): (32141, 32000), (160, 10, 16, 16, 1): (64159, 32000), (160, 10, 16, 16, 2): (112307, 32000),
+    (160, 10, 16, 32, 0): (32137, 32000), (160, 10, 16, 32, 1): (64168, 32000), (160, 10, 16, 32, 2): (112318, 32000),
+    (160, 10, 16, 8, 0): (32140, 32000), (160, 10, 16, 8, 1): (64181, 32162), (160, 10, 16, 8, 2): (112388, 32254),
+    (160, 16, 10, 16, 0): (32147, 32000), (160, 16, 10, 16, 1): (64173, 32000), (160, 16, 10, 16, 2): (112393, 32000),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")
@@ -45,8 +45,8 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/cs
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "5c5233704d2e1029c9cb09207519778cfc555ae89ab3024331f2d24a7766be19"
-FDTD_TRAFFIC_KIB = {160: (105868, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "7825d7f1ac9ccc0640185d81bdffc54c42ccec0ea9a958feb4a216825ece6442"
+FDTD_TRAFFIC_KIB = {160: (105875, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 

@@ -110,9 +110,13 @@ typedef struct pstd_problem {
      * total-field box y1 <= i <= y2 per axis whose walls carry the
      * consistency terms of Eqs. FDTDpsi_extraJminus1-FDTDpsiJplus4 (y0, y3
      * unused), the same mask; step bound dtau <= 1 / (|alpha_0 + 2 sum_l
-     * alpha_l (-1)^l| sum_a 1/dxb_a^2 + |v|max).  Scheme 1 runs the plain
-     * solve only: an empty DFT window, surface_kind 0, no subdomains, no
-     * batch and no misfit (EUNSUPPORTED otherwise). */
+     * alpha_l (-1)^l| sum_a 1/dxb_a^2 + |v|max).  The walls drive the
+     * incident wave at the scheme's discrete frequency W for k_hat,
+     * sin(W dtau) = dtau k_h^2 (k_h^2 the stencil's symbol summed over the
+     * axes), and the surface DFT weighs step n with exp(i W tau_n).  Scheme 1
+     * takes the spherical surface (surface_kind 1) for the surface DFT and
+     * the projection; a DFT window with the box surface, subdomains, batch
+     * instances and the misfit return EUNSUPPORTED. */
     int32_t scheme;
 } pstd_problem;
 

@@ -88,9 +88,11 @@ pstd_status validate(const pstd_problem* p) {
         return fail(nullptr, PSTD_EINVAL, "abc_UR must be finite and abc_alphaR >= 0");
     if (p->scheme != 0 && p->scheme != 1) return fail(nullptr, PSTD_EINVAL, "scheme must be 0 or 1");
     if (p->scheme == 1) {
-        if (p->sub_core[0] || p->sub_core[1] || p->sub_core[2] || p->surface_kind != 0 || p->dft_end > p->dft_begin)
+        if (p->sub_core[0] || p->sub_core[1] || p->sub_core[2])
+            return fail(nullptr, PSTD_EUNSUPPORTED, "the FDTD scheme has no subdomain mode");
+        if (p->surface_kind == 0 && p->dft_end > p->dft_begin)
             return fail(nullptr, PSTD_EUNSUPPORTED,
-                        "the FDTD scheme runs the plain solve only (no subdomains, no surface DFT window)");
+                        "the FDTD scheme accumulates the surface DFT on the spherical surface only (surface_kind 1)");
     }
     for (int a = 0; a < 3; ++a) {
         const int N = p->n[a];
@@ -345,6 +347,14 @@ pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
 }
 
 pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int count, hipEvent_t* ev) {
+    if (s->sphere) {
+        // shell DFT in pairs of steps of the group (the odd step adds the even
+        // one before it; a last even step goes alone), before this step
+        // overwrites psi^{n-1}
+        const int k = (koff & 1) ? 2 : (koff == count - 1 ? 1 : 0);
+        hipError_t e = pstd::sphere_launch_dft(s, koff, k, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "shell DFT launch");
+    }
     if (s->prob.scheme == 1) {
         // one stencil kernel per step; its time goes to the x slot of the timers
         if (ev) HIP_TRY(s, hipEventRecord(ev[0], stream));
@@ -353,14 +363,6 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
         if (ev)
             for (int i = 1; i < 6; ++i) HIP_TRY(s, hipEventRecord(ev[i], stream));
         return PSTD_OK;
-    }
-    if (s->sphere) {
-        // shell DFT in pairs of steps of the group (the odd step adds the even
-        // one before it; a last even step goes alone), before this step's z
-        // pass overwrites psi^{n-1}
-        const int k = (koff & 1) ? 2 : (koff == count - 1 ? 1 : 0);
-        hipError_t e = pstd::sphere_launch_dft(s, koff, k, stream);
-        if (e != hipSuccess) return hip_fail(s, e, "shell DFT launch");
     }
     for (int axis = 0; axis < 3; ++axis) {
         pstd::PassArgs a;
@@ -415,9 +417,12 @@ pstd_status solver_fail(pstd_solver* s, pstd_status st, const std::string& msg) 
 void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out) {
     const int N = s->prob.n[a];
     out.resize(N);
+    const int* y = s->prob.tfsf[a];
     for (int i = 0; i < N; ++i) {
         double z, z1, z2;
         taper(s->prob, a, s->dxb[a], i, &z, &z1, &z2);
+        // the FDTD scheme's total-field region is the sharp box y1 <= i <= y2
+        if (s->prob.scheme == 1) z = (i >= y[1] && i <= y[2]) ? 1.0 : 0.0;
         const double ph = s->kh[a] * (i - N / 2) * s->dxb[a];
         out[i] = make_double2(z * std::cos(ph), z * std::sin(ph));
     }
@@ -464,7 +469,8 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
         const double f = fac * ramp_of(tau, s->tau_r);
         const double ph = s->omega * tau;
         sig[n] = make_float2((float)(f * std::cos(ph)), (float)(-f * std::sin(ph)));
-        w[n] = make_double2(std::cos(tau), std::sin(tau));
+        // the DFT at the incident wave's frequency (1, or the FDTD scheme's W)
+        w[n] = make_double2(std::cos(s->omega * tau), std::sin(s->omega * tau));
         on[n] = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
     }
     // queued steps may still read the old tables

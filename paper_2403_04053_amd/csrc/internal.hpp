@@ -31,7 +31,7 @@ struct PassArgs {
     AxisTables ax[3];
     const int64_t* ctr;        // device counters: ctr[0] = step n, ctr[1] = end (n >= end: no work)
     const float2* sigma_tab;   // per step: 2 dtau R(tau_n) exp(-i tau_n) [* eta]
-    const double2* w_tab;      // per step: exp(i tau_n)
+    const double2* w_tab;      // per step: exp(i W tau_n), W the incident frequency
     const int* dft_tab;        // per step: 1 inside the surface-DFT window
     int plane_lo, plane_hi;    // plane indices along this pass's axis (local in segmented mode)
     double2* acc;              // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]

@@ -1,7 +1,8 @@
 """GPU parity of the FDTD variant (Section 2.3: eighth-order stencil, wall
 consistency terms, mask) against the FP64 oracle `oracle/fdtd.py`, through
-the C ABI.  Tolerances as for the spectral step: one FP32 step within 1e-5 of
-max|psi|, runs within 1e-4 rel-L2."""
+the C ABI, and its far field through the spherical surface.  Tolerances as
+for the spectral step: one FP32 step within 1e-5 of max|psi|, runs and
+phasors within 1e-4 rel-L2."""
 import math
 
 import numpy as np
@@ -9,6 +10,9 @@ import pytest
 
 import synth
 from oracle import fdtd as ofdtd
+from oracle import partial_waves as pw
+from oracle import pstd as opstd
+from oracle import sphere as osph
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -92,3 +96,120 @@ def test_fdtd_walls_hold_the_incident_wave(P):
     print("  box |psi - psi_inc| max", err_box, " scattered region max", err_sf, flush=True)
     assert err_box < 1e-4 and err_sf < 1e-4
     s.close()
+
+
+@pytest.mark.parametrize("n", [160, 288])
+def test_fdtd_full_size_single_step(P, n):
+    """One step of the benchmark's grid (160^3 and 288^3 square barrier) from
+    seeded random states, every cell against the oracle."""
+    prob, V = synth.square_barrier_160(n_fft=n)
+    prob = prob.replace(scheme=1, dft_begin=0, dft_end=0)
+    V = V.astype(np.float32).astype(np.float64)
+    print(f"FDTD full-size single step: grid {prob.n}", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.autotune(reps=3)
+    prev = synth.random_state(prob.n, 21).astype(np.complex64)
+    cur = synth.random_state(prob.n, 22).astype(np.complex64)
+    step = 300  # inside the ramp: the wall terms carry a fraction of the wave
+    s.set_state(prev, cur, step)
+    s.run(1)
+    got = s.psi(0).cpu().numpy()
+    s.close()
+    ref = ofdtd.step(ofdtd.build(prob, V), prev.astype(np.complex128), cur.astype(np.complex128), step)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("  max err / max|psi|", err, flush=True)
+    assert err < 1e-5
+
+
+def sphere_problem(v0=1.0, theta=0.5, phi=0.8):
+    """48^3 at 8 points per wavelength, total-field box 19..29, a barrier of
+    radius 3 cells, a sphere of radius 0.95 (9.5 cells) around the box whose
+    shell crosses its walls."""
+    h = 0.1
+    k0 = 2 * math.pi / (8 * h)
+    E0 = k0 * k0 / 2
+    alpha = 1.0
+    prob = synth.Problem(n=(48, 48, 48), h=(h,) * 3, k0=k0, theta=theta, phi=phi, abc_cells=(4,) * 3,
+                         abc_alpha=alpha, abc_U0=synth.paper_u0(alpha, k0 * h, 4), tfsf=((16, 19, 29, 32),) * 3,
+                         v_max=max(abs(v0), 1e-9) * E0, ramp_periods=0.5, n_steps=160, dft_begin=80, dft_end=160,
+                         surf_lo=(14,) * 3, surf_hi=(34,) * 3, surface_kind=1, sphere_radius=0.95,
+                         sphere_nodes=(16, 32), scheme=1)
+    V = np.zeros((48, 48, 48))
+    x = np.arange(48) - 24
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    V[X * X + Y * Y + Z * Z <= 9] = v0 * E0
+    return prob, V.astype(np.float32).astype(np.float64)
+
+
+def test_fdtd_sphere_phasors_match_oracle(P):
+    """The shell DFT at the discrete frequency with the incident part T
+    psi_inc removed, interpolated to the nodes, against the oracle."""
+    prob, V = sphere_problem()
+    print(f"FDTD sphere phasors: grid {prob.n}", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.run(prob.n_steps)
+    v, d = (x.cpu().numpy() for x in s.sphere_phasors())
+    s.close()
+    sph = osph.Sphere(prob, prob.sphere_radius, n_theta=16, n_phi=32)
+    _, _, sd = ofdtd.run_sphere(prob, V, sph)
+    ref_v, ref_d = sph.node_values(sd.normalized())
+    ev = np.linalg.norm(v - ref_v) / np.linalg.norm(ref_v)
+    ed = np.linalg.norm(d - ref_d) / np.linalg.norm(ref_d)
+    print(f"  rel-L2: psi {ev:.2e}, d psi/dn {ed:.2e}", flush=True)
+    assert ev < 1e-4 and ed < 1e-4
+
+
+def test_fdtd_validation(P):
+    prob, _ = sphere_problem()
+    for bad in (dict(surface_kind=0), dict(sub_core=(16, 0, 0), sub_halo=8, sub_taper=3)):
+        with pytest.raises(P.PstdError) as e:
+            P.Solver(prob.replace(**bad))
+        assert e.value.name == "PSTD_EUNSUPPORTED"
+    s = P.Solver(prob)
+    with pytest.raises(P.PstdError) as e:
+        s.misfit(prob.n_steps, np.array([[0.0, 0.0, 3.0]]), np.ones(1))
+    assert e.value.name == "PSTD_EUNSUPPORTED"
+    s.close()
+
+
+def test_fdtd_square_barrier_far_field(P):
+    """The 160^3 square-barrier workload advanced by the FDTD step over the
+    same physical time as the spectral run (the DFT window the last 4
+    periods at W), far field from the sphere of radius 5 against the
+    partial-wave series and against the spectral solve."""
+    base, V = synth.square_barrier_160()
+    # the barrier lies inside the total-field box 56..104 of every axis
+    lo, hi = base.tfsf[0][1], base.tfsf[0][2]
+    inside = np.zeros(base.n[0], bool)
+    inside[lo:hi + 1] = True
+    assert np.abs(V[~inside, :, :]).max() == 0 and np.abs(V[:, ~inside, :]).max() == 0
+    assert np.abs(V[:, :, ~inside]).max() == 0
+    sph = dict(surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
+    fd = base.replace(scheme=1, **sph)
+    dt_p, dt_f = opstd.dtau_of(base), ofdtd.dtau_of(fd)
+    W = ofdtd.discrete_frequency(opstd.khat(fd.theta, fd.phi), opstd.dxbar(fd), dt_f)
+    steps = int(round(base.n_steps * dt_p / dt_f))
+    win = int(round(4 * 2 * math.pi / (W * dt_f)))
+    fd = fd.replace(n_steps=steps, dft_begin=steps - win, dft_end=steps)
+    print(f"FDTD square barrier: grid {fd.n}, {steps} steps, window {win}", flush=True)
+    th = np.deg2rad(np.arange(0, 181, 3.0))
+    ph = np.deg2rad(np.arange(0, 360, 30.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3)
+    out = {}
+    for name, prob in (("fdtd", fd), ("pstd", base.replace(**sph))):
+        s = P.Solver(prob)
+        s.set_potential(V)
+        s.run(prob.n_steps)
+        out[name] = s.far_field(d).cpu().numpy().reshape(T.shape)
+        s.close()
+    ref = pw.amplitude(base.k0, 2.4, 0.5 * base.k0 ** 2 / 2, th)[:, None] * np.ones_like(F)
+    w = np.sin(T) + 1e-3
+
+    def rel(a, b):
+        return math.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2))
+    r_fp, r_sp, r_fs = rel(out["fdtd"], ref), rel(out["pstd"], ref), rel(out["fdtd"], out["pstd"])
+    print(f"  vs partial waves: FDTD {r_fp:.4f}, PSTD {r_sp:.4f}; FDTD vs PSTD {r_fs:.4f}", flush=True)
+    assert r_fp < 0.05

@@ -57,14 +57,16 @@ def test_defaults_are_valid_plain_method_geometry():
 
 def test_fdtd_scheme_step_bound_and_limits():
     """The FDTD variant's step (0.9 of its bound, no eta) matches the oracle;
-    what it does not run is refused before any device work."""
+    what it does not run (a DFT window on the box surface, subdomains) is
+    refused before any device work; the spherical surface is accepted."""
     from oracle import fdtd as ofdtd
     prob, _ = synth.tiny(n=(24, 24, 32), P=4, transition=2, dft=(0, 0))
     prob = prob.replace(scheme=1)
     dtau, eta = lib_mod.pstd_reduced_step(lib_mod.problem_from(prob))
     assert dtau == pytest.approx(ofdtd.dtau_of(prob), rel=1e-14)
-    for bad in (dict(dft_begin=0, dft_end=10), dict(surface_kind=1, sphere_radius=0.5),
-                dict(sub_core=(12, 0, 0), sub_halo=8, sub_taper=3)):
+    lib_mod.pstd_reduced_step(lib_mod.problem_from(prob.replace(surface_kind=1, sphere_radius=0.5,
+                                                                dft_begin=0, dft_end=10)))
+    for bad in (dict(dft_begin=0, dft_end=10), dict(sub_core=(12, 0, 0), sub_halo=8, sub_taper=3)):
         with pytest.raises(lib_mod.PstdError) as e:
             lib_mod.pstd_reduced_step(lib_mod.problem_from(prob.replace(**bad)))
         assert e.value.name == "PSTD_EUNSUPPORTED"
