@@ -16,12 +16,14 @@ Definition (reduced units, k = 1, x_bar = k0 x):
     Lagrange interpolation of `order` points per axis around each node
     (index space, derivative of the interpolant), normalised by the incident
     phasor at the origin like the box phasors (Eq. scaledphsiphasor);
-  * Kirchhoff surface integral with G = exp(iR)/(4 pi R), outward normal:
-      Psi(r) = -(1/4pi) sum_q w_q exp(iR_q)/R_q
-               [d_n psi_q + (-i + 1/R_q) (n_q . (s_q - r) / R_q) psi_q],
+  * Kirchhoff surface integral with G = exp(ikR)/(4 pi R), outward normal
+    (k = 1 for the central wave, another reduced wavenumber for a phasor of
+    a pulsed run):
+      Psi(r) = -(1/4pi) sum_q w_q exp(ikR_q)/R_q
+               [d_n psi_q + (-ik + 1/R_q) (n_q . (s_q - r) / R_q) psi_q],
       R_q = |r - s_q|;
-    far field f(r_hat) = lim r e^{-ir} Psi:
-      f = -(1/4pi) sum_q w_q [d_n psi_q + i (n_q . r_hat) psi_q] exp(-i r_hat . s_q),
+    far field f(r_hat) = lim r e^{-ikr} Psi:
+      f = -(1/4pi) sum_q w_q [d_n psi_q + ik (n_q . r_hat) psi_q] exp(-ik r_hat . s_q),
     in physical length units f / k0.
 """
 from __future__ import annotations
@@ -135,25 +137,26 @@ class Sphere:
             dn[q] = nq[0] * gx + nq[1] * gy + nq[2] * gz
         return val, dn
 
-    def project(self, psi_q, dpsi_q, points_reduced):
-        """Psi at reduced points outside the sphere (Kirchhoff integral)."""
+    def project(self, psi_q, dpsi_q, points_reduced, k=1.0):
+        """Psi at reduced points outside the sphere (Kirchhoff integral with
+        G = exp(ikR)/(4 pi R); k = 1 is the central wave)."""
         out = np.zeros(len(points_reduced), np.complex128)
         for o, r in enumerate(np.atleast_2d(points_reduced)):
             d = self.nodes - r[None, :]                  # s - r
             Rq = np.sqrt(np.sum(d * d, axis=1))
             ndr = np.sum(self.normal * d, axis=1) / Rq
-            term = dpsi_q + (-1j + 1.0 / Rq) * ndr * psi_q
-            out[o] = -np.sum(self.weights * np.exp(1j * Rq) / Rq * term) / (4 * math.pi)
+            term = dpsi_q + (-1j * k + 1.0 / Rq) * ndr * psi_q
+            out[o] = -np.sum(self.weights * np.exp(1j * k * Rq) / Rq * term) / (4 * math.pi)
         return out
 
-    def far_field(self, psi_q, dpsi_q, dirs):
-        """f(r_hat) in physical length units."""
+    def far_field(self, psi_q, dpsi_q, dirs, k=1.0):
+        """f(r_hat) in physical length units, for the wavenumber k (reduced)."""
         dirs = np.atleast_2d(dirs)
         out = np.zeros(len(dirs), np.complex128)
         for o, rh in enumerate(dirs):
             nr = self.normal @ rh
-            ph = np.exp(-1j * (self.nodes @ rh))
-            out[o] = -np.sum(self.weights * (dpsi_q + 1j * nr * psi_q) * ph) / (4 * math.pi)
+            ph = np.exp(-1j * k * (self.nodes @ rh))
+            out[o] = -np.sum(self.weights * (dpsi_q + 1j * k * nr * psi_q) * ph) / (4 * math.pi)
         return out / self.k0
 
 

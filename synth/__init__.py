@@ -437,3 +437,13 @@ def random_state(n, seed, scale=1.0):
     nx, ny, nz = n
     a = rng.normal(size=(nz, ny, nx)) + 1j * rng.normal(size=(nz, ny, nx))
     return scale * a
+
+
+def gaussian_pulse_1d(n1d, delta, k_c, sigma, d0):
+    """A Gaussian packet on the periodic 1D grid d_j = j delta (reduced
+    units): exp(-(d - d0)^2 / (2 sigma^2)) exp(i k_c (d - d0)), with d - d0
+    taken at the nearest periodic image."""
+    L = n1d * delta
+    x = np.arange(n1d) * delta - d0
+    x = (x + L / 2) % L - L / 2
+    return np.exp(-x * x / (2 * sigma * sigma)) * np.exp(1j * k_c * x)

@@ -37,11 +37,11 @@ def sph():
     return prob, osph.Sphere(prob, 5.0, n_theta=64, n_phi=128)
 
 
-def point_source(x, x0):
+def point_source(x, x0, k=1.0):
     d = x - x0
     rho = np.sqrt(np.sum(d * d, axis=-1))
-    f = np.exp(1j * rho) / rho
-    grad = (f * (1j - 1 / rho))[..., None] * d / rho[..., None]
+    f = np.exp(1j * k * rho) / rho
+    grad = (f * (1j * k - 1 / rho))[..., None] * d / rho[..., None]
     return f, grad
 
 
@@ -51,21 +51,25 @@ def test_quadrature_area(sph):
     assert np.allclose(np.linalg.norm(s.nodes, axis=1), s.R)
 
 
-def test_kirchhoff_reproduces_outgoing_field(sph):
+@pytest.mark.parametrize("k", [1.0, 1.3, 0.7])
+def test_kirchhoff_reproduces_outgoing_field(sph, k):
+    """An outgoing point-source wave of wavenumber k (the central wave, or a
+    phasor of a pulsed run) from inside: the integral with G = exp(ikR)/(4
+    pi R) gives it back outside, and its far field exp(-ik r_hat . x0)."""
     prob, s = sph
     x0 = np.array([2.0, -1.5, 3.0])                     # reduced, inside (R = 39.3)
-    f, g = point_source(s.nodes, x0)
+    f, g = point_source(s.nodes, x0, k)
     dn = np.sum(s.normal * g, axis=1)
     rng = np.random.default_rng(1)
     pts = rng.normal(size=(12, 3))
     pts = pts / np.linalg.norm(pts, axis=1, keepdims=True) * rng.uniform(45, 120, size=(12, 1))
-    got = s.project(f, dn, pts)
-    ref, _ = point_source(pts, x0)
+    got = s.project(f, dn, pts, k=k)
+    ref, _ = point_source(pts, x0, k)
     assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
     dirs = rng.normal(size=(12, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    ff = s.far_field(f, dn, dirs)
-    assert np.abs(ff - np.exp(-1j * dirs @ x0) / prob.k0).max() < 1e-9 / prob.k0
+    ff = s.far_field(f, dn, dirs, k=k)
+    assert np.abs(ff - np.exp(-1j * k * (dirs @ x0)) / prob.k0).max() < 1e-9 / prob.k0
 
 
 def test_kirchhoff_of_regular_field_vanishes_outside(sph):
