@@ -263,6 +263,54 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_ob
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
 
 /*
+ * Pulsed (broadband) incidence: Section 2.4, calculation of the incident
+ * wave (Eqs. Oinc, inc_d, pstd_psiinc, pstd_dpsiinc), and Section 3.3 with
+ * several frequencies (Eqs. psiphasor-scaleddpsiphasor repeated per
+ * frequency).
+ *
+ * Replaces the monochromatic plane wave of the solve by a packet of any
+ * shape travelling along k_hat.  psi0_host: the packet at step 0 on the
+ * periodic 1D grid d_j = j delta (reduced length, d = 0 at the corner of
+ * the taper box that the front reaches first, Eq. Oinc; a cell sits at d =
+ * k_hat . (x - x_O), Eq. inc_d), n1d complex values as interleaved FP64
+ * (re, im) in host memory, copied.  The packet advances by the leapfrog of
+ * Eq. PSTDupdating in 1D (free space, eta on the kinetic term), started on
+ * each mode's physical root so that it travels one way; each step its value
+ * and gradient at the transition-layer cells come from Eqs. pstd_psiinc and
+ * pstd_dpsiinc (the spectral sum evaluated on a table four times finer than
+ * the grids and interpolated from it with 8-point Lagrange weights: within
+ * 1e-8 of the packet), and the layer source of Eq. dimlesstildeSchrodinger
+ * is added to the step; the monochromatic source is off.  The 1D grid must
+ * be long enough that the packet does not come round again during the run.
+ *
+ * kbar_host: n_k reduced wavenumbers k/k0 (host, copied).  The spherical
+ * surface accumulates one phasor per wavenumber over the DFT window, step n
+ * weighted by exp(i W tau_n) with sin(W dtau) = dtau eta kbar^2 (the
+ * scheme's frequency of that wavenumber), each normalised by the incident
+ * phasor at the grid origin (the DFT of the packet there over the same
+ * steps); the _k outputs below project it with G = exp(i kbar R)/(4 pi R).
+ *
+ * Requires the spectral scheme, the spherical surface (surface_kind 1) with
+ * its interpolation shell where the taper is zero, no subdomains and no
+ * batch (EUNSUPPORTED otherwise); call before the first step (ESTATE).
+ * EINVAL: n1d not a power of two in [8, 2^20], delta <= 0, n_k outside
+ * [1, 64], a wavenumber <= 0 or beyond the step bound, the 1D grid's
+ * Nyquist mode beyond the step bound, a non-finite or zero packet.  A
+ * pulsed run has no checkpoint (pstd_save_state / pstd_load_state return
+ * EUNSUPPORTED).  Synchronises. */
+pstd_status pstd_set_pulse(pstd_solver* s, const double* psi0_host, int32_t n1d, double delta,
+                           const double* kbar_host, int32_t n_k);
+
+/* pstd_get_sphere_phasors, pstd_project and pstd_far_field for the phasors
+ * of wavenumber index ik of a pulsed run (the plain calls read index 0;
+ * without a pulse ik must be 0).  EINVAL for an index out of range. */
+pstd_status pstd_get_sphere_phasors_k(pstd_solver* s, int32_t ik, double* out_dev, int64_t n);
+pstd_status pstd_project_k(pstd_solver* s, int32_t ik, const double* obs_xyz_dev, int64_t n_obs,
+                           double* psi_out_dev);
+pstd_status pstd_far_field_k(pstd_solver* s, int32_t ik, const double* dir_dev, int64_t n_dir,
+                             double* f_out_dev);
+
+/*
  * Differentiation with respect to the voxel potential (not in the paper; the
  * discrete adjoint of Eq. PSTDupdating, of the surface DFT of Eqs. psiphasor /
  * dpsiphasor / scaledphsiphasor and of the box projection of Section 3.2).

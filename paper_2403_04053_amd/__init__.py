@@ -15,7 +15,8 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_pass_time", "pstd_check_state", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_far_field", "pstd_set_pulse", "pstd_get_sphere_phasors_k", "pstd_project_k", "pstd_far_field_k",
+    "pstd_pass_time", "pstd_check_state", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -134,6 +135,10 @@ _SIGS = {
     "pstd_get_surface_phasors": [_vp, _vp, _i64],
     "pstd_project": [_vp, _vp, _i64, _vp],
     "pstd_far_field": [_vp, _vp, _i64, _vp],
+    "pstd_set_pulse": [_vp, _vp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_int32],
+    "pstd_get_sphere_phasors_k": [_vp, ctypes.c_int32, _vp, _i64],
+    "pstd_project_k": [_vp, ctypes.c_int32, _vp, _i64, _vp],
+    "pstd_far_field_k": [_vp, ctypes.c_int32, _vp, _i64, _vp],
     "pstd_misfit_forward": [_vp, _i64, _vp, _i64, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pstd_misfit_backward": [_vp, _vp, _i64],
     "pstd_state_size": [_vp, ctypes.POINTER(_i64)],
@@ -270,6 +275,27 @@ def pstd_project(solver, obs_dev, n_obs, out_dev):
 
 def pstd_far_field(solver, dir_dev, n_dir, out_dev):
     _check(lib.pstd_far_field(solver, _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
+
+
+def pstd_set_pulse(solver, psi0, delta, kbars):
+    """psi0: complex packet on the 1D grid (host); kbars: reduced wavenumbers (host)."""
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    k = np.ascontiguousarray(np.asarray(kbars, dtype=np.float64))
+    _check(lib.pstd_set_pulse(solver, p.ctypes.data_as(_vp), int(p.size), float(delta),
+                              k.ctypes.data_as(_vp), int(k.size)), solver)
+
+
+def pstd_get_sphere_phasors_k(solver, ik, out_dev, n):
+    _check(lib.pstd_get_sphere_phasors_k(solver, int(ik), _ptr(out_dev), int(n)), solver)
+
+
+def pstd_project_k(solver, ik, obs_dev, n_obs, out_dev):
+    _check(lib.pstd_project_k(solver, int(ik), _ptr(obs_dev), int(n_obs), _ptr(out_dev)), solver)
+
+
+def pstd_far_field_k(solver, ik, dir_dev, n_dir, out_dev):
+    _check(lib.pstd_far_field_k(solver, int(ik), _ptr(dir_dev), int(n_dir), _ptr(out_dev)), solver)
 
 
 def pstd_sphere_size(solver):
@@ -481,24 +507,30 @@ class Solver:
             off += 2 * m
         return phi, dphi
 
-    def project(self, points):
+    def project(self, points, ik=0):
+        """Psi at physical points; ik selects a pulsed run's wavenumber."""
         pts = self.torch.as_tensor(points, dtype=self.torch.float64, device=self.device).contiguous()
         out = self.torch.empty(pts.shape[0], dtype=self.torch.complex128, device=self.device)
-        pstd_project(self.handle, pts, pts.shape[0], out)
+        pstd_project_k(self.handle, ik, pts, pts.shape[0], out)
         return out
 
-    def far_field(self, dirs):
+    def far_field(self, dirs, ik=0):
+        """f(r_hat); ik selects a pulsed run's wavenumber."""
         d = self.torch.as_tensor(dirs, dtype=self.torch.float64, device=self.device).contiguous()
         out = self.torch.empty(d.shape[0], dtype=self.torch.complex128, device=self.device)
-        pstd_far_field(self.handle, d, d.shape[0], out)
+        pstd_far_field_k(self.handle, ik, d, d.shape[0], out)
         return out
 
+    def set_pulse(self, psi0, delta, kbars):
+        """Pulsed incidence (pstd_set_pulse): the packet psi0 on the 1D grid of
+        spacing delta (reduced) and the wavenumbers of the phasors."""
+        pstd_set_pulse(self.handle, psi0, delta, kbars)
 
-    def sphere_phasors(self):
+    def sphere_phasors(self, ik=0):
         """(psi, d psi/d n) at the sphere's nodes (complex128 CUDA tensors)."""
         n = pstd_sphere_size(self.handle)
         out = self.torch.empty(2 * n, dtype=self.torch.complex128, device=self.device)
-        pstd_get_sphere_phasors(self.handle, out, 2 * n)
+        pstd_get_sphere_phasors_k(self.handle, ik, out, 2 * n)
         return out[:n], out[n:]
 
     def save_state(self):

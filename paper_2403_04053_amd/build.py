@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpstd.so")
-SOURCES = ["pass.hip", "project.hip", "api.hip", "batch.hip", "adjoint.hip", "sphere.hip", "fdtd.hip"]
+SOURCES = ["pass.hip", "project.hip", "api.hip", "batch.hip", "adjoint.hip", "sphere.hip", "fdtd.hip", "pulse.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -364,6 +364,11 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
             for (int i = 1; i < 6; ++i) HIP_TRY(s, hipEventRecord(ev[i], stream));
         return PSTD_OK;
     }
+    if (s->pulse) {
+        // the packet's values on the layer's table for this step
+        hipError_t e = pstd::pulse_launch_table(s, koff, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "pulse table launch");
+    }
     for (int axis = 0; axis < 3; ++axis) {
         pstd::PassArgs a;
         pstd::solver_args(s, axis, a);
@@ -372,6 +377,11 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
         hipError_t e = pstd::launch_variant_single(s->variant[axis], seg, axis, a, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
+    }
+    if (s->pulse) {
+        // the layer source of the packet, added to psi^{n+1}
+        hipError_t e = pstd::pulse_launch_source(s, koff, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "pulse source launch");
     }
     return PSTD_OK;
 }
@@ -413,6 +423,10 @@ pstd_status build_graph(pstd_solver* s) {
 namespace pstd {
 
 pstd_status solver_fail(pstd_solver* s, pstd_status st, const std::string& msg) { return fail(s, st, msg); }
+
+void solver_taper(const pstd_problem& p, int a, double dxb, int i, double* z, double* z1, double* z2) {
+    taper(p, a, dxb, i, z, z1, z2);
+}
 
 void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out) {
     const int N = s->prob.n[a];
@@ -460,17 +474,24 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     if (n_end <= s->tab_cap) return PSTD_OK;
     int64_t cap = std::max<int64_t>(n_end, 2 * s->tab_cap);
     cap = std::max<int64_t>(cap, 1024);
+    // one row of DFT weights per wavenumber (several with a pulse, whose
+    // source comes from its own kernels: sigma = 0)
+    const int nk = pulse_wavenumbers(s);
     std::vector<float2> sig(cap);
-    std::vector<double2> w(cap);
+    std::vector<double2> w(nk * cap);
     std::vector<int> on(cap);
     const double fac = 2.0 * s->dtau * (s->prob.eta_on_source && s->prob.scheme == 0 ? s->eta : 1.0);
     for (int64_t n = 0; n < cap; ++n) {
         const double tau = n * s->dtau;
         const double f = fac * ramp_of(tau, s->tau_r);
         const double ph = s->omega * tau;
-        sig[n] = make_float2((float)(f * std::cos(ph)), (float)(-f * std::sin(ph)));
-        // the DFT at the incident wave's frequency (1, or the FDTD scheme's W)
-        w[n] = make_double2(std::cos(s->omega * tau), std::sin(s->omega * tau));
+        sig[n] = s->pulse ? make_float2(0.f, 0.f) : make_float2((float)(f * std::cos(ph)), (float)(-f * std::sin(ph)));
+        // the DFT at the incident wave's frequency (1, the FDTD scheme's W,
+        // or each wavenumber's frequency of a pulse)
+        for (int k = 0; k < nk; ++k) {
+            const double om = pulse_frequency(s, k) * tau;
+            w[k * cap + n] = make_double2(std::cos(om), std::sin(om));
+        }
         on[n] = (n >= s->prob.dft_begin && n < s->prob.dft_end) ? 1 : 0;
     }
     // queued steps may still read the old tables
@@ -485,10 +506,10 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
     s->dft_zero = nullptr;
     s->tab_cap = 0;
     HIP_TRY(s, hipMalloc(&s->sigma_tab, cap * sizeof(float2)));
-    HIP_TRY(s, hipMalloc(&s->w_tab, cap * sizeof(double2)));
+    HIP_TRY(s, hipMalloc(&s->w_tab, nk * cap * sizeof(double2)));
     HIP_TRY(s, hipMalloc(&s->dft_tab, cap * sizeof(int)));
     HIP_TRY(s, hipMemcpy(s->sigma_tab, sig.data(), cap * sizeof(float2), hipMemcpyHostToDevice));
-    HIP_TRY(s, hipMemcpy(s->w_tab, w.data(), cap * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(s->w_tab, w.data(), nk * cap * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemcpy(s->dft_tab, on.data(), cap * sizeof(int), hipMemcpyHostToDevice));
     if (s->prob.surface_kind == 1) {
         HIP_TRY(s, hipMalloc(&s->dft_zero, cap * sizeof(int)));
@@ -501,8 +522,10 @@ pstd_status solver_ensure_tables(pstd_solver* s, int64_t n_end) {
 }
 
 void solver_account_steps(pstd_solver* s, int64_t from, int64_t to) {
-    for (int64_t n = std::max(from, s->prob.dft_begin); n < std::min(to, s->prob.dft_end); ++n)
+    for (int64_t n = std::max(from, s->prob.dft_begin); n < std::min(to, s->prob.dft_end); ++n) {
         s->inc_sum += ramp_of(n * s->dtau, s->tau_r);
+        s->win_steps += 1;
+    }
 }
 
 void solver_drop_graph(pstd_solver* s) {
@@ -797,6 +820,8 @@ pstd_status pstd_set_state(pstd_solver* s, const void* prev, const void* cur, in
     HIP_TRY(s, hipDeviceSynchronize());
     s->step = step;
     s->inc_sum = 0;
+    s->win_steps = 0;
+    pulse_reset(s);
     return PSTD_OK;
 }
 
@@ -975,6 +1000,7 @@ pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out) {
 
 pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
     if (!s || !dev_buf) return PSTD_EINVAL;
+    if (s->pulse) return fail(s, PSTD_EUNSUPPORTED, "no checkpoint of a pulsed run");
     const int64_t need = state_bytes(s);
     if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
     StateHeader h{kStateMagic, {s->prob.n[0], s->prob.n[1], s->prob.n[2]}, s->step, s->inc_sum, need, 0};
@@ -998,6 +1024,7 @@ pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
 
 pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) {
     if (!s || !dev_buf) return PSTD_EINVAL;
+    if (s->pulse) return fail(s, PSTD_EUNSUPPORTED, "no checkpoint of a pulsed run");
     if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
     const int64_t need = state_bytes(s);
     if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
@@ -1026,6 +1053,7 @@ pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) 
     HIP_TRY(s, hipMemcpy(s->ctr, c, sizeof(c), hipMemcpyHostToDevice));
     s->step = h.step;
     s->inc_sum = h.inc_sum;
+    s->win_steps = h.inc_sum > 0 ? 1 : 0;
     return PSTD_OK;
 }
 
@@ -1053,21 +1081,36 @@ pstd_status pstd_sphere_size(const pstd_solver* s, int64_t* n_nodes_out) {
     return PSTD_OK;
 }
 
-pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+namespace {
+
+// a window step has run (with a pulse the ramp plays no part)
+bool window_ran(const pstd_solver* s) { return s->pulse ? s->win_steps > 0 : s->inc_sum > 0; }
+
+}  // namespace
+
+pstd_status pstd_get_sphere_phasors_k(pstd_solver* s, int32_t ik, double* out_dev, int64_t n) {
     if (!s || !out_dev) return PSTD_EINVAL;
     if (!s->sphere) return fail(s, PSTD_ESTATE, "the problem has no spherical surface");
     if (n != 2 * sphere_nodes(s)) return fail(s, PSTD_EINVAL, "output size must be twice pstd_sphere_size");
-    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
-    hipError_t e = sphere_phasors(s, (double2*)out_dev, s->stream);
+    if (!window_ran(s)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    SphereOut o;
+    if (pstd_status st = pulse_output(s, ik, &o)) return st;
+    hipError_t e = sphere_phasors(s, o, (double2*)out_dev, s->stream);
     if (e) return hip_fail(s, e, "sphere phasors");
     return PSTD_OK;
 }
 
-pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
+pstd_status pstd_get_sphere_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+    return pstd_get_sphere_phasors_k(s, 0, out_dev, n);
+}
+
+pstd_status pstd_project_k(pstd_solver* s, int32_t ik, const double* obs_dev, int64_t n_obs, double* out_dev) {
     if (!s || n_obs < 0 || (n_obs > 0 && (!obs_dev || !out_dev))) return PSTD_EINVAL;
     if (n_obs == 0) return PSTD_OK;  // nothing to evaluate
-    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (!window_ran(s)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     if (s->sphere) {
+        SphereOut o;
+        if (pstd_status st = pulse_output(s, ik, &o)) return st;
         // the Kirchhoff integral holds outside the sphere only
         std::vector<double> h(3 * n_obs);
         HIP_TRY(s, hipMemcpyAsync(h.data(), obs_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -1076,10 +1119,11 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, d
             const double r = std::sqrt(h[3 * o] * h[3 * o] + h[3 * o + 1] * h[3 * o + 1] + h[3 * o + 2] * h[3 * o + 2]);
             if (!(r > s->prob.sphere_radius)) return fail(s, PSTD_EINVAL, "observation point inside the sphere or not finite");
         }
-        hipError_t e = sphere_project(s, (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream);
+        hipError_t e = sphere_project(s, o, (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream);
         if (e) return hip_fail(s, e, "sphere projection");
         return PSTD_OK;
     }
+    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
     std::string msg;
     hipError_t e = project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
                                   (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
@@ -1087,20 +1131,39 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, d
     return PSTD_OK;
 }
 
-pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
+pstd_status pstd_project(pstd_solver* s, const double* obs_dev, int64_t n_obs, double* out_dev) {
+    return pstd_project_k(s, 0, obs_dev, n_obs, out_dev);
+}
+
+pstd_status pstd_far_field_k(pstd_solver* s, int32_t ik, const double* dir_dev, int64_t n_dir, double* out_dev) {
     if (!s || n_dir < 0 || (n_dir > 0 && (!dir_dev || !out_dev))) return PSTD_EINVAL;
     if (n_dir == 0) return PSTD_OK;  // nothing to evaluate
-    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    if (!window_ran(s)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
     if (s->sphere) {
-        hipError_t e = sphere_far_field(s, (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream);
+        SphereOut o;
+        if (pstd_status st = pulse_output(s, ik, &o)) return st;
+        hipError_t e = sphere_far_field(s, o, (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream);
         if (e) return hip_fail(s, e, "sphere far field");
         return PSTD_OK;
     }
+    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
     std::string msg;
     hipError_t e = far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
                              (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
     if (e) return msg.empty() ? hip_fail(s, e, "far_field") : fail(s, PSTD_EINVAL, msg);
     return PSTD_OK;
+}
+
+pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* out_dev) {
+    return pstd_far_field_k(s, 0, dir_dev, n_dir, out_dev);
+}
+
+pstd_status pstd_set_pulse(pstd_solver* s, const double* psi0_host, int32_t n1d, double delta, const double* kbar_host,
+                           int32_t n_k) {
+    if (!s) return PSTD_EINVAL;
+    adjoint_invalidate(s);
+    solver_drop_graph(s);
+    return pulse_set(s, psi0_host, n1d, delta, kbar_host, n_k);
 }
 
 pstd_status pstd_destroy(pstd_solver* s) {
@@ -1123,6 +1186,7 @@ pstd_status pstd_destroy(pstd_solver* s) {
     project_free(s->proj);
     adjoint_free(s);
     sphere_free(s->sphere);
+    pulse_free(s->pulse);
     delete s;
     return PSTD_OK;
 }

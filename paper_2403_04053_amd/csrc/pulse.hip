@@ -1,0 +1,393 @@
+// Pulsed incidence (Section 2.4, calculation of the incident wave; Section
+// 3.3 at several frequencies).  A plane-wave packet of any shape travels
+// along k_hat; cells on one wavefront share its value, so the packet is a 1D
+// problem on the axis that starts at the corner of the taper box the front
+// meets first (Eq. Oinc), a cell sitting at d = k_hat . (x - x_O) on it (Eq.
+// inc_d).  The packet is stepped in free space by the 3D model's leapfrog in
+// 1D; in the spectral basis every mode is independent, so step n of the
+// leapfrog started on each mode's physical root is exactly
+//   a_l(n) = c_l exp(-i theta_l n),  sin(theta_l) = dtau eta k_l^2,
+// c_l = F[psi^0]_l / N, and nothing has to be stored per step.
+//
+// Each step, pulse_table_kernel evaluates the spectral interpolation of
+// Eqs. pstd_psiinc / pstd_dpsiinc on a table four times finer than the
+// grids, over the d-range of the transition layer only (a few hundred
+// points); pulse_source_kernel, after the z pass, interpolates the table at
+// every layer cell with 8-point Lagrange weights (error ~ (k h)^8 / 8!, below
+// 1e-8 of the packet) and adds the layer source of Eq.
+// dimlesstildeSchrodinger, lap(zeta) psi_inc + 2 grad(zeta) . k_hat
+// dpsi_inc/dd, times -i Gamma 2 dtau (eta): linear in the update, so adding
+// it after the pass equals adding it inside.  The passes are unchanged; the
+// monochromatic source is off (sigma = 0).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "solver.hpp"
+
+namespace pstd {
+
+struct PulseState {
+    int K = 0;                 // modes l_lo .. l_lo + K - 1
+    double k_lo = 0, dk = 0;   // k_l = k_lo + (l - l_lo) dk
+    double2* coef = nullptr;   // c_l
+    double* theta = nullptr;   // phase per step of each mode
+    int J = 0;                 // table points d_lo + j h
+    double d_lo = 0, h = 0;
+    double2* tab = nullptr;    // [2][J]: sum a_l e^{i k_l d}, sum a_l k_l e^{i k_l d}
+    int64_t n_cells = 0;       // transition-layer cells
+    int* cell = nullptr;
+    int* j0 = nullptr;         // first table point of each cell's stencil
+    double* w = nullptr;       // [cell][8] Lagrange weights
+    double2* ab = nullptr;     // per cell: Gamma fac lap(zeta), Gamma fac 2 grad(zeta) . k_hat
+    // host
+    std::vector<double> kbar, W;        // wavenumbers of the phasors and their frequencies
+    std::vector<double2> g;             // c_l exp(i k_l d_origin)
+    std::vector<double> theta_h;
+    int64_t from = 0;                   // first step since creation or pstd_set_state
+};
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kModeChunk = 512;
+constexpr int kLag = 8;
+
+// in-place radix-2 DFT, forward (e^{-i 2 pi l j / N}), N a power of two
+void fft_pow2(std::vector<std::complex<double>>& a) {
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const double ang = -2 * kPi * (double)k / (double)len;
+                const std::complex<double> w(std::cos(ang), std::sin(ang));
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+    }
+}
+
+// T0(d_j) = sum_l a_l(n) e^{i k_l d_j}, T1(d_j) = sum_l a_l(n) k_l e^{i k_l d_j}
+// for the table points of step n = ctr[0] + koff
+__global__ __launch_bounds__(256) void pulse_table_kernel(const int64_t* __restrict__ ctr, int koff, int K,
+                                                          const double2* __restrict__ coef,
+                                                          const double* __restrict__ theta, double k_lo, double dk,
+                                                          int J, double d_lo, double h, double2* __restrict__ tab) {
+    const int64_t n = ctr[0] + koff;
+    if (n >= ctr[1]) return;  // whole grid, before any barrier
+    __shared__ double2 a[kModeChunk];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const double d = d_lo + j * h;
+    double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+    for (int m0 = 0; m0 < K; m0 += kModeChunk) {
+        const int nm = min(kModeChunk, K - m0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nm; e += blockDim.x) {
+            double sn, cs;
+            sincos(theta[m0 + e] * (double)n, &sn, &cs);
+            const double2 c = coef[m0 + e];
+            a[e] = make_double2(c.x * cs + c.y * sn, c.y * cs - c.x * sn);  // c e^{-i theta n}
+        }
+        __syncthreads();
+        if (j >= J) continue;
+        double er, ei, rr, ri;
+        sincos((k_lo + m0 * dk) * d, &ei, &er);
+        sincos(dk * d, &ri, &rr);
+        for (int e = 0; e < nm; ++e) {
+            const double2 ae = a[e];
+            const double kl = k_lo + (m0 + e) * dk;
+            const double tr = ae.x * er - ae.y * ei, ti = ae.x * ei + ae.y * er;
+            s0r += tr;
+            s0i += ti;
+            s1r += kl * tr;
+            s1i += kl * ti;
+            const double nr = er * rr - ei * ri;
+            ei = er * ri + ei * rr;
+            er = nr;
+        }
+    }
+    if (j < J) {
+        tab[j] = make_double2(s0r, s0i);
+        tab[J + j] = make_double2(s1r, s1i);
+    }
+}
+
+// psi^{n+1} -= i (A psi_inc + B dpsi_inc/dd) at the layer cells, psi_inc =
+// T0 and dpsi_inc/dd = i T1 interpolated from the table
+__global__ __launch_bounds__(256) void pulse_source_kernel(const int64_t* __restrict__ ctr, int koff, int64_t nc,
+                                                           const int* __restrict__ cell, const int* __restrict__ j0,
+                                                           const double* __restrict__ w, const double2* __restrict__ ab,
+                                                           const double2* __restrict__ tab, int J,
+                                                           float2* __restrict__ buf0, float2* __restrict__ buf1) {
+    const int64_t n = ctr[0] + koff;
+    if (n >= ctr[1]) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int j = j0[c];
+    const double* wc = w + kLag * c;
+    double p0r = 0, p0i = 0, p1r = 0, p1i = 0;
+    for (int m = 0; m < kLag; ++m) {
+        const double2 t0 = tab[j + m], t1 = tab[J + j + m];
+        p0r += wc[m] * t0.x;
+        p0i += wc[m] * t0.y;
+        p1r += wc[m] * t1.x;
+        p1i += wc[m] * t1.y;
+    }
+    const double2 q = ab[c];
+    // S = A T0 + B i T1
+    const double sr = q.x * p0r - q.y * p1i, si = q.x * p0i + q.y * p1r;
+    float2* out = ((n + 1) & 1) ? buf1 : buf0;
+    float2 v = out[cell[c]];
+    v.x += (float)si;
+    v.y -= (float)sr;
+    out[cell[c]] = v;
+}
+
+}  // namespace
+
+void pulse_free(PulseState* p) {
+    if (!p) return;
+    void* ptrs[] = {p->coef, p->theta, p->tab, p->cell, p->j0, p->w, p->ab};
+    for (void* q : ptrs) (void)hipFree(q);
+    delete p;
+}
+
+int pulse_wavenumbers(const pstd_solver* s) { return s->pulse ? (int)s->pulse->kbar.size() : 1; }
+
+double pulse_frequency(const pstd_solver* s, int ik) { return s->pulse ? s->pulse->W[ik] : s->omega; }
+
+pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double delta, const double* kbar, int32_t nk) {
+    const pstd_problem& p = s->prob;
+    if (s->in_batch) return solver_fail(s, PSTD_EUNSUPPORTED, "batch instances take the monochromatic wave only");
+    if (p.scheme != 0 || p.surface_kind != 1 || p.sub_core[0] || p.sub_core[1] || p.sub_core[2])
+        return solver_fail(s, PSTD_EUNSUPPORTED,
+                           "pulsed incidence needs the spectral scheme, the spherical surface and no subdomains");
+    if (s->step != 0 || s->win_steps != 0) return solver_fail(s, PSTD_ESTATE, "set the pulse before the first step");
+    if (!psi0 || !kbar) return solver_fail(s, PSTD_EINVAL, "null pulse or wavenumber array");
+    if (n1d < 8 || n1d > (1 << 20) || (n1d & (n1d - 1)))
+        return solver_fail(s, PSTD_EINVAL, "n1d must be a power of two in [8, 2^20]");
+    if (!(delta > 0) || !std::isfinite(delta)) return solver_fail(s, PSTD_EINVAL, "delta must be positive");
+    if (nk < 1 || nk > 64) return solver_fail(s, PSTD_EINVAL, "1 to 64 wavenumbers");
+    if (sphere_taper_max(s) != 0)
+        return solver_fail(s, PSTD_EINVAL, "the sphere's shell must lie where the taper is zero");
+    const double q = s->dtau * s->eta;
+    const double knyq = kPi / delta;
+    if (!(q * knyq * knyq < 1)) return solver_fail(s, PSTD_EINVAL, "the 1D grid's Nyquist mode exceeds the step bound");
+    std::vector<double> W(nk);
+    for (int f = 0; f < nk; ++f) {
+        if (!(kbar[f] > 0) || !(q * kbar[f] * kbar[f] < 1))
+            return solver_fail(s, PSTD_EINVAL, "wavenumbers must be positive and below the step bound");
+        W[f] = std::asin(q * kbar[f] * kbar[f]) / s->dtau;
+    }
+    // spectrum of the packet
+    std::vector<std::complex<double>> F(n1d);
+    double amax = 0;
+    for (int j = 0; j < n1d; ++j) {
+        if (!std::isfinite(psi0[2 * j]) || !std::isfinite(psi0[2 * j + 1]))
+            return solver_fail(s, PSTD_EINVAL, "the pulse is not finite");
+        F[j] = {psi0[2 * j], psi0[2 * j + 1]};
+    }
+    fft_pow2(F);
+    for (auto& v : F) {
+        v /= (double)n1d;
+        amax = std::max(amax, std::abs(v));
+    }
+    if (!(amax > 0)) return solver_fail(s, PSTD_EINVAL, "the pulse is zero");
+    // contiguous range of signed mode indices holding every mode above 1e-14 of the largest
+    int lmin = n1d, lmax = -n1d;
+    for (int j = 0; j < n1d; ++j) {
+        const int l = j >= n1d / 2 ? j - n1d : j;
+        if (std::abs(F[j]) > 1e-14 * amax) {
+            lmin = std::min(lmin, l);
+            lmax = std::max(lmax, l);
+        }
+    }
+    const int K = lmax - lmin + 1;
+    const double dk = 2 * kPi / (n1d * delta);
+    PulseState* ps = new PulseState();
+    ps->K = K;
+    ps->dk = dk;
+    ps->k_lo = lmin * dk;
+    ps->kbar.assign(kbar, kbar + nk);
+    ps->W = W;
+    std::vector<double2> coef(K);
+    ps->theta_h.resize(K);
+    for (int m = 0; m < K; ++m) {
+        const int l = lmin + m;
+        const std::complex<double> c = F[(l + n1d) % n1d];
+        coef[m] = make_double2(c.real(), c.imag());
+        const double kl = l * dk;
+        ps->theta_h[m] = std::asin(q * kl * kl);
+    }
+    // origin corner (Eq. Oinc) and the grid origin on the axis
+    int O[3];
+    for (int a = 0; a < 3; ++a) O[a] = s->kh[a] >= 0 ? p.tfsf[a][0] : p.tfsf[a][3];
+    double d_origin = 0;
+    for (int a = 0; a < 3; ++a) d_origin += (p.n[a] / 2 - O[a]) * s->dxb[a] * s->kh[a];
+    ps->g.resize(K);
+    for (int m = 0; m < K; ++m) {
+        const double kl = ps->k_lo + m * dk, ph = kl * d_origin;
+        const double cr = std::cos(ph), ci = std::sin(ph);
+        ps->g[m] = make_double2(coef[m].x * cr - coef[m].y * ci, coef[m].x * ci + coef[m].y * cr);
+    }
+    // transition-layer cells (taper box of every axis), their axis coordinate and coefficients
+    std::vector<double> z[3], z1[3], z2[3], gam[3];
+    for (int a = 0; a < 3; ++a) {
+        const int N = p.n[a];
+        z[a].resize(N);
+        z1[a].resize(N);
+        z2[a].resize(N);
+        gam[a].resize(N);
+        for (int i = 0; i < N; ++i) {
+            solver_taper(p, a, s->dxb[a], i, &z[a][i], &z1[a][i], &z2[a][i]);
+            const int d = std::min(i, N - 1 - i);
+            double gg = 0;
+            if (d < p.abc_cells[a]) {
+                const double c = std::cosh(p.abc_alpha * d);
+                gg = p.abc_U0 / (c * c);
+            }
+            gam[a][i] = std::exp(-gg * s->dtau);
+        }
+    }
+    const double fac = 2.0 * s->dtau * (p.eta_on_source ? s->eta : 1.0);
+    std::vector<int> cell;
+    std::vector<double> dc;
+    std::vector<double2> ab;
+    const int64_t nx = p.n[0], ny = p.n[1];
+    for (int k = p.tfsf[2][0]; k <= p.tfsf[2][3]; ++k)
+        for (int j = p.tfsf[1][0]; j <= p.tfsf[1][3]; ++j)
+            for (int i = p.tfsf[0][0]; i <= p.tfsf[0][3]; ++i) {
+                const int ix[3] = {i, j, k};
+                double lap = 0, grad = 0;
+                for (int a = 0; a < 3; ++a) {
+                    double others = 1;
+                    for (int b = 0; b < 3; ++b)
+                        if (b != a) others *= z[b][ix[b]];
+                    lap += z2[a][ix[a]] * others;
+                    grad += z1[a][ix[a]] * s->kh[a] * others;
+                }
+                if (lap == 0 && grad == 0) continue;
+                const double G = gam[0][i] * gam[1][j] * gam[2][k];
+                cell.push_back((int)(i + nx * (j + ny * (int64_t)k)));
+                double d = 0;
+                for (int a = 0; a < 3; ++a) d += (ix[a] - O[a]) * s->dxb[a] * s->kh[a];
+                dc.push_back(d);
+                ab.push_back(make_double2(G * fac * lap, G * fac * 2.0 * grad));
+            }
+    ps->n_cells = (int64_t)cell.size();
+    // table over the layer's d-range, 4 times finer than the finer of the two grids
+    double dmin = 0, dmax = 0;
+    if (!dc.empty()) {
+        dmin = *std::min_element(dc.begin(), dc.end());
+        dmax = *std::max_element(dc.begin(), dc.end());
+    }
+    ps->h = std::min(delta, std::min(s->dxb[0], std::min(s->dxb[1], s->dxb[2]))) / 4;
+    ps->d_lo = dmin - 4 * ps->h;
+    ps->J = (int)std::ceil((dmax - ps->d_lo) / ps->h) + 5;
+    std::vector<int> j0(cell.size());
+    std::vector<double> w(kLag * cell.size());
+    for (size_t c = 0; c < cell.size(); ++c) {
+        const double u = (dc[c] - ps->d_lo) / ps->h;
+        const int first = (int)std::floor(u) - (kLag / 2 - 1);
+        j0[c] = first;
+        for (int m = 0; m < kLag; ++m) {
+            double l = 1;
+            for (int r = 0; r < kLag; ++r)
+                if (r != m) l *= (u - (first + r)) / (double)(m - r);
+            w[kLag * c + m] = l;
+        }
+    }
+    auto up = [&](auto** dst, const auto& v) {
+        using T = typename std::decay_t<decltype(v)>::value_type;
+        hipError_t r = hipMalloc((void**)dst, std::max<size_t>(v.size(), 1) * sizeof(T));
+        if (r == hipSuccess && !v.empty()) r = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        return r;
+    };
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s->stream)) || (e = up(&ps->coef, coef)) || (e = up(&ps->theta, ps->theta_h)) ||
+        (e = hipMalloc(&ps->tab, 2 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->cell, cell)) ||
+        (e = up(&ps->j0, j0)) || (e = up(&ps->w, w)) || (e = up(&ps->ab, ab))) {
+        pulse_free(ps);
+        return solver_hip_fail(s, e, "pulse tables");
+    }
+    pulse_free(s->pulse);
+    s->pulse = ps;
+    if ((e = sphere_set_wavenumbers(s, nk))) return solver_hip_fail(s, e, "phasor sums");
+    // rebuild the per-step tables: no monochromatic source, one DFT weight row per wavenumber
+    const int64_t cap = std::max<int64_t>(s->tab_cap, 1024);
+    s->tab_cap = 0;
+    return solver_ensure_tables(s, cap);
+}
+
+hipError_t pulse_launch_table(const pstd_solver* s, int koff, hipStream_t stream) {
+    const PulseState* ps = s->pulse;
+    if (!ps || ps->n_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(pulse_table_kernel, dim3((unsigned)((ps->J + 255) / 256)), dim3(256), 0, stream, s->ctr, koff,
+                       ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->d_lo, ps->h, ps->tab);
+    return hipGetLastError();
+}
+
+hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t stream) {
+    const PulseState* ps = s->pulse;
+    if (!ps || ps->n_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(pulse_source_kernel, dim3((unsigned)((ps->n_cells + 255) / 256)), dim3(256), 0, stream, s->ctr,
+                       koff, ps->n_cells, ps->cell, ps->j0, ps->w, ps->ab, ps->tab, ps->J, s->buf[0], s->buf[1]);
+    return hipGetLastError();
+}
+
+namespace {
+
+// the incident phasor at the grid origin (Eq. incpsiphasor) over the window
+// steps run since the last reset, [max(dft_begin, from), min(dft_end,
+// step)): per mode a geometric series in phi = W dtau - theta_l, taken whole
+// so that it does not depend on how the steps were split into runs,
+//   sum_{n=a}^{b-1} e^{i phi n} = e^{i phi (a + (m-1)/2)} sin(m phi / 2) / sin(phi / 2)
+std::complex<double> incident_phasor(const pstd_solver* s, int f) {
+    const PulseState* ps = s->pulse;
+    const int64_t a = std::max(ps->from, s->prob.dft_begin), b = std::min(s->step, s->prob.dft_end);
+    if (b <= a) return 0.0;
+    const double m = (double)(b - a);
+    std::complex<double> acc = 0;
+    for (int l = 0; l < ps->K; ++l) {
+        const double phi = ps->W[f] * s->dtau - ps->theta_h[l];
+        const double sh = std::sin(0.5 * phi);
+        const double ratio = std::fabs(sh) < 1e-300 ? m : std::sin(0.5 * m * phi) / sh;
+        acc += std::complex<double>(ps->g[l].x, ps->g[l].y) * std::polar(ratio, phi * ((double)a + 0.5 * (m - 1)));
+    }
+    return acc;
+}
+
+}  // namespace
+
+void pulse_reset(pstd_solver* s) {
+    if (s->pulse) s->pulse->from = s->step;
+}
+
+pstd_status pulse_output(pstd_solver* s, int ik, SphereOut* o) {
+    if (!s->pulse) {
+        if (ik != 0) return solver_fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
+        *o = SphereOut{0, make_double2(1.0 / s->inc_sum, 0.0), 1.0};
+        return PSTD_OK;
+    }
+    PulseState* ps = s->pulse;
+    if (ik < 0 || ik >= (int)ps->kbar.size()) return solver_fail(s, PSTD_EINVAL, "wavenumber index out of range");
+    const std::complex<double> inc = incident_phasor(s, ik);
+    const std::complex<double> inv = 1.0 / inc;
+    if (!(std::abs(inc) > 0) || !std::isfinite(inv.real()) || !std::isfinite(inv.imag()))
+        return solver_fail(s, PSTD_ESTATE, "the incident phasor of this wavenumber is zero");
+    *o = SphereOut{ik, make_double2(inv.real(), inv.imag()), ps->kbar[ik]};
+    return PSTD_OK;
+}
+
+}  // namespace pstd

@@ -14,6 +14,7 @@
 namespace pstd {
 struct AdjointState;  // misfit checkpoints and adjoint buffers
 struct SphereState;   // spherical equivalence surface
+struct PulseState;    // pulsed incidence
 }
 
 struct pstd_solver {
@@ -27,6 +28,7 @@ struct pstd_solver {
     int64_t cells = 0;
     int64_t step = 0;      // host mirror of the device step counter
     double inc_sum = 0;    // incident phasor at the origin over the window steps run so far
+    int64_t win_steps = 0; // window steps run so far
     float2* buf[2] = {nullptr, nullptr};
     float2* L = nullptr;
     float* v2 = nullptr;
@@ -52,6 +54,7 @@ struct pstd_solver {
     pstd::ProjectState* proj = nullptr;
     pstd::AdjointState* adj = nullptr;
     pstd::SphereState* sphere = nullptr;
+    pstd::PulseState* pulse = nullptr;
     std::string err;
     bool in_batch = false;
 };
@@ -72,6 +75,9 @@ void solver_drop_graph(pstd_solver* s);
 // the misfit forward run no longer matches the solver state
 void adjoint_invalidate(pstd_solver* s);
 void adjoint_free(pstd_solver* s);
+// taper factor of axis a at index i with its first and second derivatives
+// in the reduced coordinate (Eq. zeta_y)
+void solver_taper(const pstd_problem& p, int a, double dxb, int i, double* z, double* z1, double* z2);
 // zeta_a(i) exp(i khat_a xbar_i) for every grid index of axis a, FP64
 void solver_incident_axis(const pstd_solver* s, int a, std::vector<double2>& out);
 
@@ -87,9 +93,35 @@ int64_t sphere_state_bytes(const pstd_solver* s);
 hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream);
 hipError_t sphere_load(pstd_solver* s, const char* src, hipStream_t stream);
 int64_t sphere_nodes(const pstd_solver* s);
-// node phasors (psi, d_n psi; scattered part, normalised by 1 / inc_sum)
-hipError_t sphere_phasors(pstd_solver* s, double2* out, hipStream_t stream);
-hipError_t sphere_project(pstd_solver* s, const double3* obs, int64_t n_obs, double2* out, hipStream_t stream);
-hipError_t sphere_far_field(pstd_solver* s, const double3* dirs, int64_t n_dir, double2* out, hipStream_t stream);
+// which phasor set an output reads: wavenumber index, the factor that
+// normalises it (one over the incident phasor) and the reduced wavenumber
+struct SphereOut {
+    int ik;
+    double2 scale;
+    double k;
+};
+// node phasors (psi, d_n psi; scattered part, normalised)
+hipError_t sphere_phasors(pstd_solver* s, const SphereOut& o, double2* out, hipStream_t stream);
+hipError_t sphere_project(pstd_solver* s, const SphereOut& o, const double3* obs, int64_t n_obs, double2* out,
+                          hipStream_t stream);
+hipError_t sphere_far_field(pstd_solver* s, const SphereOut& o, const double3* dirs, int64_t n_dir, double2* out,
+                            hipStream_t stream);
+// phasor sums for nk wavenumbers (cleared)
+hipError_t sphere_set_wavenumbers(pstd_solver* s, int nk);
+// largest taper value on the shell cells
+double sphere_taper_max(const pstd_solver* s);
+
+// pulsed incidence (pulse.hip)
+pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double delta, const double* kbar, int32_t nk);
+void pulse_free(PulseState* p);
+int pulse_wavenumbers(const pstd_solver* s);
+double pulse_frequency(const pstd_solver* s, int ik);
+// table and source kernels of step ctr[0] + koff (before the x pass, after the z pass)
+hipError_t pulse_launch_table(const pstd_solver* s, int koff, hipStream_t stream);
+hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t stream);
+// the steps that count for the incident phasors start at the current step
+void pulse_reset(pstd_solver* s);
+// the output of wavenumber ik
+pstd_status pulse_output(pstd_solver* s, int ik, SphereOut* o);
 
 }  // namespace pstd

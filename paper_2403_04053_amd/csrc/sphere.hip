@@ -32,7 +32,9 @@ struct SphereState {
     int* list = nullptr;          // shell cells (linear index), ascending
     int* slot = nullptr;          // grid -> shell slot (-1 outside)
     double2* inc = nullptr;       // zeta exp(i khat . x) per shell slot
-    double2* sum = nullptr;       // running DFT, value and compensation
+    double inc_max = 0;           // largest |zeta| on the shell (0: scattered field only)
+    int nk = 1;                   // wavenumbers with a phasor (more than one with a pulse)
+    double2* sum = nullptr;       // running DFT [wavenumber][slot], value and compensation
     double2* comp = nullptr;
     double2* phasor = nullptr;    // [2][node]: psi, d_n psi
 };
@@ -99,14 +101,16 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 }
 
 // Eq. psiphasor on the shell cells for `count` (1 or 2) consecutive steps
-// ending at ctr[0] + koff, each with its own weight and window flag.  Run
-// before that step's z pass, when both psi^{n-1} and psi^n are in place, so
-// a pair of steps costs one read-modify-write of the FP64 sums; the terms
-// are added in step order, as one launch per step would.
+// ending at ctr[0] + koff, each with its own weight and window flag, for
+// each of nk wavenumbers (weights w_tab[f * wstride + step]).  Run before
+// that step's passes, when both psi^{n-1} and psi^n are in place, so a pair
+// of steps costs one read-modify-write of the FP64 sums; the terms are added
+// in step order, as one launch per step would.
 __global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int count, const int* __restrict__ dft_tab,
-                                 const double2* __restrict__ w_tab, const float2* __restrict__ buf0,
-                                 const float2* __restrict__ buf1, const int* __restrict__ list, int64_t n,
-                                 double2* __restrict__ sum, double2* __restrict__ comp) {
+                                 const double2* __restrict__ w_tab, int64_t wstride, int nk,
+                                 const float2* __restrict__ buf0, const float2* __restrict__ buf1,
+                                 const int* __restrict__ list, int64_t n, double2* __restrict__ sum,
+                                 double2* __restrict__ comp) {
     const int64_t last = ctr[0] + koff;
     const int64_t first = last - (count - 1);
     bool any = false;
@@ -115,24 +119,29 @@ __global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int 
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const int cell = list[c];
-    double2 s = sum[c], e = comp[c];
-    for (int64_t m = first; m <= last; ++m) {
-        if (m >= ctr[1] || !dft_tab[m]) continue;
-        const float2 x = ((m & 1) ? buf1 : buf0)[cell];
-        const double2 w = w_tab[m];
-        const double zr = w.x * x.x - w.y * x.y, zi = w.x * x.y + w.y * x.x;
-        neumaier(s.x, e.x, zr);
-        neumaier(s.y, e.y, zi);
+    float2 x[2];
+    for (int64_t m = first; m <= last; ++m) x[m - first] = ((m & 1) ? buf1 : buf0)[cell];
+    for (int f = 0; f < nk; ++f) {
+        double2 s = sum[f * n + c], e = comp[f * n + c];
+        for (int64_t m = first; m <= last; ++m) {
+            if (m >= ctr[1] || !dft_tab[m]) continue;
+            const float2 v = x[m - first];
+            const double2 w = w_tab[f * wstride + m];
+            const double zr = w.x * v.x - w.y * v.y, zi = w.x * v.y + w.y * v.x;
+            neumaier(s.x, e.x, zr);
+            neumaier(s.y, e.y, zi);
+        }
+        sum[f * n + c] = s;
+        comp[f * n + c] = e;
     }
-    sum[c] = s;
-    comp[c] = e;
 }
 
-// node values: separable interpolation of (sum + comp) * scale - inc
+// node values: separable interpolation of (sum + comp) * scale - inc (scale
+// complex: one over the incident phasor)
 __global__ void node_kernel(int n_nodes, const int* __restrict__ start, const double* __restrict__ lw,
                             const double3* __restrict__ normal, const int* __restrict__ slot, int nx, int ny,
                             const double2* __restrict__ sum, const double2* __restrict__ comp,
-                            const double2* __restrict__ inc, double scale, double2* __restrict__ out) {
+                            const double2* __restrict__ inc, double2 scale, double2* __restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_nodes) return;
     const int ix = start[3 * q], iy = start[3 * q + 1], iz = start[3 * q + 2];
@@ -151,7 +160,8 @@ __global__ void node_kernel(int n_nodes, const int* __restrict__ start, const do
                 const int64_t lin = (ix + a) + (int64_t)nx * ((iy + b) + (int64_t)ny * (iz + c));
                 const int sl = slot[lin];
                 const double2 sv = sum[sl], cv = comp[sl], iv = inc[sl];
-                const double pr = (sv.x + cv.x) * scale - iv.x, pi = (sv.y + cv.y) * scale - iv.y;
+                const double ar = sv.x + cv.x, ai = sv.y + cv.y;
+                const double pr = ar * scale.x - ai * scale.y - iv.x, pi = ar * scale.y + ai * scale.x - iv.y;
                 const double w0 = Lx[a] * wyz;
                 vr += w0 * pr;
                 vi += w0 * pi;
@@ -174,12 +184,14 @@ __global__ void node_kernel(int n_nodes, const int* __restrict__ start, const do
 
 constexpr int kNodeChunk = 256;
 
-// Psi(r) = -(1/4pi) sum_q w_q exp(iR)/R [dn psi + (-i + 1/R)(n . (s - r)/R) psi]
+// Psi(r) = -(1/4pi) sum_q w_q exp(ikR)/R [dn psi + (-ik + 1/R)(n . (s - r)/R) psi],
+// k the reduced wavenumber of the phasors (1 for the central wave)
 __global__ __launch_bounds__(256) void sphere_points_kernel(int n_nodes, const double3* __restrict__ node,
                                                             const double3* __restrict__ normal,
                                                             const double* __restrict__ weight,
                                                             const double2* __restrict__ ph, const double3* __restrict__ obs,
-                                                            int64_t n_obs, double k0, double2* __restrict__ out) {
+                                                            int64_t n_obs, double k0, double kw,
+                                                            double2* __restrict__ out) {
     __shared__ double3 s_node[kNodeChunk], s_nrm[kNodeChunk];
     __shared__ double s_w[kNodeChunk];
     __shared__ double2 s_v[kNodeChunk], s_d[kNodeChunk];
@@ -208,12 +220,12 @@ __global__ __launch_bounds__(256) void sphere_points_kernel(int n_nodes, const d
             const double R = sqrt(dx * dx + dy * dy + dz * dz);
             const double inv = 1.0 / R;
             const double ndr = (s_nrm[e].x * dx + s_nrm[e].y * dy + s_nrm[e].z * dz) * inv;
-            // dn psi + (-i + 1/R) ndr psi
+            // dn psi + (-ik + 1/R) ndr psi
             const double2 v = s_v[e], d = s_d[e];
-            const double tr = d.x + ndr * (v.y + inv * v.x);
-            const double ti = d.y + ndr * (-v.x + inv * v.y);
+            const double tr = d.x + ndr * (kw * v.y + inv * v.x);
+            const double ti = d.y + ndr * (-kw * v.x + inv * v.y);
             double sn, cs;
-            sincos(R, &sn, &cs);
+            sincos(kw * R, &sn, &cs);
             const double f = s_w[e] * inv;
             ar += f * (cs * tr - sn * ti);
             ai += f * (cs * ti + sn * tr);
@@ -222,12 +234,13 @@ __global__ __launch_bounds__(256) void sphere_points_kernel(int n_nodes, const d
     if (live) out[o] = make_double2(-ar / (4 * kPi), -ai / (4 * kPi));
 }
 
-// f(r_hat) = -(1/4pi) sum_q w_q [dn psi + i (n . r_hat) psi] exp(-i r_hat . s) / k0
+// f(r_hat) = -(1/4pi) sum_q w_q [dn psi + ik (n . r_hat) psi] exp(-ik r_hat . s) / k0
 __global__ __launch_bounds__(256) void sphere_far_kernel(int n_nodes, const double3* __restrict__ node,
                                                          const double3* __restrict__ normal,
                                                          const double* __restrict__ weight,
                                                          const double2* __restrict__ ph, const double3* __restrict__ dirs,
-                                                         int64_t n_dir, double k0, double2* __restrict__ out) {
+                                                         int64_t n_dir, double k0, double kw,
+                                                         double2* __restrict__ out) {
     __shared__ double3 s_node[kNodeChunk], s_nrm[kNodeChunk];
     __shared__ double s_w[kNodeChunk];
     __shared__ double2 s_v[kNodeChunk], s_d[kNodeChunk];
@@ -251,9 +264,9 @@ __global__ __launch_bounds__(256) void sphere_far_kernel(int n_nodes, const doub
         for (int e = 0; e < nq; ++e) {
             const double nr = s_nrm[e].x * rh.x + s_nrm[e].y * rh.y + s_nrm[e].z * rh.z;
             const double2 v = s_v[e], d = s_d[e];
-            const double tr = d.x - nr * v.y, ti = d.y + nr * v.x;  // dn psi + i nr psi
+            const double tr = d.x - kw * nr * v.y, ti = d.y + kw * nr * v.x;  // dn psi + ik nr psi
             double sn, cs;
-            sincos(-(rh.x * s_node[e].x + rh.y * s_node[e].y + rh.z * s_node[e].z), &sn, &cs);
+            sincos(-kw * (rh.x * s_node[e].x + rh.y * s_node[e].y + rh.z * s_node[e].z), &sn, &cs);
             ar += s_w[e] * (cs * tr - sn * ti);
             ai += s_w[e] * (cs * ti + sn * tr);
         }
@@ -341,11 +354,15 @@ pstd_status sphere_create(pstd_solver* s) {
         const double2 xy = make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
         inc[k] = make_double2(xy.x * z.x - xy.y * z.y, xy.x * z.y + xy.y * z.x);
     }
+    // |exp(i khat . x)| = 1, so |inc| is the taper on the shell
+    double inc_max = 0;
+    for (const double2& v : inc) inc_max = std::max(inc_max, std::sqrt(v.x * v.x + v.y * v.y));
     SphereState* sp = new SphereState();
     s->sphere = sp;
     sp->n_nodes = n_nodes;
     sp->R = R;
     sp->n_shell = (int64_t)list.size();
+    sp->inc_max = inc_max;
     hipError_t e;
     auto up = [&](auto** dst, const auto& v) {
         using T = typename std::decay_t<decltype(v)>::value_type;
@@ -370,27 +387,45 @@ hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStrea
     if (!sp || sp->n_shell == 0 || count < 1) return hipSuccess;
     if (count > 2 || koff < count - 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(shell_dft_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
-                       koff, count, s->dft_tab, s->w_tab, s->buf[0], s->buf[1], sp->list, sp->n_shell, sp->sum,
-                       sp->comp);
+                       koff, count, s->dft_tab, s->w_tab, s->tab_cap, sp->nk, s->buf[0], s->buf[1], sp->list,
+                       sp->n_shell, sp->sum, sp->comp);
     return hipGetLastError();
 }
 
 hipError_t sphere_clear(pstd_solver* s, hipStream_t stream) {
     SphereState* sp = s->sphere;
     if (!sp) return hipSuccess;
-    hipError_t e = hipMemsetAsync(sp->sum, 0, sp->n_shell * sizeof(double2), stream);
-    if (e == hipSuccess) e = hipMemsetAsync(sp->comp, 0, sp->n_shell * sizeof(double2), stream);
+    const size_t b = sp->nk * sp->n_shell * sizeof(double2);
+    hipError_t e = hipMemsetAsync(sp->sum, 0, b, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(sp->comp, 0, b, stream);
     return e;
 }
 
+hipError_t sphere_set_wavenumbers(pstd_solver* s, int nk) {
+    SphereState* sp = s->sphere;
+    if (!sp || nk < 1) return hipErrorInvalidValue;
+    (void)hipFree(sp->sum);
+    (void)hipFree(sp->comp);
+    sp->sum = sp->comp = nullptr;
+    sp->nk = nk;
+    const size_t b = nk * sp->n_shell * sizeof(double2);
+    hipError_t e = hipMalloc(&sp->sum, b);
+    if (e == hipSuccess) e = hipMalloc(&sp->comp, b);
+    if (e == hipSuccess) e = hipMemset(sp->sum, 0, b);
+    if (e == hipSuccess) e = hipMemset(sp->comp, 0, b);
+    return e;
+}
+
+double sphere_taper_max(const pstd_solver* s) { return s->sphere ? s->sphere->inc_max : 0.0; }
+
 int64_t sphere_state_bytes(const pstd_solver* s) {
-    return s->sphere ? 2 * s->sphere->n_shell * (int64_t)sizeof(double2) : 0;
+    return s->sphere ? 2 * s->sphere->nk * s->sphere->n_shell * (int64_t)sizeof(double2) : 0;
 }
 
 hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream) {
     const SphereState* sp = s->sphere;
     if (!sp) return hipSuccess;
-    const size_t b = sp->n_shell * sizeof(double2);
+    const size_t b = sp->nk * sp->n_shell * sizeof(double2);
     hipError_t e = hipMemcpyAsync(dst, sp->sum, b, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dst + b, sp->comp, b, hipMemcpyDeviceToDevice, stream);
     return e;
@@ -399,7 +434,7 @@ hipError_t sphere_save(const pstd_solver* s, char* dst, hipStream_t stream) {
 hipError_t sphere_load(pstd_solver* s, const char* src, hipStream_t stream) {
     SphereState* sp = s->sphere;
     if (!sp) return hipSuccess;
-    const size_t b = sp->n_shell * sizeof(double2);
+    const size_t b = sp->nk * sp->n_shell * sizeof(double2);
     hipError_t e = hipMemcpyAsync(sp->sum, src, b, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sp->comp, src + b, b, hipMemcpyDeviceToDevice, stream);
     return e;
@@ -407,32 +442,36 @@ hipError_t sphere_load(pstd_solver* s, const char* src, hipStream_t stream) {
 
 int64_t sphere_nodes(const pstd_solver* s) { return s->sphere ? s->sphere->n_nodes : 0; }
 
-hipError_t sphere_phasors(pstd_solver* s, double2* out, hipStream_t stream) {
+hipError_t sphere_phasors(pstd_solver* s, const SphereOut& o, double2* out, hipStream_t stream) {
     SphereState* sp = s->sphere;
+    if (o.ik < 0 || o.ik >= sp->nk) return hipErrorInvalidValue;
+    const int64_t off = (int64_t)o.ik * sp->n_shell;
     hipLaunchKernelGGL(node_kernel, dim3((unsigned)((sp->n_nodes + 127) / 128)), dim3(128), 0, stream, sp->n_nodes,
-                       sp->start, sp->lw, sp->normal, sp->slot, s->prob.n[0], s->prob.n[1], sp->sum, sp->comp, sp->inc,
-                       1.0 / s->inc_sum, sp->phasor);
+                       sp->start, sp->lw, sp->normal, sp->slot, s->prob.n[0], s->prob.n[1], sp->sum + off,
+                       sp->comp + off, sp->inc, o.scale, sp->phasor);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && out)
         e = hipMemcpyAsync(out, sp->phasor, 2 * (size_t)sp->n_nodes * sizeof(double2), hipMemcpyDeviceToDevice, stream);
     return e;
 }
 
-hipError_t sphere_project(pstd_solver* s, const double3* obs, int64_t n_obs, double2* out, hipStream_t stream) {
+hipError_t sphere_project(pstd_solver* s, const SphereOut& o, const double3* obs, int64_t n_obs, double2* out,
+                          hipStream_t stream) {
     SphereState* sp = s->sphere;
-    hipError_t e = sphere_phasors(s, nullptr, stream);
+    hipError_t e = sphere_phasors(s, o, nullptr, stream);
     if (e || n_obs == 0) return e;
     hipLaunchKernelGGL(sphere_points_kernel, dim3((unsigned)((n_obs + 255) / 256)), dim3(256), 0, stream, sp->n_nodes,
-                       sp->node, sp->normal, sp->weight, sp->phasor, obs, n_obs, s->prob.k0, out);
+                       sp->node, sp->normal, sp->weight, sp->phasor, obs, n_obs, s->prob.k0, o.k, out);
     return hipGetLastError();
 }
 
-hipError_t sphere_far_field(pstd_solver* s, const double3* dirs, int64_t n_dir, double2* out, hipStream_t stream) {
+hipError_t sphere_far_field(pstd_solver* s, const SphereOut& o, const double3* dirs, int64_t n_dir, double2* out,
+                            hipStream_t stream) {
     SphereState* sp = s->sphere;
-    hipError_t e = sphere_phasors(s, nullptr, stream);
+    hipError_t e = sphere_phasors(s, o, nullptr, stream);
     if (e || n_dir == 0) return e;
     hipLaunchKernelGGL(sphere_far_kernel, dim3((unsigned)((n_dir + 255) / 256)), dim3(256), 0, stream, sp->n_nodes,
-                       sp->node, sp->normal, sp->weight, sp->phasor, dirs, n_dir, s->prob.k0, out);
+                       sp->node, sp->normal, sp->weight, sp->phasor, dirs, n_dir, s->prob.k0, o.k, out);
     return hipGetLastError();
 }
 
