@@ -86,7 +86,8 @@ def main():
                     help="single: equivalence surface (sphere r = 5 with a shell DFT, or the box planes at "
                          "N/2 -+ 40 with the plane sums inside the passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3", "fdtd"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3", "fdtd", "pulse"],
+                    default="single",
                     help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
                          "adjoint: misfit gradient of the 160^3 voxel potential (6000 steps)")
     ap.add_argument("--fd-voxels", type=int, default=64, help="adjoint: finite-difference check voxels")
@@ -126,6 +127,8 @@ def main():
         return bench_x3(args)
     if args.workload == "fdtd":
         return bench_fdtd(args)
+    if args.workload == "pulse":
+        return bench_pulse(args)
 
     prob, V = synth.square_barrier_160(n_fft=args.n)
     # the whole timed region sits inside the surface-DFT window
@@ -357,6 +360,104 @@ def bench_adjoint(args):
         out["fd_check"] = {"voxels": len(vox), "delta_E0": args.fd_delta, "max_rel_err": float(err.max()),
                            "median_rel_err": float(np.median(err)),
                            "criterion": "|g_adj - g_fd| / max(|g_fd|, 1e-3 max|g_fd|)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_pulse(args):
+    """Pulsed incidence on the 160^3 square-barrier grid: a Gaussian packet
+    (centre k = k0, width 6 reduced lengths) along z, the spherical surface
+    of radius 5.6 accumulating phasors at five wavenumbers k = 0.8 ... 1.2
+    k0 every step.  Reports the pulsed step rate (passes, the packet's
+    table and layer-source kernels, the five-wavenumber shell DFT) and a
+    whole solve (tau = 160, then the far field at every wavenumber) against
+    the monochromatic solve of the same grid, which gives one wavenumber per
+    run (14440 steps)."""
+    import numpy as np
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+    base, V = synth.square_barrier_160(n_fft=args.n)
+    sph = dict(surface_kind=1, sphere_radius=5.6 * args.n / 160, sphere_nodes=(64, 128))
+    dtau_p, _ = P.pstd_reduced_step(P.problem_from(base))
+    solve_steps = int(round(160.0 / dtau_p))
+    prob = base.replace(n_steps=solve_steps, dft_begin=0, dft_end=10 ** 12, **sph)
+    delta = base.k0 * base.h[0]
+    psi0 = synth.gaussian_pulse_1d(512, delta, 1.0, 6.0, -30.0)
+    kb = [0.8, 0.9, 1.0, 1.1, 1.2]
+    stream = torch.cuda.current_stream()
+    th = np.deg2rad(np.arange(0, 181, 1.0))
+    ph = np.deg2rad(np.arange(0, 360, 2.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    dirs = torch.as_tensor(np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3),
+                           device="cuda:0")
+
+    def solve(problem, pulse, steps, tune=None):
+        s = P.Solver(problem, stream=stream)
+        s.set_potential(V)
+        if tune is not None:
+            for axis in range(3):
+                s.set_tile(axis, *tune[axis][1:2], *tune[axis][3:4])
+        else:
+            tune = s.autotune(reps=20)
+        if pulse:
+            s.set_pulse(psi0, delta, kb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(steps)
+        fs = [s.far_field(dirs, ik=ik) for ik in range(len(kb) if pulse else 1)]
+        torch.cuda.synchronize()
+        return s, time.perf_counter() - t0, tune
+
+    # the pulsed step rate, inside the packet's passage
+    s, _, tune = solve(prob, True, args.warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = prob.cells
+    n_timed = min(args.steps, 100)
+    pass_ms = s.run_timed(n_timed)
+    avg = {k: pass_ms[i] / n_timed for i, k in enumerate("xyz")}
+    us = s.pass_time(2, reps=100)
+    achieved = PASS_BYTES["z"] * cells / (us / 1e6) / 1e9
+    finite = bool(torch.isfinite(torch.view_as_real(s.psi(0))).all().item())
+    s.close()
+    # whole solves: the pulsed one (five wavenumbers) and the monochromatic one
+    s, t_pulse, _ = solve(prob, True, solve_steps, tune)
+    s.close()
+    cw_prob = base.replace(dft_begin=base.n_steps - 1354, dft_end=base.n_steps, **sph)
+    s, t_cw, _ = solve(cw_prob, False, base.n_steps, tune)
+    s.close()
+    out = {
+        "metric": "PSTD Gcell-updates/s (FP32 step, pulsed incidence, FP64 shell DFT at 5 wavenumbers)",
+        "value": round(cells * args.steps / (ms / 1e3) / 1e9, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 FFT grid, Gaussian packet along z "
+                               "(k0, width 6), sphere r=5.6 (64x128 nodes), phasors at k/k0 = 0.8, 0.9, 1.0, 1.1, 1.2",
+                   "cells": cells},
+        "roofline": {"bound": "hbm", "kernel": "pass_z", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": PASS_BYTES["z"], "kernel_us": round(us, 3),
+                     "pass_ms_in_steps": {k: round(v, 5) for k, v in avg.items()}},
+        "solve": {"pulsed_s": round(t_pulse, 3), "pulsed_steps": solve_steps, "wavenumbers": len(kb),
+                  "monochromatic_s": round(t_cw, 3), "monochromatic_steps": base.n_steps,
+                  "wavenumbers_per_s_pulsed": round(len(kb) / t_pulse, 3),
+                  "wavenumbers_per_s_monochromatic": round(1 / t_cw, 3)},
+        "finite": finite,
+    }
     print(json.dumps(out), flush=True)
 
 

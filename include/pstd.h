@@ -295,7 +295,8 @@ pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir,
  * batch (EUNSUPPORTED otherwise); call before the first step (ESTATE).
  * EINVAL: n1d not a power of two in [8, 2^20], delta <= 0, n_k outside
  * [1, 64], a wavenumber <= 0 or beyond the step bound, the 1D grid's
- * Nyquist mode beyond the step bound, a non-finite or zero packet.  A
+ * Nyquist mode beyond the step bound, a non-finite or zero packet, a
+ * spectrum so wide that the layer's table would exceed 2^26 entries.  A
  * pulsed run has no checkpoint (pstd_save_state / pstd_load_state return
  * EUNSUPPORTED).  Synchronises. */
 pstd_status pstd_set_pulse(pstd_solver* s, const double* psi0_host, int32_t n1d, double delta,

@@ -347,7 +347,21 @@ pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
 }
 
 pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int count, hipEvent_t* ev) {
-    if (s->sphere) {
+    if (s->pulse) {
+        // the packet's values on the layer's table for this step, and psi^n
+        // on the shell into the group's ring (added at the group's end), in
+        // one launch
+        const int* list;
+        int64_t n_shell;
+        float2* stage;
+        pstd::sphere_stage_buffers(s, &list, &n_shell, &stage);
+        const float2* src[2] = {s->buf[0], s->buf[1]};
+        hipError_t e = pstd::pulse_launch_pre(s, koff, src, list, n_shell, stage, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "pulse table / shell stage launch");
+    } else if (pstd::sphere_staged(s)) {
+        hipError_t e = pstd::sphere_launch_stage(s, koff, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "shell stage launch");
+    } else if (s->sphere) {
         // shell DFT in pairs of steps of the group (the odd step adds the even
         // one before it; a last even step goes alone), before this step
         // overwrites psi^{n-1}
@@ -364,11 +378,6 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
             for (int i = 1; i < 6; ++i) HIP_TRY(s, hipEventRecord(ev[i], stream));
         return PSTD_OK;
     }
-    if (s->pulse) {
-        // the packet's values on the layer's table for this step
-        hipError_t e = pstd::pulse_launch_table(s, koff, stream);
-        if (e != hipSuccess) return hip_fail(s, e, "pulse table launch");
-    }
     for (int axis = 0; axis < 3; ++axis) {
         pstd::PassArgs a;
         pstd::solver_args(s, axis, a);
@@ -382,6 +391,11 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
         // the layer source of the packet, added to psi^{n+1}
         hipError_t e = pstd::pulse_launch_source(s, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pulse source launch");
+    }
+    if (pstd::sphere_staged(s) && koff == count - 1) {
+        // the group's staged steps into the phasor sums (before the counter advances)
+        hipError_t e = pstd::sphere_launch_flush(s, count, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "shell flush launch");
     }
     return PSTD_OK;
 }

@@ -12,7 +12,7 @@
 // Each step, pulse_table_kernel evaluates the spectral interpolation of
 // Eqs. pstd_psiinc / pstd_dpsiinc on a table four times finer than the
 // grids, over the d-range of the transition layer only (a few hundred
-// points); pulse_source_kernel, after the z pass, interpolates the table at
+// points, one wave each); pulse_source_kernel, after the z pass, interpolates the table at
 // every layer cell with 8-point Lagrange weights (error ~ (k h)^8 / 8!, below
 // 1e-8 of the packet) and adds the layer source of Eq.
 // dimlesstildeSchrodinger, lap(zeta) psi_inc + 2 grad(zeta) . k_hat
@@ -39,6 +39,7 @@ struct PulseState {
     int J = 0;                 // table points d_lo + j h
     double d_lo = 0, h = 0;
     double2* tab = nullptr;    // [2][J]: sum a_l e^{i k_l d}, sum a_l k_l e^{i k_l d}
+    double2* ekd = nullptr;    // [J][K]: e^{i k_l d_j}
     int64_t n_cells = 0;       // transition-layer cells
     int* cell = nullptr;
     int* j0 = nullptr;         // first table point of each cell's stencil
@@ -54,7 +55,6 @@ struct PulseState {
 namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
-constexpr int kModeChunk = 512;
 constexpr int kLag = 8;
 
 // in-place radix-2 DFT, forward (e^{-i 2 pi l j / N}), N a power of two
@@ -79,45 +79,53 @@ void fft_pow2(std::vector<std::complex<double>>& a) {
 }
 
 // T0(d_j) = sum_l a_l(n) e^{i k_l d_j}, T1(d_j) = sum_l a_l(n) k_l e^{i k_l d_j}
-// for the table points of step n = ctr[0] + koff
-__global__ __launch_bounds__(256) void pulse_table_kernel(const int64_t* __restrict__ ctr, int koff, int K,
-                                                          const double2* __restrict__ coef,
-                                                          const double* __restrict__ theta, double k_lo, double dk,
-                                                          int J, double d_lo, double h, double2* __restrict__ tab) {
+// for the table points of step n = ctr[0] + koff.  One wave per table point:
+// its 64 lanes take every 64th mode (a_l(n) from one FP64 sincos, e^{i k_l
+// d_j} from the precomputed table), then the wave adds the lane sums in a
+// fixed order.  Blocks past the table's stage psi^n on the sphere's shell
+// into slot koff of the ring (same launch: both only read the state before
+// the step).
+__global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restrict__ ctr, int koff, int K,
+                                                        const double2* __restrict__ coef,
+                                                        const double* __restrict__ theta, double k_lo, double dk,
+                                                        int J, const double2* __restrict__ ekd,
+                                                        double2* __restrict__ tab, int table_blocks,
+                                                        const float2* __restrict__ buf0, const float2* __restrict__ buf1,
+                                                        const int* __restrict__ list, int64_t n_shell,
+                                                        float2* __restrict__ stage) {
     const int64_t n = ctr[0] + koff;
-    if (n >= ctr[1]) return;  // whole grid, before any barrier
-    __shared__ double2 a[kModeChunk];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const double d = d_lo + j * h;
-    double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
-    for (int m0 = 0; m0 < K; m0 += kModeChunk) {
-        const int nm = min(kModeChunk, K - m0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nm; e += blockDim.x) {
-            double sn, cs;
-            sincos(theta[m0 + e] * (double)n, &sn, &cs);
-            const double2 c = coef[m0 + e];
-            a[e] = make_double2(c.x * cs + c.y * sn, c.y * cs - c.x * sn);  // c e^{-i theta n}
-        }
-        __syncthreads();
-        if (j >= J) continue;
-        double er, ei, rr, ri;
-        sincos((k_lo + m0 * dk) * d, &ei, &er);
-        sincos(dk * d, &ri, &rr);
-        for (int e = 0; e < nm; ++e) {
-            const double2 ae = a[e];
-            const double kl = k_lo + (m0 + e) * dk;
-            const double tr = ae.x * er - ae.y * ei, ti = ae.x * ei + ae.y * er;
-            s0r += tr;
-            s0i += ti;
-            s1r += kl * tr;
-            s1i += kl * ti;
-            const double nr = er * rr - ei * ri;
-            ei = er * ri + ei * rr;
-            er = nr;
-        }
+    if (n >= ctr[1]) return;
+    if ((int)blockIdx.x >= table_blocks) {
+        const int64_t c = (int64_t)(blockIdx.x - table_blocks) * blockDim.x + threadIdx.x;
+        if (c < n_shell) stage[koff * n_shell + c] = ((n & 1) ? buf1 : buf0)[list[c]];
+        return;
     }
-    if (j < J) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (j >= J) return;  // whole waves
+    double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+    const double2* e_j = ekd + (int64_t)j * K;
+    for (int l = lane; l < K; l += 64) {
+        double sn, cs;
+        sincos(theta[l] * (double)n, &sn, &cs);
+        const double2 e = e_j[l];
+        // c e^{i (k d - theta n)}
+        const double er = e.x * cs + e.y * sn, ei = e.y * cs - e.x * sn;
+        const double2 c = coef[l];
+        const double tr = c.x * er - c.y * ei, ti = c.x * ei + c.y * er;
+        const double kl = k_lo + l * dk;
+        s0r += tr;
+        s0i += ti;
+        s1r += kl * tr;
+        s1i += kl * ti;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s0r += __shfl_xor(s0r, off);
+        s0i += __shfl_xor(s0i, off);
+        s1r += __shfl_xor(s1r, off);
+        s1i += __shfl_xor(s1i, off);
+    }
+    if (lane == 0) {
         tab[j] = make_double2(s0r, s0i);
         tab[J + j] = make_double2(s1r, s1i);
     }
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(256) void pulse_source_kernel(const int64_t* __rest
 
 void pulse_free(PulseState* p) {
     if (!p) return;
-    void* ptrs[] = {p->coef, p->theta, p->tab, p->cell, p->j0, p->w, p->ab};
+    void* ptrs[] = {p->coef, p->theta, p->tab, p->ekd, p->cell, p->j0, p->w, p->ab};
     for (void* q : ptrs) (void)hipFree(q);
     delete p;
 }
@@ -295,6 +303,16 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     ps->h = std::min(delta, std::min(s->dxb[0], std::min(s->dxb[1], s->dxb[2]))) / 4;
     ps->d_lo = dmin - 4 * ps->h;
     ps->J = (int)std::ceil((dmax - ps->d_lo) / ps->h) + 5;
+    if ((int64_t)ps->J * K > (int64_t(1) << 26)) {
+        pulse_free(ps);
+        return solver_fail(s, PSTD_EINVAL, "the packet's spectrum is too wide for the layer's table (J K > 2^26)");
+    }
+    std::vector<double2> ekd((size_t)ps->J * K);
+    for (int j = 0; j < ps->J; ++j)
+        for (int m = 0; m < K; ++m) {
+            const double ph = (ps->k_lo + m * dk) * (ps->d_lo + j * ps->h);
+            ekd[(size_t)j * K + m] = make_double2(std::cos(ph), std::sin(ph));
+        }
     std::vector<int> j0(cell.size());
     std::vector<double> w(kLag * cell.size());
     for (size_t c = 0; c < cell.size(); ++c) {
@@ -316,7 +334,8 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     };
     hipError_t e;
     if ((e = hipStreamSynchronize(s->stream)) || (e = up(&ps->coef, coef)) || (e = up(&ps->theta, ps->theta_h)) ||
-        (e = hipMalloc(&ps->tab, 2 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->cell, cell)) ||
+        (e = hipMalloc(&ps->tab, 2 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->ekd, ekd)) ||
+        (e = up(&ps->cell, cell)) ||
         (e = up(&ps->j0, j0)) || (e = up(&ps->w, w)) || (e = up(&ps->ab, ab))) {
         pulse_free(ps);
         return solver_hip_fail(s, e, "pulse tables");
@@ -330,11 +349,17 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     return solver_ensure_tables(s, cap);
 }
 
-hipError_t pulse_launch_table(const pstd_solver* s, int koff, hipStream_t stream) {
+hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const float2* const* stage_src, const int* list,
+                            int64_t n_shell, float2* stage, hipStream_t stream) {
     const PulseState* ps = s->pulse;
-    if (!ps || ps->n_cells == 0) return hipSuccess;
-    hipLaunchKernelGGL(pulse_table_kernel, dim3((unsigned)((ps->J + 255) / 256)), dim3(256), 0, stream, s->ctr, koff,
-                       ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->d_lo, ps->h, ps->tab);
+    if (!ps) return hipSuccess;
+    if (stage && (koff < 0 || koff >= kStageSteps)) return hipErrorInvalidValue;
+    const int table_blocks = ps->n_cells ? (ps->J + 3) / 4 : 0;
+    const int stage_blocks = stage ? (int)((n_shell + 255) / 256) : 0;
+    if (table_blocks + stage_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(pulse_pre_kernel, dim3((unsigned)(table_blocks + stage_blocks)), dim3(256), 0, stream, s->ctr,
+                       koff, ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->ekd, ps->tab, table_blocks,
+                       stage_src[0], stage_src[1], list, stage ? n_shell : 0, stage);
     return hipGetLastError();
 }
 

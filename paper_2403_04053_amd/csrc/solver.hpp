@@ -106,8 +106,16 @@ hipError_t sphere_project(pstd_solver* s, const SphereOut& o, const double3* obs
                           hipStream_t stream);
 hipError_t sphere_far_field(pstd_solver* s, const SphereOut& o, const double3* dirs, int64_t n_dir, double2* out,
                             hipStream_t stream);
-// phasor sums for nk wavenumbers (cleared)
+// phasor sums for nk wavenumbers (cleared) and the ring of staged steps:
+// a pulsed run stages psi on the shell each step and adds a launch group's
+// steps to the sums once, at its end
+constexpr int kStageSteps = 16;  // steps per launch group at most
 hipError_t sphere_set_wavenumbers(pstd_solver* s, int nk);
+bool sphere_staged(const pstd_solver* s);
+hipError_t sphere_launch_stage(const pstd_solver* s, int koff, hipStream_t stream);
+hipError_t sphere_launch_flush(const pstd_solver* s, int count, hipStream_t stream);
+// the shell list and the ring (null without staging) for a fused launch
+void sphere_stage_buffers(const pstd_solver* s, const int** list, int64_t* n_shell, float2** stage);
 // largest taper value on the shell cells
 double sphere_taper_max(const pstd_solver* s);
 
@@ -116,8 +124,11 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
 void pulse_free(PulseState* p);
 int pulse_wavenumbers(const pstd_solver* s);
 double pulse_frequency(const pstd_solver* s, int ik);
-// table and source kernels of step ctr[0] + koff (before the x pass, after the z pass)
-hipError_t pulse_launch_table(const pstd_solver* s, int koff, hipStream_t stream);
+// before the x pass of step ctr[0] + koff: the packet's table, and psi^n of
+// the shell cells `list` into slot koff of `stage` (when stage is not null)
+hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const float2* const* stage_src, const int* list,
+                            int64_t n_shell, float2* stage, hipStream_t stream);
+// after the z pass: the layer source
 hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t stream);
 // the steps that count for the incident phasors start at the current step
 void pulse_reset(pstd_solver* s);

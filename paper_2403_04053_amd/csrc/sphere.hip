@@ -36,6 +36,7 @@ struct SphereState {
     int nk = 1;                   // wavenumbers with a phasor (more than one with a pulse)
     double2* sum = nullptr;       // running DFT [wavenumber][slot], value and compensation
     double2* comp = nullptr;
+    float2* stage = nullptr;      // [kStageSteps][slot]: psi of the steps of a launch group (pulsed runs)
     double2* phasor = nullptr;    // [2][node]: psi, d_n psi
 };
 
@@ -130,6 +131,46 @@ __global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int 
             const double zr = w.x * v.x - w.y * v.y, zi = w.x * v.y + w.y * v.x;
             neumaier(s.x, e.x, zr);
             neumaier(s.y, e.y, zi);
+        }
+        sum[f * n + c] = s;
+        comp[f * n + c] = e;
+    }
+}
+
+// psi^n on the shell cells into slot koff of the ring, n = ctr[0] + koff,
+// before step n's passes (psi^n is in place until step n + 1)
+__global__ void shell_stage_kernel(const int64_t* __restrict__ ctr, int koff, const float2* __restrict__ buf0,
+                                   const float2* __restrict__ buf1, const int* __restrict__ list, int64_t n,
+                                   float2* __restrict__ stage) {
+    const int64_t m = ctr[0] + koff;
+    if (m >= ctr[1]) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    stage[koff * n + c] = ((m & 1) ? buf1 : buf0)[list[c]];
+}
+
+// Eq. psiphasor for the `count` staged steps ctr[0] .. ctr[0] + count - 1 of
+// a launch group at each of nk wavenumbers, added in step order: one
+// read-modify-write of the FP64 sums per group instead of per pair
+__global__ void shell_flush_kernel(const int64_t* __restrict__ ctr, int count, const int* __restrict__ dft_tab,
+                                   const double2* __restrict__ w_tab, int64_t wstride, int nk,
+                                   const float2* __restrict__ stage, int64_t n, double2* __restrict__ sum,
+                                   double2* __restrict__ comp) {
+    const int64_t first = ctr[0];
+    bool any = false;
+    for (int k = 0; k < count; ++k) any |= first + k < ctr[1] && dft_tab[first + k] != 0;
+    if (!any) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int f = 0; f < nk; ++f) {
+        double2 s = sum[f * n + c], e = comp[f * n + c];
+        for (int k = 0; k < count; ++k) {
+            const int64_t m = first + k;
+            if (m >= ctr[1] || !dft_tab[m]) continue;
+            const float2 v = stage[k * n + c];
+            const double2 w = w_tab[f * wstride + m];
+            neumaier(s.x, e.x, w.x * v.x - w.y * v.y);
+            neumaier(s.y, e.y, w.x * v.y + w.y * v.x);
         }
         sum[f * n + c] = s;
         comp[f * n + c] = e;
@@ -278,8 +319,8 @@ __global__ __launch_bounds__(256) void sphere_far_kernel(int n_nodes, const doub
 
 void sphere_free(SphereState* sp) {
     if (!sp) return;
-    void* ptrs[] = {sp->node, sp->normal, sp->weight, sp->start, sp->lw, sp->list,
-                    sp->slot, sp->inc,    sp->sum,    sp->comp,  sp->phasor};
+    void* ptrs[] = {sp->node, sp->normal, sp->weight, sp->start, sp->lw,   sp->list,
+                    sp->slot, sp->inc,    sp->sum,    sp->comp,  sp->phasor, sp->stage};
     for (void* p : ptrs) (void)hipFree(p);
     delete sp;
 }
@@ -392,6 +433,33 @@ hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStrea
     return hipGetLastError();
 }
 
+bool sphere_staged(const pstd_solver* s) { return s->sphere && s->sphere->stage; }
+
+void sphere_stage_buffers(const pstd_solver* s, const int** list, int64_t* n_shell, float2** stage) {
+    const SphereState* sp = s->sphere;
+    *list = sp ? sp->list : nullptr;
+    *n_shell = sp ? sp->n_shell : 0;
+    *stage = sp ? sp->stage : nullptr;
+}
+
+hipError_t sphere_launch_stage(const pstd_solver* s, int koff, hipStream_t stream) {
+    const SphereState* sp = s->sphere;
+    if (!sp || !sp->stage || sp->n_shell == 0) return hipSuccess;
+    if (koff < 0 || koff >= kStageSteps) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shell_stage_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
+                       koff, s->buf[0], s->buf[1], sp->list, sp->n_shell, sp->stage);
+    return hipGetLastError();
+}
+
+hipError_t sphere_launch_flush(const pstd_solver* s, int count, hipStream_t stream) {
+    const SphereState* sp = s->sphere;
+    if (!sp || !sp->stage || sp->n_shell == 0) return hipSuccess;
+    if (count < 1 || count > kStageSteps) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shell_flush_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
+                       count, s->dft_tab, s->w_tab, s->tab_cap, sp->nk, sp->stage, sp->n_shell, sp->sum, sp->comp);
+    return hipGetLastError();
+}
+
 hipError_t sphere_clear(pstd_solver* s, hipStream_t stream) {
     SphereState* sp = s->sphere;
     if (!sp) return hipSuccess;
@@ -406,11 +474,14 @@ hipError_t sphere_set_wavenumbers(pstd_solver* s, int nk) {
     if (!sp || nk < 1) return hipErrorInvalidValue;
     (void)hipFree(sp->sum);
     (void)hipFree(sp->comp);
+    (void)hipFree(sp->stage);
     sp->sum = sp->comp = nullptr;
+    sp->stage = nullptr;
     sp->nk = nk;
     const size_t b = nk * sp->n_shell * sizeof(double2);
     hipError_t e = hipMalloc(&sp->sum, b);
     if (e == hipSuccess) e = hipMalloc(&sp->comp, b);
+    if (e == hipSuccess) e = hipMalloc(&sp->stage, kStageSteps * sp->n_shell * sizeof(float2));
     if (e == hipSuccess) e = hipMemset(sp->sum, 0, b);
     if (e == hipSuccess) e = hipMemset(sp->comp, 0, b);
     return e;
