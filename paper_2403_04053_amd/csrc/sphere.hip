@@ -102,16 +102,15 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 }
 
 // Eq. psiphasor on the shell cells for `count` (1 or 2) consecutive steps
-// ending at ctr[0] + koff, each with its own weight and window flag, for
-// each of nk wavenumbers (weights w_tab[f * wstride + step]).  Run before
-// that step's passes, when both psi^{n-1} and psi^n are in place, so a pair
-// of steps costs one read-modify-write of the FP64 sums; the terms are added
-// in step order, as one launch per step would.
+// ending at ctr[0] + koff, each with its own weight and window flag.  Run
+// before that step's z pass, when both psi^{n-1} and psi^n are in place, so
+// a pair of steps costs one read-modify-write of the FP64 sums; the terms
+// are added in step order, as one launch per step would.  One wavenumber
+// (a pulsed run's several go through the staged path below).
 __global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int count, const int* __restrict__ dft_tab,
-                                 const double2* __restrict__ w_tab, int64_t wstride, int nk,
-                                 const float2* __restrict__ buf0, const float2* __restrict__ buf1,
-                                 const int* __restrict__ list, int64_t n, double2* __restrict__ sum,
-                                 double2* __restrict__ comp) {
+                                 const double2* __restrict__ w_tab, const float2* __restrict__ buf0,
+                                 const float2* __restrict__ buf1, const int* __restrict__ list, int64_t n,
+                                 double2* __restrict__ sum, double2* __restrict__ comp) {
     const int64_t last = ctr[0] + koff;
     const int64_t first = last - (count - 1);
     bool any = false;
@@ -120,21 +119,17 @@ __global__ void shell_dft_kernel(const int64_t* __restrict__ ctr, int koff, int 
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const int cell = list[c];
-    float2 x[2];
-    for (int64_t m = first; m <= last; ++m) x[m - first] = ((m & 1) ? buf1 : buf0)[cell];
-    for (int f = 0; f < nk; ++f) {
-        double2 s = sum[f * n + c], e = comp[f * n + c];
-        for (int64_t m = first; m <= last; ++m) {
-            if (m >= ctr[1] || !dft_tab[m]) continue;
-            const float2 v = x[m - first];
-            const double2 w = w_tab[f * wstride + m];
-            const double zr = w.x * v.x - w.y * v.y, zi = w.x * v.y + w.y * v.x;
-            neumaier(s.x, e.x, zr);
-            neumaier(s.y, e.y, zi);
-        }
-        sum[f * n + c] = s;
-        comp[f * n + c] = e;
+    double2 s = sum[c], e = comp[c];
+    for (int64_t m = first; m <= last; ++m) {
+        if (m >= ctr[1] || !dft_tab[m]) continue;
+        const float2 x = ((m & 1) ? buf1 : buf0)[cell];
+        const double2 w = w_tab[m];
+        const double zr = w.x * x.x - w.y * x.y, zi = w.x * x.y + w.y * x.x;
+        neumaier(s.x, e.x, zr);
+        neumaier(s.y, e.y, zi);
     }
+    sum[c] = s;
+    comp[c] = e;
 }
 
 // psi^n on the shell cells into slot koff of the ring, n = ctr[0] + koff,
@@ -427,9 +422,10 @@ hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStrea
     const SphereState* sp = s->sphere;
     if (!sp || sp->n_shell == 0 || count < 1) return hipSuccess;
     if (count > 2 || koff < count - 1) return hipErrorInvalidValue;
+    if (sp->nk != 1) return hipErrorInvalidValue;  // several wavenumbers are staged
     hipLaunchKernelGGL(shell_dft_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
-                       koff, count, s->dft_tab, s->w_tab, s->tab_cap, sp->nk, s->buf[0], s->buf[1], sp->list,
-                       sp->n_shell, sp->sum, sp->comp);
+                       koff, count, s->dft_tab, s->w_tab, s->buf[0], s->buf[1], sp->list, sp->n_shell, sp->sum,
+                       sp->comp);
     return hipGetLastError();
 }
 
