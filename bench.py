@@ -449,7 +449,8 @@ def bench_pulse(args):
                                "(k0, width 6), sphere r=5.6 (64x128 nodes), phasors at k/k0 = 0.8, 0.9, 1.0, 1.1, 1.2",
                    "cells": cells},
         "roofline": {"bound": "hbm", "kernel": "pass_z", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(tuple(tune[2]), 2) if args.n == 160 else None,
                      "bytes_per_cell": PASS_BYTES["z"], "kernel_us": round(us, 3),
                      "pass_ms_in_steps": {k: round(v, 5) for k, v in avg.items()}},
         "solve": {"pulsed_s": round(t_pulse, 3), "pulsed_steps": solve_steps, "wavenumbers": len(kb),
