@@ -43,6 +43,13 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/cs
                   "paper_2403_04053_amd/csrc/internal.hpp")
 
 
+# The shell DFT of the spherical surface (r = 5, 64 x 128 nodes) on the same
+# workload, per launch of a pair of steps, valid for the sphere sources whose
+# SHA-256 is SHELL_TRAFFIC_SRC_SHA256.
+SHELL_TRAFFIC_SRC_SHA256 = "e72486ae279ce183bc74b442534e415d72cffb5948888930814aa55a08dbc351"
+SHELL_TRAFFIC_KIB = (18327, 10505)
+SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
+
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
 FDTD_TRAFFIC_SRC_SHA256 = "7825d7f1ac9ccc0640185d81bdffc54c42ccec0ea9a958feb4a216825ece6442"
@@ -67,6 +74,23 @@ def measured_traffic(tile, axis):
         return None
     kib = TRAFFIC_KIB.get((*tile, axis))
     return None if kib is None else 1024 * (kib[0] + kib[1])
+
+
+def measured_step_traffic(tiles, sphere):
+    """HBM bytes of one step (the three passes in the chosen tiles, plus half
+    a pair of shell-DFT steps with the sphere) from the measured counters, or
+    None when any of them is not measured for these sources."""
+    total = 0
+    for axis in range(3):
+        t = measured_traffic(tuple(tiles[axis]), axis)
+        if t is None:
+            return None
+        total += t
+    if sphere:
+        if SHELL_TRAFFIC_SRC_SHA256 is None or kernel_src_sha256(SHELL_SOURCES) != SHELL_TRAFFIC_SRC_SHA256:
+            return None
+        total += 1024 * (SHELL_TRAFFIC_KIB[0] + SHELL_TRAFFIC_KIB[1]) / 2
+    return int(total)
 
 
 def measured_fdtd_traffic(n):
@@ -158,6 +182,7 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
+    step_traffic = measured_step_traffic(tiles, args.surface == "sphere") if args.n == 160 else None
     gcells = cells * args.steps / (ms / 1e3) / 1e9
 
     # per-pass kernel durations, HIP events on the solver's stream
@@ -206,6 +231,9 @@ def main():
             "pass_ms_in_steps": {k: round(v, 5) for k, v in avg.items()},
             "tiles": {k: list(tiles[i]) for i, k in enumerate("xyz")},
             "step_frac_28B": round(STEP_BYTES * cells / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step_traffic": step_traffic,
+            "step_frac_measured": (round(step_traffic / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                   if step_traffic else None),
         },
         "wall_s": round(wall, 4),
         "finite": finite,
