@@ -342,7 +342,14 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     }
     pulse_free(s->pulse);
     s->pulse = ps;
-    if ((e = sphere_set_wavenumbers(s, nk))) return solver_hip_fail(s, e, "phasor sums");
+    if ((e = sphere_set_wavenumbers(s, nk))) {
+        // leave the solver as it was created: no pulse, one wavenumber
+        pulse_free(s->pulse);
+        s->pulse = nullptr;
+        (void)sphere_set_wavenumbers(s, 1);
+        sphere_drop_stage(s);
+        return solver_hip_fail(s, e, "phasor sums");
+    }
     // rebuild the per-step tables: no monochromatic source, one DFT weight row per wavenumber
     const int64_t cap = std::max<int64_t>(s->tab_cap, 1024);
     s->tab_cap = 0;

@@ -112,6 +112,7 @@ hipError_t sphere_far_field(pstd_solver* s, const SphereOut& o, const double3* d
 constexpr int kStageSteps = 16;  // steps per launch group at most
 hipError_t sphere_set_wavenumbers(pstd_solver* s, int nk);
 bool sphere_staged(const pstd_solver* s);
+void sphere_drop_stage(pstd_solver* s);
 hipError_t sphere_launch_stage(const pstd_solver* s, int koff, hipStream_t stream);
 hipError_t sphere_launch_flush(const pstd_solver* s, int count, hipStream_t stream);
 // the shell list and the ring (null without staging) for a fused launch

@@ -431,6 +431,12 @@ hipError_t sphere_launch_dft(const pstd_solver* s, int koff, int count, hipStrea
 
 bool sphere_staged(const pstd_solver* s) { return s->sphere && s->sphere->stage; }
 
+void sphere_drop_stage(pstd_solver* s) {
+    if (!s->sphere) return;
+    (void)hipFree(s->sphere->stage);
+    s->sphere->stage = nullptr;
+}
+
 void sphere_stage_buffers(const pstd_solver* s, const int** list, int64_t* n_shell, float2** stage) {
     const SphereState* sp = s->sphere;
     *list = sp ? sp->list : nullptr;
