@@ -88,6 +88,27 @@ def test_pulse_phasors_match_oracle(P, small):
         assert np.abs(gf - rf).max() <= 1e-10 * np.abs(rf).max()
 
 
+@pytest.mark.parametrize("theta,phi", [(2.3, 4.0), (1.2, 5.5)])
+def test_pulse_other_octants_match_oracle(P, theta, phi):
+    """Incidence from two more octants (the origin corner of Eq. Oinc and
+    the axis coordinate change with the signs of k_hat): 150 steps, psi
+    against the oracle."""
+    prob, V, psi0, delta = small_problem(steps=150)
+    prob = prob.replace(theta=theta, phi=phi, dft_end=0)
+    print(f"pulse, theta {theta} phi {phi}: grid {prob.n}, {prob.n_steps} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.set_pulse(psi0, delta, KB)
+    s.run(prob.n_steps)
+    got = s.psi(0).cpu().numpy()
+    s.close()
+    _, _, ref, _ = opulse.run(prob, V, psi0, delta)
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"  psi rel-L2 {rel:.2e}, max|psi| {np.abs(ref).max():.3f}", flush=True)
+    assert np.abs(ref).max() > 0.01
+    assert rel < 1e-4
+
+
 def test_pulse_split_runs_are_bit_identical(P):
     prob, V, psi0, delta = small_problem(steps=60)
     out = []
