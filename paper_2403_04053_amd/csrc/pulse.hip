@@ -56,6 +56,7 @@ namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kLag = 8;
+constexpr int kModeChunk = 256;
 
 // in-place radix-2 DFT, forward (e^{-i 2 pi l j / N}), N a power of two
 void fft_pow2(std::vector<std::complex<double>>& a) {
@@ -80,9 +81,9 @@ void fft_pow2(std::vector<std::complex<double>>& a) {
 
 // T0(d_j) = sum_l a_l(n) e^{i k_l d_j}, T1(d_j) = sum_l a_l(n) k_l e^{i k_l d_j}
 // for the table points of step n = ctr[0] + koff.  One wave per table point:
-// its 64 lanes take every 64th mode (a_l(n) from one FP64 sincos, e^{i k_l
-// d_j} from the precomputed table), then the wave adds the lane sums in a
-// fixed order.  Blocks past the table's stage psi^n on the sphere's shell
+// its 64 lanes take every 64th mode (a_l(n) shared by the block's four
+// points through LDS, e^{i k_l d_j} from the precomputed table), then the
+// wave adds the lane sums in a fixed order.  Blocks past the table's stage psi^n on the sphere's shell
 // into slot koff of the ring (same launch: both only read the state before
 // the step).
 __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restrict__ ctr, int koff, int K,
@@ -100,24 +101,33 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
         if (c < n_shell) stage[koff * n_shell + c] = ((n & 1) ? buf1 : buf0)[list[c]];
         return;
     }
+    // the step's mode amplitudes a_l(n) = c_l e^{-i theta_l n}, once per
+    // block in LDS (chunks of kModeChunk modes); every wave of a table block
+    // takes part in the barriers, those past the table's end store nothing
+    __shared__ double2 a_s[kModeChunk];
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (j >= J) return;  // whole waves
+    const double2* e_j = ekd + (int64_t)min(j, J - 1) * K;
     double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
-    const double2* e_j = ekd + (int64_t)j * K;
-    for (int l = lane; l < K; l += 64) {
-        double sn, cs;
-        sincos(theta[l] * (double)n, &sn, &cs);
-        const double2 e = e_j[l];
-        // c e^{i (k d - theta n)}
-        const double er = e.x * cs + e.y * sn, ei = e.y * cs - e.x * sn;
-        const double2 c = coef[l];
-        const double tr = c.x * er - c.y * ei, ti = c.x * ei + c.y * er;
-        const double kl = k_lo + l * dk;
-        s0r += tr;
-        s0i += ti;
-        s1r += kl * tr;
-        s1i += kl * ti;
+    for (int m0 = 0; m0 < K; m0 += kModeChunk) {
+        const int nm = min(kModeChunk, K - m0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nm; e += blockDim.x) {
+            double sn, cs;
+            sincos(theta[m0 + e] * (double)n, &sn, &cs);
+            const double2 c = coef[m0 + e];
+            a_s[e] = make_double2(c.x * cs + c.y * sn, c.y * cs - c.x * sn);
+        }
+        __syncthreads();
+        for (int l = lane; l < nm; l += 64) {
+            const double2 a = a_s[l], e = e_j[m0 + l];
+            const double tr = a.x * e.x - a.y * e.y, ti = a.x * e.y + a.y * e.x;
+            const double kl = k_lo + (m0 + l) * dk;
+            s0r += tr;
+            s0i += ti;
+            s1r += kl * tr;
+            s1i += kl * ti;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         s0r += __shfl_xor(s0r, off);
@@ -125,7 +135,7 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
         s1r += __shfl_xor(s1r, off);
         s1i += __shfl_xor(s1i, off);
     }
-    if (lane == 0) {
+    if (lane == 0 && j < J) {
         tab[j] = make_double2(s0r, s0i);
         tab[J + j] = make_double2(s1r, s1i);
     }
