@@ -170,8 +170,9 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms_host
 
 /* Pick, for each axis pass, the fastest compiled tile shape (FFT factor
  * order N1 x N2 and pencils per workgroup) by timing `reps` launches of every
- * candidate on scratch buffers of the solver's size; the solver's state is
- * not touched.  Candidates are tried in compiled order and a later one
+ * candidate on scratch buffers of the solver's size, in two rounds (each
+ * candidate keeps the faster of its two timings); the solver's state is
+ * not touched.  Candidates are compared in compiled order and a later one
  * replaces the current choice only when it is at least 3 % faster, so timing
  * noise does not flip the choice between runs.  Also captures the step graph
  * of the chosen shapes, so that the next pstd_run does not.  Synchronises.
