@@ -487,6 +487,8 @@ def bench_pulse(args):
                   "wavenumbers_per_s_monochromatic": round(1 / t_cw, 3)},
         "finite": finite,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_pulse(prob, V, psi0, delta)
     print(json.dumps(out), flush=True)
 
 
@@ -588,6 +590,8 @@ def bench_fdtd(args):
                      "kernel_us": round(us, 3)},
         "finite": finite,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_fdtd(prob, V)
     print(json.dumps(out), flush=True)
 
 
@@ -745,21 +749,73 @@ def cpu_baseline(prob, V):
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: one full step of the 160^3 grid."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import pstd as opstd
     import synth
     m = opstd.build(prob, V)
     prev = np.zeros((prob.n[2], prob.n[1], prob.n[0]), np.complex128)
     cur = synth.random_state(prob.n, 1)
-    t0 = time.perf_counter()
-    opstd.step(m, prev, cur, 100)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(1):  # the library calls inside numpy stay on one thread
+        t0 = time.perf_counter()
+        opstd.step(m, prev, cur, 100)
+        dt = time.perf_counter() - t0
     return {
         "value": round(prob.cells / dt / 1e9, 6),
         "unit": "Gcell-updates/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"1 leapfrog step of the {prob.n[0]}^3 grid (FP64 numpy, library-free Bluestein/radix-2 FFT, "
+                  f"single-threaded; host has {os.cpu_count()} logical CPUs), {dt:.2f} s",
+    }
+
+
+def cpu_baseline_fdtd(prob, V):
+    """The FDTD-variant oracle, as it stands, on one full step of the grid."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fdtd as ofdtd
+    import synth
+    m = ofdtd.build(prob, V)
+    prev = np.zeros((prob.n[2], prob.n[1], prob.n[0]), np.complex128)
+    cur = synth.random_state(prob.n, 1)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ofdtd.step(m, prev, cur, 100)
+        dt = time.perf_counter() - t0
+    return {
+        "value": round(prob.cells / dt / 1e9, 6),
+        "unit": "Gcell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"1 FDTD-8 step of the {prob.n[0]}^3 grid (FP64 numpy, single-threaded; host has "
+                  f"{os.cpu_count()} logical CPUs), {dt:.2f} s",
+    }
+
+
+def cpu_baseline_pulse(prob, V, psi0, delta):
+    """The pulsed-incidence oracle, as it stands, on one full step of the grid
+    (the 1D packet's step, its deployment to the layer and the 3D step)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pulse as opulse
+    import synth
+    pm = opulse.PulseModel(prob, V, psi0, delta)
+    prev = np.zeros((prob.n[2], prob.n[1], prob.n[0]), np.complex128)
+    cur = synth.random_state(prob.n, 1)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pm.step(prev, cur, 100)
+        pm.pulse.step()
+        dt = time.perf_counter() - t0
+    return {
+        "value": round(prob.cells / dt / 1e9, 6),
+        "unit": "Gcell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"1 pulsed leapfrog step of the {prob.n[0]}^3 grid (FP64 numpy, library-free FFT, "
                   f"single-threaded; host has {os.cpu_count()} logical CPUs), {dt:.2f} s",
     }
 
