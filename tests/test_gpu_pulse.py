@@ -151,11 +151,12 @@ def test_pulse_validation(P):
         s.save_state()
     assert e.value.name == "PSTD_EUNSUPPORTED"
     s.close()
-    for bad in (dict(surface_kind=0), dict(sphere_radius=1.2)):  # 1.2: the shell reaches the taper
+    for bad, name in ((dict(surface_kind=0), "PSTD_EUNSUPPORTED"), (dict(scheme=1), "PSTD_EUNSUPPORTED"),
+                      (dict(sphere_radius=1.2), "PSTD_EINVAL")):  # 1.2: the shell reaches the taper
         s = P.Solver(prob.replace(**bad))
         with pytest.raises(P.PstdError) as e:
             s.set_pulse(psi0, delta, KB)
-        assert e.value.name == ("PSTD_EUNSUPPORTED" if "surface_kind" in bad else "PSTD_EINVAL"), bad
+        assert e.value.name == name, bad
         s.close()
 
 
