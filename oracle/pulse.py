@@ -157,14 +157,57 @@ class MultiShellDFT:
         return out
 
 
-def run(prob, V, psi0, delta, n_steps=None, sphere=None, kbars=()):
-    """March from rest with the pulse; with a sphere, the phasors at the
-    wavenumbers kbars over [dft_begin, dft_end)."""
+class MultiSurfaceDFT:
+    """Eqs. psiphasor and dpsiphasor on the six box planes (values and the
+    spectral normal derivative) at several wavenumbers, and Eq.
+    incpsiphasor at the grid origin for each.  The planes must lie where
+    the taper is zero (at or outside the taper box), so nothing is
+    removed."""
+
+    def __init__(self, pm, kbars):
+        p = pm.m.prob
+        for a in range(3):
+            if not (p.surf_lo[a] <= p.tfsf[a][0] and p.surf_hi[a] >= p.tfsf[a][3]):
+                raise ValueError("a box plane reaches the taper")
+        self.pm = pm
+        self.k = np.asarray(kbars, dtype=np.float64)
+        self.W = scheme_frequency(self.k, pm.m.dtau, pm.m.eta)
+        shapes = [_pstd.plane(pm.m.v, _pstd.FACES[f][0], 0).shape for f in range(6)]
+        self.phi = [[np.zeros(sh, np.complex128) for sh in shapes] for _ in self.k]
+        self.dphi = [[np.zeros(sh, np.complex128) for sh in shapes] for _ in self.k]
+        self.inc = np.zeros(self.k.size, np.complex128)
+
+    def accumulate(self, psi, n):
+        m = self.pm.m
+        w = np.exp(1j * self.W * n * m.dtau)
+        ders = [_pstd.derivative(m, psi, a) for a in range(3)]
+        for f in range(6):
+            a, _ = _pstd.FACES[f]
+            idx = _pstd.face_index(m.prob, f)
+            v = _pstd.plane(psi, a, idx)
+            d = _pstd.plane(ders[a], a, idx)
+            for q in range(self.k.size):
+                self.phi[q][f] += w[q] * v
+                self.dphi[q][f] += w[q] * d
+        p0, _ = self.pm.pulse.at(np.array([self.pm.d_origin]))
+        self.inc += w * p0[0]
+
+    def normalized(self, q):
+        return [x / self.inc[q] for x in self.phi[q]], [x / self.inc[q] for x in self.dphi[q]]
+
+
+def run(prob, V, psi0, delta, n_steps=None, sphere=None, kbars=(), box=False):
+    """March from rest with the pulse; with a sphere (or box=True, the box
+    planes), the phasors at the wavenumbers kbars over [dft_begin,
+    dft_end)."""
     pm = PulseModel(prob, V, psi0, delta)
     n_steps = prob.n_steps if n_steps is None else n_steps
     prev = np.zeros(pm.m.v.shape, np.complex128)
     cur = np.zeros(pm.m.v.shape, np.complex128)
-    sd = MultiShellDFT(pm, sphere, kbars) if sphere is not None else None
+    if box:
+        sd = MultiSurfaceDFT(pm, kbars)
+    else:
+        sd = MultiShellDFT(pm, sphere, kbars) if sphere is not None else None
     for n in range(n_steps):
         if sd is not None and prob.dft_begin <= n < prob.dft_end:
             sd.accumulate(cur, n)

@@ -100,6 +100,14 @@ def test_single_mode_pulse_is_the_monochromatic_run():
     got = sd.normalized(0)[mask]
     want = cw[mask] / 60.0
     assert np.abs(got - want).max() < 1e-11 * np.abs(want).max()
+    # and on the box planes (values and normal derivatives)
+    _, _, _, bd = pulse.run(prob, V, psi0, delta, kbars=[1.0], box=True)
+    _, _, _, cwd = pstd.run(prob, V)
+    got_p, got_d = bd.normalized(0)
+    want_p, want_d = cwd.normalized()
+    for f in range(6):
+        assert np.abs(got_p[f] - want_p[f]).max() < 1e-11 * np.abs(want_p[f]).max()
+        assert np.abs(got_d[f] - want_d[f]).max() < 1e-11 * np.abs(want_d[f]).max()
 
 
 def test_pulse_without_potential_crosses_the_box():
