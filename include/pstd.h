@@ -291,9 +291,16 @@ pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir,
  * phasor at the grid origin (the DFT of the packet there over the same
  * steps); the _k outputs below project it with G = exp(i kbar R)/(4 pi R).
  *
- * Requires the spectral scheme, the spherical surface (surface_kind 1) with
- * its interpolation shell where the taper is zero, no subdomains and no
- * batch (EUNSUPPORTED otherwise); call before the first step (ESTATE).
+ * With the box surface (surface_kind 0) the passes stage the plane values of
+ * each launch group of steps and one flush per group adds them to a set of
+ * plane sums per wavenumber; the box projection of wavenumber k is the
+ * central wave's in units rescaled by k (k0 -> k k0, dxb -> k dxb).
+ *
+ * Requires the spectral scheme, an equivalence surface where the taper is
+ * zero (box planes at or outside the taper box; or the sphere's
+ * interpolation shell), no subdomains and no batch (EUNSUPPORTED
+ * otherwise; the misfit refuses a pulsed solver); call before the first
+ * step (ESTATE).
  * EINVAL: n1d not a power of two in [8, 2^20], delta <= 0, n_k outside
  * [1, 64], a wavenumber <= 0 or beyond the step bound, the 1D grid's
  * Nyquist mode beyond the step bound, a non-finite or zero packet, a
@@ -303,9 +310,12 @@ pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir,
 pstd_status pstd_set_pulse(pstd_solver* s, const double* psi0_host, int32_t n1d, double delta,
                            const double* kbar_host, int32_t n_k);
 
-/* pstd_get_sphere_phasors, pstd_project and pstd_far_field for the phasors
- * of wavenumber index ik of a pulsed run (the plain calls read index 0;
- * without a pulse ik must be 0).  EINVAL for an index out of range. */
+/* pstd_get_surface_phasors, pstd_get_sphere_phasors, pstd_project and
+ * pstd_far_field for the phasors of wavenumber index ik of a pulsed run (the
+ * plain calls read index 0; without a pulse ik must be 0).  The box
+ * phasors' derivatives are per reduced length of the grid, as for the
+ * central wave.  EINVAL for an index out of range. */
+pstd_status pstd_get_surface_phasors_k(pstd_solver* s, int32_t ik, double* out_dev, int64_t n);
 pstd_status pstd_get_sphere_phasors_k(pstd_solver* s, int32_t ik, double* out_dev, int64_t n);
 pstd_status pstd_project_k(pstd_solver* s, int32_t ik, const double* obs_xyz_dev, int64_t n_obs,
                            double* psi_out_dev);

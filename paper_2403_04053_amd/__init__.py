@@ -15,7 +15,7 @@ __all__ = [
     "pstd_problem_init_defaults", "pstd_critical_dt", "pstd_reduced_step", "pstd_create",
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
-    "pstd_far_field", "pstd_set_pulse", "pstd_get_sphere_phasors_k", "pstd_project_k", "pstd_far_field_k",
+    "pstd_far_field", "pstd_set_pulse", "pstd_get_surface_phasors_k", "pstd_get_sphere_phasors_k", "pstd_project_k", "pstd_far_field_k",
     "pstd_pass_time", "pstd_check_state", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
@@ -137,6 +137,7 @@ _SIGS = {
     "pstd_far_field": [_vp, _vp, _i64, _vp],
     "pstd_set_pulse": [_vp, _vp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_int32],
     "pstd_get_sphere_phasors_k": [_vp, ctypes.c_int32, _vp, _i64],
+    "pstd_get_surface_phasors_k": [_vp, ctypes.c_int32, _vp, _i64],
     "pstd_project_k": [_vp, ctypes.c_int32, _vp, _i64, _vp],
     "pstd_far_field_k": [_vp, ctypes.c_int32, _vp, _i64, _vp],
     "pstd_misfit_forward": [_vp, _i64, _vp, _i64, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
@@ -284,6 +285,10 @@ def pstd_set_pulse(solver, psi0, delta, kbars):
     k = np.ascontiguousarray(np.asarray(kbars, dtype=np.float64))
     _check(lib.pstd_set_pulse(solver, p.ctypes.data_as(_vp), int(p.size), float(delta),
                               k.ctypes.data_as(_vp), int(k.size)), solver)
+
+
+def pstd_get_surface_phasors_k(solver, ik, out_dev, n):
+    _check(lib.pstd_get_surface_phasors_k(solver, int(ik), _ptr(out_dev), int(n)), solver)
 
 
 def pstd_get_sphere_phasors_k(solver, ik, out_dev, n):
@@ -488,10 +493,12 @@ class Solver:
         pstd_get_psi(self.handle, level, out, self.cells)
         return out
 
-    def phasors(self):
+    def phasors(self, ik=0):
+        """Normalised box phasors (flat complex128 CUDA tensor); ik selects a
+        pulsed run's wavenumber."""
         n = pstd_surface_size(self.handle)
         out = self.torch.empty(n, dtype=self.torch.complex128, device=self.device)
-        pstd_get_surface_phasors(self.handle, out, n)
+        pstd_get_surface_phasors_k(self.handle, ik, out, n)
         return out
 
     def split_phasors(self, flat):

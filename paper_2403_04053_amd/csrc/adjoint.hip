@@ -249,6 +249,7 @@ pstd_status pstd_misfit_forward(pstd_solver* s, int64_t n_steps, const double* o
         return fail(s, PSTD_EUNSUPPORTED, "the adjoint runs on whole-axis pencils only");
     if (s->sphere) return fail(s, PSTD_EUNSUPPORTED, "the misfit projects from the box surface only");
     if (s->prob.scheme != 0) return fail(s, PSTD_EUNSUPPORTED, "the misfit runs the spectral scheme only");
+    if (s->pulse) return fail(s, PSTD_EUNSUPPORTED, "the misfit takes the monochromatic wave only");
     if (std::min<int64_t>(s->prob.dft_end, n_steps) <= s->prob.dft_begin)
         return fail(s, PSTD_EINVAL, "no step of the DFT window lies in [0, n_steps)");
     const int64_t S = (n_steps + n_checkpoints - 1) / n_checkpoints;

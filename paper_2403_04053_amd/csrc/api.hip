@@ -392,6 +392,11 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
         hipError_t e = pstd::pulse_launch_source(s, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pulse source launch");
     }
+    if (s->pulse && koff == count - 1) {
+        // a pulsed run on the box: the group's staged plane values into the sums
+        hipError_t e = pstd::pulse_launch_box_flush(s, count, stream);
+        if (e != hipSuccess) return hip_fail(s, e, "plane flush launch");
+    }
     if (pstd::sphere_staged(s) && koff == count - 1) {
         // the group's staged steps into the phasor sums (before the counter advances)
         hipError_t e = pstd::sphere_launch_flush(s, count, stream);
@@ -481,6 +486,7 @@ void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
     a.seg_halo = seg ? p.sub_halo : 0;
     a.nseg = seg ? p.n[axis] / p.sub_core[axis] : 1;
     a.wloc = s->wloc[axis];
+    a.bstage = pulse_box_stage(s, axis);
     variant_tiles(s->variant[axis], axis, a);
 }
 
@@ -1082,16 +1088,28 @@ pstd_status pstd_surface_size(const pstd_solver* s, int64_t* n_out) {
     return PSTD_OK;
 }
 
-pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+pstd_status pstd_get_surface_phasors_k(pstd_solver* s, int32_t ik, double* out_dev, int64_t n) {
     if (!s || !out_dev) return PSTD_EINVAL;
     int64_t need;
     pstd_surface_size(s, &need);
     if (n != need) return fail(s, PSTD_EINVAL, "output size must equal pstd_surface_size");
     if (s->sphere) return fail(s, PSTD_ESTATE, "the problem integrates over the sphere (pstd_get_sphere_phasors)");
-    if (!(s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
-    hipError_t e = finalize_phasors(s->acc, s->points, 1.0 / s->inc_sum, (double2*)out_dev, s->stream);
+    if (!(s->pulse ? s->win_steps > 0 : s->inc_sum > 0)) return fail(s, PSTD_ESTATE, "no step of the DFT window has run");
+    hipError_t e;
+    if (s->pulse) {
+        BoxOut o;
+        if (pstd_status st = pulse_box_output(s, ik, false, &o)) return st;
+        e = finalize_phasors(o.acc, s->points, o.scale, (double2*)out_dev, s->stream);
+    } else {
+        if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
+        e = finalize_phasors(s->acc, s->points, real_scale(1.0 / s->inc_sum), (double2*)out_dev, s->stream);
+    }
     if (e) return hip_fail(s, e, "finalize_phasors");
     return PSTD_OK;
+}
+
+pstd_status pstd_get_surface_phasors(pstd_solver* s, double* out_dev, int64_t n) {
+    return pstd_get_surface_phasors_k(s, 0, out_dev, n);
 }
 
 pstd_status pstd_sphere_size(const pstd_solver* s, int64_t* n_nodes_out) {
@@ -1142,9 +1160,17 @@ pstd_status pstd_project_k(pstd_solver* s, int32_t ik, const double* obs_dev, in
         if (e) return hip_fail(s, e, "sphere projection");
         return PSTD_OK;
     }
-    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
     std::string msg;
-    hipError_t e = project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
+    if (s->pulse) {
+        BoxOut o;
+        if (pstd_status st = pulse_box_output(s, ik, true, &o)) return st;
+        hipError_t e = project_points(o.proj, o.prob, o.dxb, o.acc, s->points, o.scale, (const double3*)obs_dev, n_obs,
+                                      (double2*)out_dev, s->stream, &msg);
+        if (e) return msg.empty() ? hip_fail(s, e, "project") : fail(s, PSTD_EINVAL, msg);
+        return PSTD_OK;
+    }
+    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
+    hipError_t e = project_points(&s->proj, s->prob, s->dxb, s->acc, s->points, real_scale(1.0 / s->inc_sum),
                                   (const double3*)obs_dev, n_obs, (double2*)out_dev, s->stream, &msg);
     if (e) return msg.empty() ? hip_fail(s, e, "project") : fail(s, PSTD_EINVAL, msg);
     return PSTD_OK;
@@ -1165,9 +1191,17 @@ pstd_status pstd_far_field_k(pstd_solver* s, int32_t ik, const double* dir_dev, 
         if (e) return hip_fail(s, e, "sphere far field");
         return PSTD_OK;
     }
-    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
     std::string msg;
-    hipError_t e = far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, 1.0 / s->inc_sum,
+    if (s->pulse) {
+        BoxOut o;
+        if (pstd_status st = pulse_box_output(s, ik, true, &o)) return st;
+        hipError_t e = far_field(o.proj, o.prob, o.dxb, o.acc, s->points, o.scale, (const double3*)dir_dev, n_dir,
+                                 (double2*)out_dev, s->stream, &msg);
+        if (e) return msg.empty() ? hip_fail(s, e, "far_field") : fail(s, PSTD_EINVAL, msg);
+        return PSTD_OK;
+    }
+    if (ik != 0) return fail(s, PSTD_EINVAL, "without a pulse the only wavenumber index is 0");
+    hipError_t e = far_field(&s->proj, s->prob, s->dxb, s->acc, s->points, real_scale(1.0 / s->inc_sum),
                              (const double3*)dir_dev, n_dir, (double2*)out_dev, s->stream, &msg);
     if (e) return msg.empty() ? hip_fail(s, e, "far_field") : fail(s, PSTD_EINVAL, msg);
     return PSTD_OK;

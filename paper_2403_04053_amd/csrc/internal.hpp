@@ -35,6 +35,8 @@ struct PassArgs {
     const int* dft_tab;        // per step: 1 inside the surface-DFT window
     int plane_lo, plane_hi;    // plane indices along this pass's axis (local in segmented mode)
     double2* acc;              // [2 sides][4: sum psi, comp psi, sum dpsi, comp dpsi][points]
+    float2* bstage;            // null, or (pulsed runs) [group step][2 sides][psi, dpsi][points]: the
+                               // plane values are staged there instead of added to acc
     int64_t points;            // points of one plane of this axis
     // overlapping-subdomain mode along this pass's axis (Section 2.6)
     int seg_core, seg_halo, nseg;

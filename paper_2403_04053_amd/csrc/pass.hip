@@ -71,6 +71,7 @@ struct Fields {
     GMEM const int* dft_tab;
     int plane_lo, plane_hi, seg_plane0, seg_plane1;
     GMEM double2* acc;
+    GMEM float2* bstage;
     int64_t points;
     int seg_core, seg_halo, nseg;
     GMEM const float* wloc;
@@ -113,6 +114,7 @@ __device__ __forceinline__ Fields fields(const PassArgs& a) {
     f.seg_plane0 = a.seg_plane[0];
     f.seg_plane1 = a.seg_plane[1];
     f.acc = gmem(a.acc);
+    f.bstage = gmem(a.bstage);
     f.points = a.points;
     f.seg_core = a.seg_core;
     f.seg_halo = a.seg_halo;
@@ -469,7 +471,12 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     const int x = geo.tx * P + p;
                     if (x < f.nx && geo.tq % nseg == segp) spt = x + (int64_t)f.nx * (geo.tq / nseg);
                 }
-                if (spt >= 0) {
+                if (spt >= 0 && f.bstage) {
+                    // pulsed runs: stage the plane value of this step of the group
+                    float2 s = make_float2(0.f, 0.f);
+                    for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
+                    f.bstage[((int64_t)(koff * 2 + side) * 2 + (q >> 1)) * f.points + spt] = s;
+                } else if (spt >= 0) {
                     float2 s = make_float2(0.f, 0.f);
                     for (int m = 0; m < N2; ++m) s = cadd(s, ex[p * STRIDE + m * 4 + q]);
                     const double re = (double)s.x, im = (double)s.y;

@@ -46,14 +46,15 @@ __device__ __forceinline__ double dsinc(double x) { return fabs(x) < 1e-8 ? 1.0 
 // phasor finalisation
 // ---------------------------------------------------------------------------
 
-__global__ void finalize_kernel(const double2* __restrict__ acc, int side, int64_t points, double scale,
+__global__ void finalize_kernel(const double2* __restrict__ acc, int side, int64_t points, double2 sv, double2 sd,
                                 double2* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= points) return;
     const double2* base = acc + (int64_t)side * 4 * points;
     const double2 s0 = base[i], c0 = base[points + i], s1 = base[2 * points + i], c1 = base[3 * points + i];
-    out[i] = make_double2((s0.x + c0.x) * scale, (s0.y + c0.y) * scale);
-    out[points + i] = make_double2((s1.x + c1.x) * scale, (s1.y + c1.y) * scale);
+    const double ar = s0.x + c0.x, ai = s0.y + c0.y, br = s1.x + c1.x, bi = s1.y + c1.y;
+    out[i] = make_double2(ar * sv.x - ai * sv.y, ar * sv.y + ai * sv.x);
+    out[points + i] = make_double2(br * sd.x - bi * sd.y, br * sd.y + bi * sd.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,7 +495,7 @@ int split_count(int64_t waves, int64_t cap) {
     } while (0)
 
 hipError_t prepare(ProjectState** pst, const pstd_problem& p, double2* const acc[3], const int64_t points[3],
-                   double scale, hipStream_t stream) {
+                   PhasorScale scale, hipStream_t stream) {
     if (!*pst) {
         ProjectState* s = new ProjectState();
         int64_t off = 0;
@@ -548,14 +549,14 @@ hipError_t prepare(ProjectState** pst, const pstd_problem& p, double2* const acc
 
 }  // namespace
 
-hipError_t finalize_phasors(double2* const acc[3], const int64_t points[3], double scale, double2* out,
+hipError_t finalize_phasors(double2* const acc[3], const int64_t points[3], PhasorScale scale, double2* out,
                             hipStream_t stream) {
     int64_t off = 0;
     for (int f = 0; f < 6; ++f) {
         const int a = f / 2;
         const int64_t P = points[a];
         hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, acc[a], f % 2, P,
-                           scale, out + off);
+                           scale.v, scale.d, out + off);
         off += 2 * P;
     }
     return hipGetLastError();
@@ -633,7 +634,7 @@ hipError_t near_tables(ProjectState* s, const pstd_problem& p, const double dxb[
 }  // namespace
 
 hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
-                     const int64_t points[3], double scale, const double3* dirs, int64_t n_dir, double2* out,
+                     const int64_t points[3], PhasorScale scale, const double3* dirs, int64_t n_dir, double2* out,
                      hipStream_t stream, std::string* msg) {
     TRY(prepare(pst, p, acc, points, scale, stream));
     ProjectState* s = *pst;
@@ -680,7 +681,7 @@ hipError_t far_field(ProjectState** pst, const pstd_problem& p, const double dxb
 }
 
 hipError_t project_points(ProjectState** pst, const pstd_problem& p, const double dxb[3], double2* const acc[3],
-                          const int64_t points[3], double scale, const double3* obs, int64_t n_obs, double2* out,
+                          const int64_t points[3], PhasorScale scale, const double3* obs, int64_t n_obs, double2* out,
                           hipStream_t stream, std::string* msg) {
     // the cell formula holds outside the box only
     {
@@ -763,7 +764,7 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
                            const int64_t points[3], double scale, const double3* obs, int64_t n_obs, const double2* g,
                            float2* inj, hipStream_t stream, std::string* msg) {
     // the state (twiddles, offsets) is shared with the forward projection
-    TRY(prepare(pst, p, acc, points, 1.0, stream));
+    TRY(prepare(pst, p, acc, points, real_scale(1.0), stream));
     ProjectState* s = *pst;
     TRY(near_tables(s, p, dxb, true));
     const double2* twc[3] = {s->twc, s->twc + p.n[0], s->twc + p.n[0] + p.n[1]};

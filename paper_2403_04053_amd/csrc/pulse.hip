@@ -50,6 +50,12 @@ struct PulseState {
     std::vector<double2> g;             // c_l exp(i k_l d_origin)
     std::vector<double> theta_h;
     int64_t from = 0;                   // first step since creation or pstd_set_state
+    // box surface: the passes stage the plane values of a launch group, the
+    // flush adds them to one set of plane sums per wavenumber
+    bool box = false;
+    float2* bstage[3] = {nullptr, nullptr, nullptr};  // [group step][side][psi, dpsi][points]
+    double2* bacc[3] = {nullptr, nullptr, nullptr};   // [wavenumber][side][4][points], as PassArgs::acc
+    std::vector<ProjectState*> proj;                  // box projection per wavenumber
 };
 
 namespace {
@@ -57,6 +63,14 @@ namespace {
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kLag = 8;
 constexpr int kModeChunk = 256;
+
+// compensated (Neumaier) summation step
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
 
 // in-place radix-2 DFT, forward (e^{-i 2 pi l j / N}), N a power of two
 void fft_pow2(std::vector<std::complex<double>>& a) {
@@ -172,12 +186,46 @@ __global__ __launch_bounds__(256) void pulse_source_kernel(const int64_t* __rest
     out[cell[c]] = v;
 }
 
+// the staged plane values of the launch group's steps ctr[0] .. ctr[0] +
+// count - 1 into the FP64 plane sums of each wavenumber, in step order; one
+// thread per (side, field, plane point)
+__global__ void box_flush_kernel(const int64_t* __restrict__ ctr, int count, const int* __restrict__ dft_tab,
+                                 const double2* __restrict__ w_tab, int64_t wstride, int nk,
+                                 const float2* __restrict__ stage, int64_t points, double2* __restrict__ acc) {
+    const int64_t first = ctr[0];
+    bool any = false;
+    for (int k = 0; k < count; ++k) any |= first + k < ctr[1] && dft_tab[first + k] != 0;
+    if (!any) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * points) return;
+    const int sf = (int)(i / points);  // side * 2 + field
+    const int64_t pt = i % points;
+    const int side = sf >> 1, fld = sf & 1;
+    for (int f = 0; f < nk; ++f) {
+        double2* S = acc + ((int64_t)f * 8 + side * 4 + fld * 2) * points + pt;
+        double2* Cc = S + points;
+        double2 s = *S, c = *Cc;
+        for (int k = 0; k < count; ++k) {
+            const int64_t m = first + k;
+            if (m >= ctr[1] || !dft_tab[m]) continue;
+            const float2 v = stage[((int64_t)k * 4 + sf) * points + pt];
+            const double2 w = w_tab[f * wstride + m];
+            neumaier(s.x, c.x, w.x * v.x - w.y * v.y);
+            neumaier(s.y, c.y, w.x * v.y + w.y * v.x);
+        }
+        *S = s;
+        *Cc = c;
+    }
+}
+
 }  // namespace
 
 void pulse_free(PulseState* p) {
     if (!p) return;
-    void* ptrs[] = {p->coef, p->theta, p->tab, p->ekd, p->cell, p->j0, p->w, p->ab};
+    void* ptrs[] = {p->coef, p->theta, p->tab, p->ekd, p->cell, p->j0, p->w, p->ab,
+                    p->bstage[0], p->bstage[1], p->bstage[2], p->bacc[0], p->bacc[1], p->bacc[2]};
     for (void* q : ptrs) (void)hipFree(q);
+    for (ProjectState* q : p->proj) project_free(q);
     delete p;
 }
 
@@ -188,17 +236,20 @@ double pulse_frequency(const pstd_solver* s, int ik) { return s->pulse ? s->puls
 pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double delta, const double* kbar, int32_t nk) {
     const pstd_problem& p = s->prob;
     if (s->in_batch) return solver_fail(s, PSTD_EUNSUPPORTED, "batch instances take the monochromatic wave only");
-    if (p.scheme != 0 || p.surface_kind != 1 || p.sub_core[0] || p.sub_core[1] || p.sub_core[2])
-        return solver_fail(s, PSTD_EUNSUPPORTED,
-                           "pulsed incidence needs the spectral scheme, the spherical surface and no subdomains");
+    if (p.scheme != 0 || p.sub_core[0] || p.sub_core[1] || p.sub_core[2])
+        return solver_fail(s, PSTD_EUNSUPPORTED, "pulsed incidence needs the spectral scheme and no subdomains");
+    const bool box = p.surface_kind == 0;
     if (s->step != 0 || s->win_steps != 0) return solver_fail(s, PSTD_ESTATE, "set the pulse before the first step");
     if (!psi0 || !kbar) return solver_fail(s, PSTD_EINVAL, "null pulse or wavenumber array");
     if (n1d < 8 || n1d > (1 << 20) || (n1d & (n1d - 1)))
         return solver_fail(s, PSTD_EINVAL, "n1d must be a power of two in [8, 2^20]");
     if (!(delta > 0) || !std::isfinite(delta)) return solver_fail(s, PSTD_EINVAL, "delta must be positive");
     if (nk < 1 || nk > 64) return solver_fail(s, PSTD_EINVAL, "1 to 64 wavenumbers");
-    if (sphere_taper_max(s) != 0)
+    if (!box && sphere_taper_max(s) != 0)
         return solver_fail(s, PSTD_EINVAL, "the sphere's shell must lie where the taper is zero");
+    for (int a = 0; a < 3 && box; ++a)
+        if (!(p.surf_lo[a] <= p.tfsf[a][0] && p.surf_hi[a] >= p.tfsf[a][3]))
+            return solver_fail(s, PSTD_EINVAL, "the box planes must lie where the taper is zero");
     const double q = s->dtau * s->eta;
     const double knyq = kPi / delta;
     if (!(q * knyq * knyq < 1)) return solver_fail(s, PSTD_EINVAL, "the 1D grid's Nyquist mode exceeds the step bound");
@@ -343,6 +394,17 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
         return r;
     };
     hipError_t e;
+    ps->box = box;
+    ps->proj.assign(nk, nullptr);
+    for (int a = 0; a < 3 && box; ++a) {
+        const size_t sb = (size_t)kStageSteps * 4 * s->points[a] * sizeof(float2);
+        const size_t ab_ = (size_t)nk * 8 * s->points[a] * sizeof(double2);
+        if ((e = hipMalloc(&ps->bstage[a], sb)) || (e = hipMalloc(&ps->bacc[a], ab_)) ||
+            (e = hipMemset(ps->bacc[a], 0, ab_))) {
+            pulse_free(ps);
+            return solver_hip_fail(s, e, "pulse plane sums");
+        }
+    }
     if ((e = hipStreamSynchronize(s->stream)) || (e = up(&ps->coef, coef)) || (e = up(&ps->theta, ps->theta_h)) ||
         (e = hipMalloc(&ps->tab, 2 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->ekd, ekd)) ||
         (e = up(&ps->cell, cell)) ||
@@ -352,7 +414,7 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     }
     pulse_free(s->pulse);
     s->pulse = ps;
-    if ((e = sphere_set_wavenumbers(s, nk))) {
+    if (!box && (e = sphere_set_wavenumbers(s, nk))) {
         // leave the solver as it was created: no pulse, one wavenumber
         pulse_free(s->pulse);
         s->pulse = nullptr;
@@ -413,7 +475,49 @@ std::complex<double> incident_phasor(const pstd_solver* s, int f) {
 }  // namespace
 
 void pulse_reset(pstd_solver* s) {
-    if (s->pulse) s->pulse->from = s->step;
+    if (!s->pulse) return;
+    s->pulse->from = s->step;
+    for (int a = 0; a < 3; ++a)
+        if (s->pulse->bacc[a])
+            (void)hipMemset(s->pulse->bacc[a], 0, s->pulse->kbar.size() * 8 * s->points[a] * sizeof(double2));
+}
+
+float2* pulse_box_stage(const pstd_solver* s, int axis) { return s->pulse ? s->pulse->bstage[axis] : nullptr; }
+
+hipError_t pulse_launch_box_flush(const pstd_solver* s, int count, hipStream_t stream) {
+    const PulseState* ps = s->pulse;
+    if (!ps || !ps->box) return hipSuccess;
+    if (count < 1 || count > kStageSteps) return hipErrorInvalidValue;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t n = 4 * s->points[a];
+        hipLaunchKernelGGL(box_flush_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, s->ctr, count,
+                           s->dft_tab, s->w_tab, s->tab_cap, (int)ps->kbar.size(), ps->bstage[a], s->points[a],
+                           ps->bacc[a]);
+    }
+    return hipGetLastError();
+}
+
+pstd_status pulse_box_output(pstd_solver* s, int ik, bool rescaled, BoxOut* o) {
+    PulseState* ps = s->pulse;
+    if (!ps || !ps->box) return solver_fail(s, PSTD_ESTATE, "no pulsed run on the box surface");
+    if (ik < 0 || ik >= (int)ps->kbar.size()) return solver_fail(s, PSTD_EINVAL, "wavenumber index out of range");
+    const std::complex<double> inc = incident_phasor(s, ik);
+    const std::complex<double> inv = 1.0 / inc;
+    if (!(std::abs(inc) > 0) || !std::isfinite(inv.real()) || !std::isfinite(inv.imag()))
+        return solver_fail(s, PSTD_ESTATE, "the incident phasor of this wavenumber is zero");
+    // the phasors of wavenumber k are those of the central wave in units
+    // rescaled by k: k0 -> k k0, dxb -> k dxb, d/dxb -> (1/k) d/dxb
+    const double k = rescaled ? ps->kbar[ik] : 1.0;
+    o->prob = s->prob;
+    o->prob.k0 = s->prob.k0 * k;
+    for (int a = 0; a < 3; ++a) {
+        o->dxb[a] = s->dxb[a] * k;
+        o->acc[a] = ps->bacc[a] + (int64_t)ik * 8 * s->points[a];
+    }
+    const std::complex<double> d = inv / k;
+    o->scale = PhasorScale{make_double2(inv.real(), inv.imag()), make_double2(d.real(), d.imag())};
+    o->proj = &ps->proj[ik];
+    return PSTD_OK;
 }
 
 pstd_status pulse_output(pstd_solver* s, int ik, SphereOut* o) {

@@ -135,5 +135,18 @@ hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t strea
 void pulse_reset(pstd_solver* s);
 // the output of wavenumber ik
 pstd_status pulse_output(pstd_solver* s, int ik, SphereOut* o);
+// box surface: the staging ring of the pass along `axis` (null unless a
+// pulsed run integrates over the box), the group flush, and the inputs of the
+// box projection for wavenumber ik (rescaled: units of that wavenumber)
+float2* pulse_box_stage(const pstd_solver* s, int axis);
+hipError_t pulse_launch_box_flush(const pstd_solver* s, int count, hipStream_t stream);
+struct BoxOut {
+    pstd_problem prob;
+    double dxb[3];
+    double2* acc[3];
+    PhasorScale scale;
+    ProjectState** proj;
+};
+pstd_status pulse_box_output(pstd_solver* s, int ik, bool rescaled, BoxOut* o);
 
 }  // namespace pstd

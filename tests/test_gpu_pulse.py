@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import ntdf as ontdf
 from oracle import partial_waves as pw
 from oracle import pstd as opstd
 from oracle import pulse as opulse
@@ -151,13 +152,21 @@ def test_pulse_validation(P):
         s.save_state()
     assert e.value.name == "PSTD_EUNSUPPORTED"
     s.close()
-    for bad, name in ((dict(surface_kind=0), "PSTD_EUNSUPPORTED"), (dict(scheme=1), "PSTD_EUNSUPPORTED"),
+    for bad, name in ((dict(scheme=1), "PSTD_EUNSUPPORTED"),
                       (dict(sphere_radius=1.2), "PSTD_EINVAL")):  # 1.2: the shell reaches the taper
         s = P.Solver(prob.replace(**bad))
         with pytest.raises(P.PstdError) as e:
             s.set_pulse(psi0, delta, KB)
         assert e.value.name == name, bad
         s.close()
+    # the box surface takes a pulse (its faces lie outside the taper box by
+    # construction), and the misfit then refuses the solver
+    s = P.Solver(prob.replace(surface_kind=0))
+    s.set_pulse(psi0, delta, KB)
+    with pytest.raises(P.PstdError) as e:
+        s.misfit(prob.n_steps, np.array([[0.0, 0.0, 3.0]]), np.ones(1))
+    assert e.value.name == "PSTD_EUNSUPPORTED"
+    s.close()
 
 
 def test_pulse_far_field_at_five_wavenumbers(P):
@@ -207,3 +216,73 @@ def test_pulse_far_field_at_five_wavenumbers(P):
           + f"; k = 1 vs the monochromatic run {r1:.4f}", flush=True)
     assert max(errs) < 0.07
     assert errs[2] < 0.035 and r1 < 0.02
+
+
+def test_pulse_box_phasors_and_projection_match_oracle(P):
+    """The same pulsed run on the box surface (planes 20 and 44, outside the
+    taper box): plane phasors and normal derivatives at three wavenumbers
+    against the oracle, then the far field and Fresnel points of each
+    wavenumber against the oracle's projection at that wavenumber on the
+    same phasors (the library rescales the units by k)."""
+    prob, V, psi0, delta = small_problem()
+    prob = prob.replace(surface_kind=0)
+    print(f"pulse on the box: grid {prob.n}, {prob.n_steps} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.set_pulse(psi0, delta, KB)
+    s.run(prob.n_steps)
+    _, _, _, sd = opulse.run(prob, V, psi0, delta, kbars=KB, box=True)
+    box = ontdf.Box(prob.n, opstd.dxbar(prob), prob.surf_lo, prob.surf_hi)
+    rng = np.random.default_rng(8)
+    dirs = rng.normal(size=(16, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pts = np.array([[0.3, -0.2, 3.5], [-3.0, 0.4, 0.2], [1.0, 3.2, -0.6]])
+    for ik, k in enumerate(KB):
+        gp, gd = s.split_phasors(s.phasors(ik).cpu().numpy())
+        rp, rd = sd.normalized(ik)
+        ep = math.sqrt(sum(np.linalg.norm(gp[f] - rp[f]) ** 2 for f in range(6)) / sum(np.linalg.norm(x) ** 2 for x in rp))
+        ed = math.sqrt(sum(np.linalg.norm(gd[f] - rd[f]) ** 2 for f in range(6)) / sum(np.linalg.norm(x) ** 2 for x in rd))
+        gf = s.far_field(dirs, ik=ik).cpu().numpy()
+        rf = ontdf.far_field(box, gp, gd, dirs, k=k) / prob.k0
+        gq = s.project(pts, ik=ik).cpu().numpy()
+        rq = ontdf.TaylorTables(box, gp, gd, order=8).project(pts * prob.k0, k=k)
+        print(f"  k = {k}: plane phasors rel-L2 {ep:.2e}, derivatives {ed:.2e}; far field "
+              f"{np.abs(gf - rf).max() / np.abs(rf).max():.1e}, points {np.abs(gq - rq).max() / np.abs(rq).max():.1e}",
+              flush=True)
+        assert ep < 1e-4 and ed < 1e-4
+        assert np.abs(gf - rf).max() <= 1e-10 * np.abs(rf).max()
+        assert np.abs(gq - rq).max() <= 1e-8 * np.abs(rq).max()
+    s.close()
+
+
+def test_pulse_box_far_field_at_five_wavenumbers(P):
+    """The pulsed 160^3 run on the box planes 40 and 120: the far field at k
+    = 0.8 ... 1.2 k0 against the partial-wave series."""
+    base, V = synth.square_barrier_160()
+    dtau = opstd.dtau_of(base)
+    steps = int(round(160.0 / dtau))
+    prob = base.replace(n_steps=steps, dft_begin=0, dft_end=steps)
+    delta = base.k0 * base.h[0]
+    psi0 = synth.gaussian_pulse_1d(512, delta, 1.0, 6.0, -30.0)
+    kb = [0.8, 0.9, 1.0, 1.1, 1.2]
+    print(f"pulsed square barrier on the box: grid {prob.n}, {steps} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V)
+    s.set_pulse(psi0, delta, kb)
+    s.run(steps)
+    th = np.deg2rad(np.arange(0, 181, 3.0))
+    ph = np.deg2rad(np.arange(0, 360, 30.0))
+    T, F = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(F), np.sin(T) * np.sin(F), np.cos(T)], -1).reshape(-1, 3)
+    w = np.sin(T) + 1e-3
+
+    def rel(a, b):
+        return math.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2))
+    errs = []
+    for ik, k in enumerate(kb):
+        f = s.far_field(d, ik=ik).cpu().numpy().reshape(T.shape)
+        ref = pw.amplitude(k * base.k0, 2.4, 0.5 * base.k0 ** 2 / 2, th)[:, None] * np.ones_like(F)
+        errs.append(rel(f, ref))
+    s.close()
+    print("  vs partial waves: " + ", ".join(f"k={k}: {e:.4f}" for k, e in zip(kb, errs)), flush=True)
+    assert max(errs) < 0.08
