@@ -32,12 +32,12 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # 512 MiB: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel
 # sources whose SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported
 # as null.  Key: (N, N1, N2, pencils per workgroup, axis).
-TRAFFIC_SRC_SHA256 = "e7bed74c77851615ec5e1b0faa5b5ae0b3f95cb0245201300b7632867a3bcaf3"
+TRAFFIC_SRC_SHA256 = "afc4e2c94af133e06f82720cbade44ec64c14bc4b729b6603b9103f921218b52"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch; this workload's passes carry no surface DFT
-    (160, 10, 16, 16, 0): (32141, 32000), (160, 10, 16, 16, 1): (64159, 32000), (160, 10, 16, 16, 2): (112307, 32000),
-    (160, 10, 16, 32, 0): (32137, 32000), (160, 10, 16, 32, 1): (64168, 32000), (160, 10, 16, 32, 2): (112318, 32000),
-    (160, 10, 16, 8, 0): (32140, 32000), (160, 10, 16, 8, 1): (64181, 32162), (160, 10, 16, 8, 2): (112388, 32254),
-    (160, 16, 10, 16, 0): (32147, 32000), (160, 16, 10, 16, 1): (64173, 32000), (160, 16, 10, 16, 2): (112393, 32000),
+    (160, 10, 16, 16, 0): (32141, 32000), (160, 10, 16, 16, 1): (64167, 32000), (160, 10, 16, 16, 2): (112317, 32000),
+    (160, 10, 16, 32, 0): (32123, 32000), (160, 10, 16, 32, 1): (64164, 32000), (160, 10, 16, 32, 2): (112313, 32000),
+    (160, 10, 16, 8, 0): (32141, 32000), (160, 10, 16, 8, 1): (64173, 32136), (160, 10, 16, 8, 2): (112365, 32273),
+    (160, 16, 10, 16, 0): (32142, 32000), (160, 16, 10, 16, 1): (64181, 32000), (160, 16, 10, 16, 2): (112385, 32000),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")
@@ -46,14 +46,14 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/cs
 # The shell DFT of the spherical surface (r = 5, 64 x 128 nodes) on the same
 # workload, per launch of a pair of steps, valid for the sphere sources whose
 # SHA-256 is SHELL_TRAFFIC_SRC_SHA256.
-SHELL_TRAFFIC_SRC_SHA256 = "e72486ae279ce183bc74b442534e415d72cffb5948888930814aa55a08dbc351"
+SHELL_TRAFFIC_SRC_SHA256 = "5a92eeda1d88c2f6d64b0f6a3a6ab22dd5923568c77e4abb8434aa4c81a7fa9f"
 SHELL_TRAFFIC_KIB = (18327, 10505)
 SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "7825d7f1ac9ccc0640185d81bdffc54c42ccec0ea9a958feb4a216825ece6442"
-FDTD_TRAFFIC_KIB = {160: (105875, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "79e21e1a9c32f67ab2d2768c6748464077f311f8847277ef525f346c447c8bfc"
+FDTD_TRAFFIC_KIB = {160: (105887, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 
@@ -406,7 +406,12 @@ def bench_pulse(args):
     import paper_2403_04053_amd as P
     import synth
     base, V = synth.square_barrier_160(n_fft=args.n)
-    sph = dict(surface_kind=1, sphere_radius=5.6 * args.n / 160, sphere_nodes=(64, 128))
+    if args.surface == "sphere":
+        sph = dict(surface_kind=1, sphere_radius=5.6 * args.n / 160, sphere_nodes=(64, 128))
+        surf_txt = "sphere r=5.6 (64x128 nodes)"
+    else:
+        sph = {}
+        surf_txt = "box planes N/2-+40 (plane values staged in the passes)"
     dtau_p, _ = P.pstd_reduced_step(P.problem_from(base))
     solve_steps = int(round(160.0 / dtau_p))
     prob = base.replace(n_steps=solve_steps, dft_begin=0, dft_end=10 ** 12, **sph)
@@ -458,10 +463,11 @@ def bench_pulse(args):
     s, t_pulse, _ = solve(prob, True, solve_steps, tune)
     s.close()
     cw_prob = base.replace(dft_begin=base.n_steps - 1354, dft_end=base.n_steps, **sph)
+    # (the box's monochromatic solve keeps its plane sums inside the passes)
     s, t_cw, _ = solve(cw_prob, False, base.n_steps, tune)
     s.close()
     out = {
-        "metric": "PSTD Gcell-updates/s (FP32 step, pulsed incidence, FP64 shell DFT at 5 wavenumbers)",
+        "metric": "PSTD Gcell-updates/s (FP32 step, pulsed incidence, FP64 surface DFT at 5 wavenumbers)",
         "value": round(cells * args.steps / (ms / 1e3) / 1e9, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -474,7 +480,7 @@ def bench_pulse(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 FFT grid, Gaussian packet along z "
-                               "(k0, width 6), sphere r=5.6 (64x128 nodes), phasors at k/k0 = 0.8, 0.9, 1.0, 1.1, 1.2",
+                               f"(k0, width 6), {surf_txt}, phasors at k/k0 = 0.8, 0.9, 1.0, 1.1, 1.2",
                    "cells": cells},
         "roofline": {"bound": "hbm", "kernel": "pass_z", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
