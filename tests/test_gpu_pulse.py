@@ -89,14 +89,14 @@ def test_pulse_phasors_match_oracle(P, small):
         assert np.abs(gf - rf).max() <= 1e-10 * np.abs(rf).max()
 
 
-@pytest.mark.parametrize("theta,phi", [(2.3, 4.0), (1.2, 5.5)])
-def test_pulse_other_octants_match_oracle(P, theta, phi):
+@pytest.mark.parametrize("theta,phi,eta_src", [(2.3, 4.0, 0), (1.2, 5.5, 0), (0.7, 0.9, 1)])
+def test_pulse_other_octants_match_oracle(P, theta, phi, eta_src):
     """Incidence from two more octants (the origin corner of Eq. Oinc and
-    the axis coordinate change with the signs of k_hat): 150 steps, psi
-    against the oracle."""
+    the axis coordinate change with the signs of k_hat), and the source
+    scaled by eta: 150 steps, psi against the oracle."""
     prob, V, psi0, delta = small_problem(steps=150)
-    prob = prob.replace(theta=theta, phi=phi, dft_end=0)
-    print(f"pulse, theta {theta} phi {phi}: grid {prob.n}, {prob.n_steps} steps", flush=True)
+    prob = prob.replace(theta=theta, phi=phi, dft_end=0, eta_on_source=eta_src)
+    print(f"pulse, theta {theta} phi {phi} eta on source {eta_src}: grid {prob.n}, {prob.n_steps} steps", flush=True)
     s = P.Solver(prob)
     s.set_potential(V)
     s.set_pulse(psi0, delta, KB)
