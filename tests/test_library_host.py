@@ -116,3 +116,38 @@ def test_subdomain_validation():
     _expect("PSTD_EINVAL", prob.replace(sub_taper=4))                       # halo < taper + 5
     _expect("PSTD_EINVAL", prob.replace(sub_core=(50, 48, 48)))            # does not tile 288
     _expect("PSTD_EUNSUPPORTED", prob.replace(sub_core=(72, 48, 48)))      # local length 88
+
+
+def test_binding_argument_kinds_match_the_header():
+    """Every function the binding declares takes, in the header, the same
+    number of parameters of the same kinds (pointer, int64, int32, double):
+    a mismatch would pass garbage through ctypes without an error."""
+    import ctypes
+    text = open(HEADER).read()
+    decls = {}
+    for m in re.finditer(r"^\s*pstd_status\s+(pstd_\w+)\s*\(([^;]*?)\)\s*;", text, re.M | re.S):
+        decls[m.group(1)] = [p.strip() for p in m.group(2).split(",") if p.strip()]
+
+    def kind_c(p):
+        if "*" in p:
+            return "ptr"
+        if p.startswith("int64_t"):
+            return "i64"
+        if p.startswith("int32_t"):
+            return "i32"
+        if p.startswith("double"):
+            return "f64"
+        return "?" + p
+
+    def kind_py(t):
+        if t in (ctypes.c_void_p,) or hasattr(t, "_type_") and isinstance(t._type_, type):
+            return "ptr"
+        return {ctypes.c_int64: "i64", ctypes.c_int32: "i32", ctypes.c_double: "f64"}.get(t, "?" + repr(t))
+
+    sigs = lib_mod._SIGS
+    assert len(sigs) >= 30
+    for name, args in sigs.items():
+        assert name in decls, name
+        want = [kind_c(p) for p in decls[name]]
+        got = [kind_py(t) for t in args]
+        assert got == want, (name, got, want)
