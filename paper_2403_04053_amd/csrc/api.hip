@@ -348,15 +348,14 @@ pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
 
 pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int count, hipEvent_t* ev) {
     if (s->pulse) {
-        // the packet's values on the layer's table for this step, and psi^n
-        // on the shell into the group's ring (added at the group's end), in
-        // one launch
+        // the packet's table of the next step, this step's layer source (into
+        // psi^{n-1}, before the z pass), and psi^n on the shell into the
+        // group's ring (added at the group's end), in one launch
         const int* list;
         int64_t n_shell;
         float2* stage;
         pstd::sphere_stage_buffers(s, &list, &n_shell, &stage);
-        const float2* src[2] = {s->buf[0], s->buf[1]};
-        hipError_t e = pstd::pulse_launch_pre(s, koff, src, list, n_shell, stage, stream);
+        hipError_t e = pstd::pulse_launch_pre(s, koff, list, n_shell, stage, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pulse table / shell stage launch");
     } else if (pstd::sphere_staged(s)) {
         hipError_t e = pstd::sphere_launch_stage(s, koff, stream);
@@ -386,11 +385,6 @@ pstd_status launch_passes(pstd_solver* s, hipStream_t stream, int koff, int coun
         hipError_t e = pstd::launch_variant_single(s->variant[axis], seg, axis, a, koff, stream);
         if (e != hipSuccess) return hip_fail(s, e, "pass launch");
         if (ev) HIP_TRY(s, hipEventRecord(ev[2 * axis + 1], stream));
-    }
-    if (s->pulse) {
-        // the layer source of the packet, added to psi^{n+1}
-        hipError_t e = pstd::pulse_launch_source(s, koff, stream);
-        if (e != hipSuccess) return hip_fail(s, e, "pulse source launch");
     }
     if (s->pulse && koff == count - 1) {
         // a pulsed run on the box: the group's staged plane values into the sums

@@ -9,16 +9,17 @@
 //   a_l(n) = c_l exp(-i theta_l n),  sin(theta_l) = dtau eta k_l^2,
 // c_l = F[psi^0]_l / N, and nothing has to be stored per step.
 //
-// Each step, pulse_table_kernel evaluates the spectral interpolation of
-// Eqs. pstd_psiinc / pstd_dpsiinc on a table four times finer than the
-// grids, over the d-range of the transition layer only (a few hundred
-// points, one wave each); pulse_source_kernel, after the z pass, interpolates the table at
-// every layer cell with 8-point Lagrange weights (error ~ (k h)^8 / 8!, below
-// 1e-8 of the packet) and adds the layer source of Eq.
+// Before the passes of each step, one launch (pulse_pre_kernel) evaluates
+// the spectral interpolation of Eqs. pstd_psiinc / pstd_dpsiinc for the next
+// step on a table four times finer than the grids, over the d-range of the
+// transition layer only (a few hundred points, one wave each), interpolates
+// this step's table at every layer cell with 8-point Lagrange weights (error
+// ~ (k h)^8 / 8!, below 1e-8 of the packet) and adds the layer source of Eq.
 // dimlesstildeSchrodinger, lap(zeta) psi_inc + 2 grad(zeta) . k_hat
-// dpsi_inc/dd, times -i Gamma 2 dtau (eta): linear in the update, so adding
-// it after the pass equals adding it inside.  The passes are unchanged; the
-// monochromatic source is off (sigma = 0).
+// dpsi_inc/dd, times -i 2 dtau (eta), to psi^{n-1} before the z pass, which
+// multiplies it by Gamma: the update is linear, so this equals adding it
+// inside.  The passes are unchanged; the monochromatic source is off
+// (sigma = 0).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +39,7 @@ struct PulseState {
     double* theta = nullptr;   // phase per step of each mode
     int J = 0;                 // table points d_lo + j h
     double d_lo = 0, h = 0;
-    double2* tab = nullptr;    // [2][J]: sum a_l e^{i k_l d}, sum a_l k_l e^{i k_l d}
+    double2* tab = nullptr;    // [step parity][2][J]: sum a_l e^{i k_l d}, sum a_l k_l e^{i k_l d}
     double2* ekd = nullptr;    // [J][K]: e^{i k_l d_j}
     int64_t n_cells = 0;       // transition-layer cells
     int* cell = nullptr;
@@ -93,42 +94,78 @@ void fft_pow2(std::vector<std::complex<double>>& a) {
     }
 }
 
-// T0(d_j) = sum_l a_l(n) e^{i k_l d_j}, T1(d_j) = sum_l a_l(n) k_l e^{i k_l d_j}
-// for the table points of step n = ctr[0] + koff.  One wave per table point:
-// its 64 lanes take every 64th mode (a_l(n) shared by the block's four
-// points through LDS, e^{i k_l d_j} from the precomputed table), then the
-// wave adds the lane sums in a fixed order.  Blocks past the table's stage psi^n on the sphere's shell
-// into slot koff of the ring (same launch: both only read the state before
-// the step).
+// One launch before the passes of step n = ctr[0] + koff, three kinds of
+// blocks, each touching its own buffers:
+//  * table blocks: T0(d_j) = sum_l a_l(m) e^{i k_l d_j} and T1(d_j) = sum_l
+//    a_l(m) k_l e^{i k_l d_j} for the next step m = n + 1, into the table
+//    buffer of m's parity.  One wave per table point: its 64 lanes take
+//    every 64th mode (a_l(m) shared by the block's four points through LDS,
+//    e^{i k_l d_j} from the precomputed table), then the wave adds the lane
+//    sums in a fixed order;
+//  * source blocks: the layer source of step n from the table of n's parity
+//    (interpolated with the cell's 8 Lagrange weights), -i fac S added to
+//    psi^{n-1}, which only the z pass reads next and which it multiplies by
+//    Gamma: the same as adding -i Gamma fac S inside the update;
+//  * stage blocks: psi^n on the sphere's shell into slot koff of the ring.
+// koff = -1 with table blocks only primes the table of step ctr[0].
 __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restrict__ ctr, int koff, int K,
                                                         const double2* __restrict__ coef,
                                                         const double* __restrict__ theta, double k_lo, double dk,
                                                         int J, const double2* __restrict__ ekd,
                                                         double2* __restrict__ tab, int table_blocks,
-                                                        const float2* __restrict__ buf0, const float2* __restrict__ buf1,
+                                                        int64_t nc, const int* __restrict__ cell,
+                                                        const int* __restrict__ j0, const double* __restrict__ w,
+                                                        const double2* __restrict__ ab, int source_blocks,
+                                                        float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                         const int* __restrict__ list, int64_t n_shell,
                                                         float2* __restrict__ stage) {
     const int64_t n = ctr[0] + koff;
     if (n >= ctr[1]) return;
-    if ((int)blockIdx.x >= table_blocks) {
-        const int64_t c = (int64_t)(blockIdx.x - table_blocks) * blockDim.x + threadIdx.x;
+    const int blk = (int)blockIdx.x;
+    if (blk >= table_blocks + source_blocks) {
+        const int64_t c = (int64_t)(blk - table_blocks - source_blocks) * blockDim.x + threadIdx.x;
         if (c < n_shell) stage[koff * n_shell + c] = ((n & 1) ? buf1 : buf0)[list[c]];
         return;
     }
-    // the step's mode amplitudes a_l(n) = c_l e^{-i theta_l n}, once per
+    if (blk >= table_blocks) {
+        const int64_t c = (int64_t)(blk - table_blocks) * blockDim.x + threadIdx.x;
+        if (c >= nc) return;
+        const double2* t = tab + (n & 1) * 2 * (int64_t)J;
+        const int j = j0[c];
+        const double* wc = w + kLag * c;
+        double p0r = 0, p0i = 0, p1r = 0, p1i = 0;
+        for (int m = 0; m < kLag; ++m) {
+            const double2 t0 = t[j + m], t1 = t[J + j + m];
+            p0r += wc[m] * t0.x;
+            p0i += wc[m] * t0.y;
+            p1r += wc[m] * t1.x;
+            p1i += wc[m] * t1.y;
+        }
+        const double2 q = ab[c];
+        // S = A T0 + B i T1; psi^{n-1} -= i S
+        const double sr = q.x * p0r - q.y * p1i, si = q.x * p0i + q.y * p1r;
+        float2* out = ((n + 1) & 1) ? buf1 : buf0;
+        float2 v = out[cell[c]];
+        v.x += (float)si;
+        v.y -= (float)sr;
+        out[cell[c]] = v;
+        return;
+    }
+    // the next step's mode amplitudes a_l(m) = c_l e^{-i theta_l m}, once per
     // block in LDS (chunks of kModeChunk modes); every wave of a table block
     // takes part in the barriers, those past the table's end store nothing
+    const int64_t mstep = n + 1;
     __shared__ double2 a_s[kModeChunk];
     const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const double2* e_j = ekd + (int64_t)min(j, J - 1) * K;
+    const int jt = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const double2* e_j = ekd + (int64_t)min(jt, J - 1) * K;
     double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
     for (int m0 = 0; m0 < K; m0 += kModeChunk) {
         const int nm = min(kModeChunk, K - m0);
         __syncthreads();
         for (int e = threadIdx.x; e < nm; e += blockDim.x) {
             double sn, cs;
-            sincos(theta[m0 + e] * (double)n, &sn, &cs);
+            sincos(theta[m0 + e] * (double)mstep, &sn, &cs);
             const double2 c = coef[m0 + e];
             a_s[e] = make_double2(c.x * cs + c.y * sn, c.y * cs - c.x * sn);
         }
@@ -149,41 +186,11 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
         s1r += __shfl_xor(s1r, off);
         s1i += __shfl_xor(s1i, off);
     }
-    if (lane == 0 && j < J) {
-        tab[j] = make_double2(s0r, s0i);
-        tab[J + j] = make_double2(s1r, s1i);
+    if (lane == 0 && jt < J) {
+        double2* t = tab + (mstep & 1) * 2 * (int64_t)J;
+        t[jt] = make_double2(s0r, s0i);
+        t[J + jt] = make_double2(s1r, s1i);
     }
-}
-
-// psi^{n+1} -= i (A psi_inc + B dpsi_inc/dd) at the layer cells, psi_inc =
-// T0 and dpsi_inc/dd = i T1 interpolated from the table
-__global__ __launch_bounds__(256) void pulse_source_kernel(const int64_t* __restrict__ ctr, int koff, int64_t nc,
-                                                           const int* __restrict__ cell, const int* __restrict__ j0,
-                                                           const double* __restrict__ w, const double2* __restrict__ ab,
-                                                           const double2* __restrict__ tab, int J,
-                                                           float2* __restrict__ buf0, float2* __restrict__ buf1) {
-    const int64_t n = ctr[0] + koff;
-    if (n >= ctr[1]) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const int j = j0[c];
-    const double* wc = w + kLag * c;
-    double p0r = 0, p0i = 0, p1r = 0, p1i = 0;
-    for (int m = 0; m < kLag; ++m) {
-        const double2 t0 = tab[j + m], t1 = tab[J + j + m];
-        p0r += wc[m] * t0.x;
-        p0i += wc[m] * t0.y;
-        p1r += wc[m] * t1.x;
-        p1i += wc[m] * t1.y;
-    }
-    const double2 q = ab[c];
-    // S = A T0 + B i T1
-    const double sr = q.x * p0r - q.y * p1i, si = q.x * p0i + q.y * p1r;
-    float2* out = ((n + 1) & 1) ? buf1 : buf0;
-    float2 v = out[cell[c]];
-    v.x += (float)si;
-    v.y -= (float)sr;
-    out[cell[c]] = v;
 }
 
 // the staged plane values of the launch group's steps ctr[0] .. ctr[0] +
@@ -311,23 +318,13 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
         ps->g[m] = make_double2(coef[m].x * cr - coef[m].y * ci, coef[m].x * ci + coef[m].y * cr);
     }
     // transition-layer cells (taper box of every axis), their axis coordinate and coefficients
-    std::vector<double> z[3], z1[3], z2[3], gam[3];
+    std::vector<double> z[3], z1[3], z2[3];
     for (int a = 0; a < 3; ++a) {
         const int N = p.n[a];
         z[a].resize(N);
         z1[a].resize(N);
         z2[a].resize(N);
-        gam[a].resize(N);
-        for (int i = 0; i < N; ++i) {
-            solver_taper(p, a, s->dxb[a], i, &z[a][i], &z1[a][i], &z2[a][i]);
-            const int d = std::min(i, N - 1 - i);
-            double gg = 0;
-            if (d < p.abc_cells[a]) {
-                const double c = std::cosh(p.abc_alpha * d);
-                gg = p.abc_U0 / (c * c);
-            }
-            gam[a][i] = std::exp(-gg * s->dtau);
-        }
+        for (int i = 0; i < N; ++i) solver_taper(p, a, s->dxb[a], i, &z[a][i], &z1[a][i], &z2[a][i]);
     }
     const double fac = 2.0 * s->dtau * (p.eta_on_source ? s->eta : 1.0);
     std::vector<int> cell;
@@ -347,12 +344,11 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
                     grad += z1[a][ix[a]] * s->kh[a] * others;
                 }
                 if (lap == 0 && grad == 0) continue;
-                const double G = gam[0][i] * gam[1][j] * gam[2][k];
                 cell.push_back((int)(i + nx * (j + ny * (int64_t)k)));
                 double d = 0;
                 for (int a = 0; a < 3; ++a) d += (ix[a] - O[a]) * s->dxb[a] * s->kh[a];
                 dc.push_back(d);
-                ab.push_back(make_double2(G * fac * lap, G * fac * 2.0 * grad));
+                ab.push_back(make_double2(fac * lap, fac * 2.0 * grad));
             }
     ps->n_cells = (int64_t)cell.size();
     // table over the layer's d-range, 4 times finer than the finer of the two grids
@@ -406,7 +402,7 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
         }
     }
     if ((e = hipStreamSynchronize(s->stream)) || (e = up(&ps->coef, coef)) || (e = up(&ps->theta, ps->theta_h)) ||
-        (e = hipMalloc(&ps->tab, 2 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->ekd, ekd)) ||
+        (e = hipMalloc(&ps->tab, 4 * (size_t)ps->J * sizeof(double2))) || (e = up(&ps->ekd, ekd)) ||
         (e = up(&ps->cell, cell)) ||
         (e = up(&ps->j0, j0)) || (e = up(&ps->w, w)) || (e = up(&ps->ab, ab))) {
         pulse_free(ps);
@@ -425,28 +421,25 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
     // rebuild the per-step tables: no monochromatic source, one DFT weight row per wavenumber
     const int64_t cap = std::max<int64_t>(s->tab_cap, 1024);
     s->tab_cap = 0;
-    return solver_ensure_tables(s, cap);
+    pstd_status st = solver_ensure_tables(s, cap);
+    if (st) return st;
+    pulse_reset(s);  // the packet's table of step 0
+    return PSTD_OK;
 }
 
-hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const float2* const* stage_src, const int* list,
-                            int64_t n_shell, float2* stage, hipStream_t stream) {
+hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const int* list, int64_t n_shell, float2* stage,
+                            hipStream_t stream) {
     const PulseState* ps = s->pulse;
     if (!ps) return hipSuccess;
     if (stage && (koff < 0 || koff >= kStageSteps)) return hipErrorInvalidValue;
     const int table_blocks = ps->n_cells ? (ps->J + 3) / 4 : 0;
-    const int stage_blocks = stage ? (int)((n_shell + 255) / 256) : 0;
-    if (table_blocks + stage_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(pulse_pre_kernel, dim3((unsigned)(table_blocks + stage_blocks)), dim3(256), 0, stream, s->ctr,
-                       koff, ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->ekd, ps->tab, table_blocks,
-                       stage_src[0], stage_src[1], list, stage ? n_shell : 0, stage);
-    return hipGetLastError();
-}
-
-hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t stream) {
-    const PulseState* ps = s->pulse;
-    if (!ps || ps->n_cells == 0) return hipSuccess;
-    hipLaunchKernelGGL(pulse_source_kernel, dim3((unsigned)((ps->n_cells + 255) / 256)), dim3(256), 0, stream, s->ctr,
-                       koff, ps->n_cells, ps->cell, ps->j0, ps->w, ps->ab, ps->tab, ps->J, s->buf[0], s->buf[1]);
+    const int source_blocks = koff >= 0 ? (int)((ps->n_cells + 255) / 256) : 0;
+    const int stage_blocks = stage && koff >= 0 ? (int)((n_shell + 255) / 256) : 0;
+    if (table_blocks + source_blocks + stage_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(pulse_pre_kernel, dim3((unsigned)(table_blocks + source_blocks + stage_blocks)), dim3(256), 0,
+                       stream, s->ctr, koff, ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->ekd, ps->tab,
+                       table_blocks, ps->n_cells, ps->cell, ps->j0, ps->w, ps->ab, source_blocks, s->buf[0],
+                       s->buf[1], list, stage ? n_shell : 0, stage);
     return hipGetLastError();
 }
 
@@ -477,6 +470,8 @@ std::complex<double> incident_phasor(const pstd_solver* s, int f) {
 void pulse_reset(pstd_solver* s) {
     if (!s->pulse) return;
     s->pulse->from = s->step;
+    // the table of the current step, read by its first launch
+    if (pulse_launch_pre(s, -1, nullptr, 0, nullptr, s->stream) == hipSuccess) (void)hipStreamSynchronize(s->stream);
     for (int a = 0; a < 3; ++a)
         if (s->pulse->bacc[a])
             (void)hipMemset(s->pulse->bacc[a], 0, s->pulse->kbar.size() * 8 * s->points[a] * sizeof(double2));

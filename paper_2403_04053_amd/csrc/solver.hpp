@@ -125,12 +125,12 @@ pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double de
 void pulse_free(PulseState* p);
 int pulse_wavenumbers(const pstd_solver* s);
 double pulse_frequency(const pstd_solver* s, int ik);
-// before the x pass of step ctr[0] + koff: the packet's table, and psi^n of
-// the shell cells `list` into slot koff of `stage` (when stage is not null)
-hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const float2* const* stage_src, const int* list,
-                            int64_t n_shell, float2* stage, hipStream_t stream);
-// after the z pass: the layer source
-hipError_t pulse_launch_source(const pstd_solver* s, int koff, hipStream_t stream);
+// before the x pass of step ctr[0] + koff: the packet's table of the next
+// step, the layer source of this one (added to psi^{n-1}), and psi^n of the
+// shell cells `list` into slot koff of `stage` (when stage is not null);
+// koff = -1 primes the table of step ctr[0]
+hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const int* list, int64_t n_shell, float2* stage,
+                            hipStream_t stream);
 // the steps that count for the incident phasors start at the current step
 void pulse_reset(pstd_solver* s);
 // the output of wavenumber ik
