@@ -125,6 +125,29 @@ def test_pulse_split_runs_are_bit_identical(P):
         assert np.array_equal(a, out[0][0]) and np.array_equal(b, out[0][1])
 
 
+def test_pulse_resumed_from_a_state_is_bit_identical(P):
+    """A pulsed run restarted from its own state at step 37 (pstd_set_state
+    primes the packet's table of that step) continues bit for bit."""
+    prob, V, psi0, delta = small_problem(steps=60)
+    prob = prob.replace(dft_end=0)
+    a = P.Solver(prob)
+    a.set_potential(V)
+    a.set_pulse(psi0, delta, KB)
+    a.run(37)
+    prev, cur = a.psi(1).clone(), a.psi(0).clone()
+    a.run(23)
+    want = a.psi(0).cpu().numpy()
+    a.close()
+    b = P.Solver(prob)
+    b.set_potential(V)
+    b.set_pulse(psi0, delta, KB)
+    b.set_state(prev, cur, 37)
+    b.run(23)
+    got = b.psi(0).cpu().numpy()
+    b.close()
+    assert np.array_equal(got, want)
+
+
 def test_pulse_validation(P):
     prob, V, psi0, delta = small_problem(steps=20)
     s = P.Solver(prob)
