@@ -218,8 +218,12 @@ pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n
  * pstd_save_state fills such a buffer (caller-owned device memory);
  * pstd_load_state restores it into a solver of the same grid, after which
  * pstd_run continues exactly as the saved solver would (bit-identical
- * results).  Both synchronise.  EINVAL: buffer too small, or (load) a buffer
- * that holds no state of this grid.  ESTATE: load into a batch instance. */
+ * results).  A pulsed run's state adds its first step and the sums of every
+ * wavenumber; load it into a solver given the same pulse (pstd_set_pulse
+ * with the same packet and wavenumbers, before the load).  Both synchronise.
+ * EINVAL: buffer too small, or (load) a buffer that holds no state of this
+ * grid, or whose run differs from this solver in having a pulse or in its
+ * number of wavenumbers.  ESTATE: load into a batch instance. */
 pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out_host);
 pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes);
 pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes);
@@ -304,9 +308,8 @@ pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir,
  * EINVAL: n1d not a power of two in [8, 2^20], delta <= 0, n_k outside
  * [1, 64], a wavenumber <= 0 or beyond the step bound, the 1D grid's
  * Nyquist mode beyond the step bound, a non-finite or zero packet, a
- * spectrum so wide that the layer's table would exceed 2^26 entries.  A
- * pulsed run has no checkpoint (pstd_save_state / pstd_load_state return
- * EUNSUPPORTED).  Synchronises. */
+ * spectrum so wide that the layer's table would exceed 2^26 entries.
+ * Synchronises. */
 pstd_status pstd_set_pulse(pstd_solver* s, const double* psi0_host, int32_t n1d, double delta,
                            const double* kbar_host, int32_t n_k);
 

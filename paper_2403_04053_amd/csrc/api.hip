@@ -994,21 +994,24 @@ pstd_status pstd_get_psi(pstd_solver* s, int32_t level, void* psi_dev, int64_t n
 }
 
 // serialized state: header, psi^{n-1}, psi^n, the surface DFT sums (value
-// and compensation) of the three axes
+// and compensation) of the three axes, the sphere's sums (one set per
+// wavenumber), a pulsed run's per-wavenumber box sums
 struct StateHeader {
     int64_t magic;
     int64_t n[3];
     int64_t step;
     double inc_sum;
     int64_t bytes;
+    int64_t n_k;     // wavenumbers of a pulsed run, 0 without a pulse
+    int64_t from;    // pulsed run: first step since the pulse was set or pstd_set_state
     int64_t pad;
 };
-constexpr int64_t kStateMagic = 0x3176534454535050LL;  // "PPSTDSv1"
+constexpr int64_t kStateMagic = 0x3276534454535050LL;  // "PPSTDSv2"
 
 static int64_t state_bytes(const pstd_solver* s) {
     int64_t b = (int64_t)sizeof(StateHeader) + 2 * s->cells * (int64_t)sizeof(float2);
     for (int a = 0; a < 3; ++a) b += 8 * s->points[a] * (int64_t)sizeof(double2);
-    return b + sphere_state_bytes(s);
+    return b + sphere_state_bytes(s) + pulse_state_bytes(s);
 }
 
 pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out) {
@@ -1019,10 +1022,11 @@ pstd_status pstd_state_size(const pstd_solver* s, int64_t* bytes_out) {
 
 pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
     if (!s || !dev_buf) return PSTD_EINVAL;
-    if (s->pulse) return fail(s, PSTD_EUNSUPPORTED, "no checkpoint of a pulsed run");
     const int64_t need = state_bytes(s);
     if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
-    StateHeader h{kStateMagic, {s->prob.n[0], s->prob.n[1], s->prob.n[2]}, s->step, s->inc_sum, need, 0};
+    const int64_t n_k = (s->pulse ? pulse_wavenumbers(s) : 0);
+    StateHeader h{kStateMagic, {s->prob.n[0], s->prob.n[1], s->prob.n[2]}, s->step, s->inc_sum, need, n_k,
+                  n_k ? pulse_from(s) : 0, 0};
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     char* d = (char*)dev_buf;
     HIP_TRY(s, hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice));
@@ -1037,13 +1041,13 @@ pstd_status pstd_save_state(pstd_solver* s, void* dev_buf, int64_t bytes) {
         d += ab;
     }
     HIP_TRY(s, sphere_save(s, d, s->stream));
+    HIP_TRY(s, pulse_save(s, d + sphere_state_bytes(s), s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return PSTD_OK;
 }
 
 pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) {
     if (!s || !dev_buf) return PSTD_EINVAL;
-    if (s->pulse) return fail(s, PSTD_EUNSUPPORTED, "no checkpoint of a pulsed run");
     if (s->in_batch) return fail(s, PSTD_ESTATE, "instances of a batch are stepped by the batch");
     const int64_t need = state_bytes(s);
     if (bytes < need) return fail(s, PSTD_EINVAL, "buffer smaller than pstd_state_size");
@@ -1053,6 +1057,8 @@ pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) 
     if (h.magic != kStateMagic || h.bytes != need || h.n[0] != s->prob.n[0] || h.n[1] != s->prob.n[1] ||
         h.n[2] != s->prob.n[2] || h.step < 0 || !(h.inc_sum >= 0))
         return fail(s, PSTD_EINVAL, "buffer does not hold a saved state of this grid");
+    if (h.n_k != (s->pulse ? pulse_wavenumbers(s) : 0) || (h.n_k && (h.from < 0 || h.from > h.step)))
+        return fail(s, PSTD_EINVAL, "the saved run and this solver differ in their pulse");
     adjoint_invalidate(s);
     pstd_status st = solver_ensure_tables(s, h.step + 1);
     if (st) return st;
@@ -1073,6 +1079,11 @@ pstd_status pstd_load_state(pstd_solver* s, const void* dev_buf, int64_t bytes) 
     s->step = h.step;
     s->inc_sum = h.inc_sum;
     s->win_steps = h.inc_sum > 0 ? 1 : 0;
+    if (h.n_k) {
+        // the window steps since the pulse's first step, and its table of this step
+        s->win_steps = std::max<int64_t>(0, std::min(h.step, s->prob.dft_end) - std::max(h.from, s->prob.dft_begin));
+        HIP_TRY(s, pulse_load(s, d + sphere_state_bytes(s), h.from));
+    }
     return PSTD_OK;
 }
 

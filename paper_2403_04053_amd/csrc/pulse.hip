@@ -238,6 +238,8 @@ void pulse_free(PulseState* p) {
 
 int pulse_wavenumbers(const pstd_solver* s) { return s->pulse ? (int)s->pulse->kbar.size() : 1; }
 
+int64_t pulse_from(const pstd_solver* s) { return s->pulse ? s->pulse->from : 0; }
+
 double pulse_frequency(const pstd_solver* s, int ik) { return s->pulse ? s->pulse->W[ik] : s->omega; }
 
 pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double delta, const double* kbar, int32_t nk) {
@@ -467,14 +469,55 @@ std::complex<double> incident_phasor(const pstd_solver* s, int f) {
 
 }  // namespace
 
+namespace {
+
+// the packet's table of the current step (the device counter holds it), read
+// by the step's first launch
+hipError_t prime_table(pstd_solver* s) {
+    hipError_t e = pulse_launch_pre(s, -1, nullptr, 0, nullptr, s->stream);
+    return e == hipSuccess ? hipStreamSynchronize(s->stream) : e;
+}
+
+int64_t box_sum_bytes(const pstd_solver* s, int a) {
+    return (int64_t)s->pulse->kbar.size() * 8 * s->points[a] * (int64_t)sizeof(double2);
+}
+
+}  // namespace
+
 void pulse_reset(pstd_solver* s) {
     if (!s->pulse) return;
     s->pulse->from = s->step;
-    // the table of the current step, read by its first launch
-    if (pulse_launch_pre(s, -1, nullptr, 0, nullptr, s->stream) == hipSuccess) (void)hipStreamSynchronize(s->stream);
+    (void)prime_table(s);
     for (int a = 0; a < 3; ++a)
-        if (s->pulse->bacc[a])
-            (void)hipMemset(s->pulse->bacc[a], 0, s->pulse->kbar.size() * 8 * s->points[a] * sizeof(double2));
+        if (s->pulse->bacc[a]) (void)hipMemset(s->pulse->bacc[a], 0, box_sum_bytes(s, a));
+}
+
+int64_t pulse_state_bytes(const pstd_solver* s) {
+    if (!s->pulse || !s->pulse->box) return 0;
+    return box_sum_bytes(s, 0) + box_sum_bytes(s, 1) + box_sum_bytes(s, 2);
+}
+
+hipError_t pulse_save(const pstd_solver* s, char* dst, hipStream_t stream) {
+    if (!s->pulse || !s->pulse->box) return hipSuccess;
+    for (int a = 0; a < 3; ++a) {
+        if (hipError_t e = hipMemcpyAsync(dst, s->pulse->bacc[a], box_sum_bytes(s, a), hipMemcpyDeviceToDevice, stream))
+            return e;
+        dst += box_sum_bytes(s, a);
+    }
+    return hipSuccess;
+}
+
+hipError_t pulse_load(pstd_solver* s, const char* src, int64_t from) {
+    PulseState* ps = s->pulse;
+    if (!ps) return hipSuccess;
+    ps->from = from;
+    if (ps->box)
+        for (int a = 0; a < 3; ++a) {
+            if (hipError_t e = hipMemcpyAsync(ps->bacc[a], src, box_sum_bytes(s, a), hipMemcpyDeviceToDevice, s->stream))
+                return e;
+            src += box_sum_bytes(s, a);
+        }
+    return prime_table(s);
 }
 
 float2* pulse_box_stage(const pstd_solver* s, int axis) { return s->pulse ? s->pulse->bstage[axis] : nullptr; }

@@ -124,6 +124,8 @@ double sphere_taper_max(const pstd_solver* s);
 pstd_status pulse_set(pstd_solver* s, const double* psi0, int32_t n1d, double delta, const double* kbar, int32_t nk);
 void pulse_free(PulseState* p);
 int pulse_wavenumbers(const pstd_solver* s);
+// a pulsed run's first step since the pulse was set or pstd_set_state
+int64_t pulse_from(const pstd_solver* s);
 double pulse_frequency(const pstd_solver* s, int ik);
 // before the x pass of step ctr[0] + koff: the packet's table of the next
 // step, the layer source of this one (added to psi^{n-1}), and psi^n of the
@@ -133,6 +135,13 @@ hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const int* list, int
                             hipStream_t stream);
 // the steps that count for the incident phasors start at the current step
 void pulse_reset(pstd_solver* s);
+// checkpoint of a pulsed run: the box's per-wavenumber plane sums (the
+// sphere's are saved with the sphere); pulse_load also restores the first
+// step since the last reset and primes the packet's table of the current
+// step, so the device counter must already hold it
+int64_t pulse_state_bytes(const pstd_solver* s);
+hipError_t pulse_save(const pstd_solver* s, char* dst, hipStream_t stream);
+hipError_t pulse_load(pstd_solver* s, const char* src, int64_t from);
 // the output of wavenumber ik
 pstd_status pulse_output(pstd_solver* s, int ik, SphereOut* o);
 // box surface: the staging ring of the pass along `axis` (null unless a

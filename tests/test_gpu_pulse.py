@@ -148,6 +148,51 @@ def test_pulse_resumed_from_a_state_is_bit_identical(P):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("surface_kind", [1, 0])
+def test_pulse_checkpoint_resumes_bit_for_bit(P, surface_kind):
+    """pstd_save_state at step 150 of a 300-step pulsed run (in the middle of
+    a launch group and of the DFT window), loaded into a fresh solver given
+    the same pulse and into the saved solver after it has run on: both end
+    with the field, the phasors and the far field of every wavenumber of the
+    uninterrupted run, bit for bit (sphere and box surfaces)."""
+    prob, V, psi0, delta = small_problem()
+    prob = prob.replace(surface_kind=surface_kind)
+    dirs = np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8], [0.0, -1.0, 0.0]])
+
+    def outputs(s):
+        out = [s.psi(0).cpu().numpy(), s.psi(1).cpu().numpy()]
+        for ik in range(len(KB)):
+            if surface_kind == 1:
+                out += [x.cpu().numpy() for x in s.sphere_phasors(ik)]
+            else:
+                out.append(s.phasors(ik).cpu().numpy())
+            out.append(s.far_field(dirs, ik=ik).cpu().numpy())
+        return out
+
+    a = P.Solver(prob)
+    a.set_potential(V)
+    a.set_pulse(psi0, delta, KB)
+    a.run(100)
+    a.run(50)
+    buf = a.save_state()
+    a.run(150)
+    want = outputs(a)
+    a.load_state(buf)
+    a.run(150)
+    again = outputs(a)
+    a.close()
+    b = P.Solver(prob)
+    b.set_potential(V)
+    b.set_pulse(psi0, delta, KB)
+    b.load_state(buf)
+    b.run(150)
+    got = outputs(b)
+    b.close()
+    for i, (x, y, z) in enumerate(zip(want, again, got)):
+        assert np.array_equal(x, y), i
+        assert np.array_equal(x, z), i
+
+
 def test_pulse_validation(P):
     prob, V, psi0, delta = small_problem(steps=20)
     s = P.Solver(prob)
@@ -171,10 +216,19 @@ def test_pulse_validation(P):
     with pytest.raises(P.PstdError) as e:
         s.set_pulse(psi0, delta, KB)
     assert e.value.name == "PSTD_ESTATE"
-    with pytest.raises(P.PstdError) as e:
-        s.save_state()
-    assert e.value.name == "PSTD_EUNSUPPORTED"
+    buf = s.save_state()
     s.close()
+    # a pulsed run's state does not load into a solver without the pulse,
+    # nor into one given another number of wavenumbers
+    for kbars in (None, KB[:2]):
+        s = P.Solver(prob)
+        s.set_potential(V)
+        if kbars is not None:
+            s.set_pulse(psi0, delta, kbars)
+        with pytest.raises(P.PstdError) as e:
+            s.load_state(buf)
+        assert e.value.name == "PSTD_EINVAL", kbars
+        s.close()
     for bad, name in ((dict(scheme=1), "PSTD_EUNSUPPORTED"),
                       (dict(sphere_radius=1.2), "PSTD_EINVAL")):  # 1.2: the shell reaches the taper
         s = P.Solver(prob.replace(**bad))
