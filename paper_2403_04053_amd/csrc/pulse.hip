@@ -119,20 +119,31 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
                                                         float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                         const int* __restrict__ list, int64_t n_shell,
                                                         float2* __restrict__ stage) {
-    const int64_t n = ctr[0] + koff;
-    if (n >= ctr[1]) return;
+    // the launch is bound by latency: what does not depend on the step (the
+    // cell and shell indices, the stencil weights) is loaded before the
+    // step counter, so that those loads and the counter's are in flight
+    // together
     const int blk = (int)blockIdx.x;
     if (blk >= table_blocks + source_blocks) {
         const int64_t c = (int64_t)(blk - table_blocks - source_blocks) * blockDim.x + threadIdx.x;
-        if (c < n_shell) stage[koff * n_shell + c] = ((n & 1) ? buf1 : buf0)[list[c]];
+        if (c >= n_shell) return;
+        const int src = list[c];
+        const int64_t n = ctr[0] + koff;
+        if (n >= ctr[1]) return;
+        stage[koff * n_shell + c] = ((n & 1) ? buf1 : buf0)[src];
         return;
     }
     if (blk >= table_blocks) {
         const int64_t c = (int64_t)(blk - table_blocks) * blockDim.x + threadIdx.x;
         if (c >= nc) return;
-        const double2* t = tab + (n & 1) * 2 * (int64_t)J;
         const int j = j0[c];
-        const double* wc = w + kLag * c;
+        const int cc = cell[c];
+        const double2 q = ab[c];
+        double wc[kLag];
+        for (int m = 0; m < kLag; ++m) wc[m] = w[kLag * c + m];
+        const int64_t n = ctr[0] + koff;
+        if (n >= ctr[1]) return;
+        const double2* t = tab + (n & 1) * 2 * (int64_t)J;
         double p0r = 0, p0i = 0, p1r = 0, p1i = 0;
         for (int m = 0; m < kLag; ++m) {
             const double2 t0 = t[j + m], t1 = t[J + j + m];
@@ -141,43 +152,65 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
             p1r += wc[m] * t1.x;
             p1i += wc[m] * t1.y;
         }
-        const double2 q = ab[c];
         // S = A T0 + B i T1; psi^{n-1} -= i S
         const double sr = q.x * p0r - q.y * p1i, si = q.x * p0i + q.y * p1r;
         float2* out = ((n + 1) & 1) ? buf1 : buf0;
-        float2 v = out[cell[c]];
+        float2 v = out[cc];
         v.x += (float)si;
         v.y -= (float)sr;
-        out[cell[c]] = v;
+        out[cc] = v;
         return;
     }
     // the next step's mode amplitudes a_l(m) = c_l e^{-i theta_l m}, once per
-    // block in LDS (chunks of kModeChunk modes); every wave of a table block
-    // takes part in the barriers, those past the table's end store nothing
-    const int64_t mstep = n + 1;
+    // block in LDS (chunks of kModeChunk = blockDim.x modes, one per thread);
+    // every wave of a table block takes part in the barriers, those past the
+    // table's end store nothing.  Each chunk's operands (the wave's row of
+    // e^{i k_l d_j}, theta_l, c_l) are loaded before anything waits: the
+    // first chunk's before the step counter is read.
+    constexpr int kPer = kModeChunk / 64;
     __shared__ double2 a_s[kModeChunk];
     const int lane = threadIdx.x & 63;
     const int jt = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const double2* e_j = ekd + (int64_t)min(jt, J - 1) * K;
+    double2 ev[kPer];
+    double th = 0;
+    double2 cf = make_double2(0, 0);
+    auto load_chunk = [&](int m0, int nm) {
+        for (int i = 0; i < kPer; ++i) {
+            const int l = lane + 64 * i;
+            ev[i] = l < nm ? e_j[m0 + l] : make_double2(0, 0);
+        }
+        if ((int)threadIdx.x < nm) {
+            th = theta[m0 + threadIdx.x];
+            cf = coef[m0 + threadIdx.x];
+        }
+    };
+    load_chunk(0, min(kModeChunk, K));
+    const int64_t n = ctr[0] + koff;
+    if (n >= ctr[1]) return;
+    const int64_t mstep = n + 1;
     double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
     for (int m0 = 0; m0 < K; m0 += kModeChunk) {
         const int nm = min(kModeChunk, K - m0);
+        if (m0 > 0) load_chunk(m0, nm);
         __syncthreads();
-        for (int e = threadIdx.x; e < nm; e += blockDim.x) {
+        if ((int)threadIdx.x < nm) {
             double sn, cs;
-            sincos(theta[m0 + e] * (double)mstep, &sn, &cs);
-            const double2 c = coef[m0 + e];
-            a_s[e] = make_double2(c.x * cs + c.y * sn, c.y * cs - c.x * sn);
+            sincos(th * (double)mstep, &sn, &cs);
+            a_s[threadIdx.x] = make_double2(cf.x * cs + cf.y * sn, cf.y * cs - cf.x * sn);
         }
         __syncthreads();
-        for (int l = lane; l < nm; l += 64) {
-            const double2 a = a_s[l], e = e_j[m0 + l];
-            const double tr = a.x * e.x - a.y * e.y, ti = a.x * e.y + a.y * e.x;
-            const double kl = k_lo + (m0 + l) * dk;
-            s0r += tr;
-            s0i += ti;
-            s1r += kl * tr;
-            s1i += kl * ti;
+        for (int i = 0; i < kPer; ++i) {
+            const int l = lane + 64 * i;
+            if (l < nm) {
+                const double2 a = a_s[l], e = ev[i];
+                const double tr = a.x * e.x - a.y * e.y, ti = a.x * e.y + a.y * e.x;
+                const double kl = k_lo + (m0 + l) * dk;
+                s0r += tr;
+                s0i += ti;
+                s1r += kl * tr;
+                s1i += kl * ti;
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -438,6 +471,7 @@ hipError_t pulse_launch_pre(const pstd_solver* s, int koff, const int* list, int
     const int source_blocks = koff >= 0 ? (int)((ps->n_cells + 255) / 256) : 0;
     const int stage_blocks = stage && koff >= 0 ? (int)((n_shell + 255) / 256) : 0;
     if (table_blocks + source_blocks + stage_blocks == 0) return hipSuccess;
+    static_assert(kModeChunk == 256, "a table block computes one mode amplitude per thread");
     hipLaunchKernelGGL(pulse_pre_kernel, dim3((unsigned)(table_blocks + source_blocks + stage_blocks)), dim3(256), 0,
                        stream, s->ctr, koff, ps->K, ps->coef, ps->theta, ps->k_lo, ps->dk, ps->J, ps->ekd, ps->tab,
                        table_blocks, ps->n_cells, ps->cell, ps->j0, ps->w, ps->ab, source_blocks, s->buf[0],
