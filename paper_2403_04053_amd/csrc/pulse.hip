@@ -229,30 +229,49 @@ __global__ __launch_bounds__(256) void pulse_pre_kernel(const int64_t* __restric
 // the staged plane values of the launch group's steps ctr[0] .. ctr[0] +
 // count - 1 into the FP64 plane sums of each wavenumber, in step order; one
 // thread per (side, field, plane point)
-__global__ void box_flush_kernel(const int64_t* __restrict__ ctr, int count, const int* __restrict__ dft_tab,
-                                 const double2* __restrict__ w_tab, int64_t wstride, int nk,
-                                 const float2* __restrict__ stage, int64_t points, double2* __restrict__ acc) {
-    const int64_t first = ctr[0];
+// the three axes' staged plane values and sums, one launch for all
+struct BoxFlush {
+    const float2* stage[3];
+    double2* acc[3];
+    int64_t points[3];
+    int blocks[3];
+};
+
+// one thread per (wavenumber, side, field, plane point): the group's staged
+// values are loaded before the step counter is read, then added in step
+// order to the compensated sums
+__global__ __launch_bounds__(256) void box_flush_kernel(const int64_t* __restrict__ ctr, int count,
+                                                        const int* __restrict__ dft_tab,
+                                                        const double2* __restrict__ w_tab, int64_t wstride, int nk,
+                                                        BoxFlush bf) {
+    int b = (int)blockIdx.x, a = 0;
+    while (a < 2 && b >= bf.blocks[a]) b -= bf.blocks[a++];
+    const int64_t points = bf.points[a];
+    const int64_t i = (int64_t)b * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nk * 4 * points) return;
+    const int f = (int)(i / (4 * points));
+    const int64_t r = i - (int64_t)f * 4 * points;
+    const int sf = (int)(r / points);  // side * 2 + field
+    const int64_t pt = r - (int64_t)sf * points;
+    float2 v[kStageSteps];
+#pragma unroll
+    for (int k = 0; k < kStageSteps; ++k)
+        v[k] = k < count ? bf.stage[a][((int64_t)k * 4 + sf) * points + pt] : make_float2(0.f, 0.f);
+    double2* S = bf.acc[a] + ((int64_t)f * 8 + (sf >> 1) * 4 + (sf & 1) * 2) * points + pt;
+    double2* Cc = S + points;
+    double2 s = *S, c = *Cc;
+    const int64_t first = ctr[0], end = ctr[1];
     bool any = false;
-    for (int k = 0; k < count; ++k) any |= first + k < ctr[1] && dft_tab[first + k] != 0;
-    if (!any) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 4 * points) return;
-    const int sf = (int)(i / points);  // side * 2 + field
-    const int64_t pt = i % points;
-    const int side = sf >> 1, fld = sf & 1;
-    for (int f = 0; f < nk; ++f) {
-        double2* S = acc + ((int64_t)f * 8 + side * 4 + fld * 2) * points + pt;
-        double2* Cc = S + points;
-        double2 s = *S, c = *Cc;
-        for (int k = 0; k < count; ++k) {
-            const int64_t m = first + k;
-            if (m >= ctr[1] || !dft_tab[m]) continue;
-            const float2 v = stage[((int64_t)k * 4 + sf) * points + pt];
-            const double2 w = w_tab[f * wstride + m];
-            neumaier(s.x, c.x, w.x * v.x - w.y * v.y);
-            neumaier(s.y, c.y, w.x * v.y + w.y * v.x);
-        }
+#pragma unroll
+    for (int k = 0; k < kStageSteps; ++k) {
+        const int64_t m = first + k;
+        if (k >= count || m >= end || !dft_tab[m]) continue;
+        any = true;
+        const double2 w = w_tab[f * wstride + m];
+        neumaier(s.x, c.x, w.x * v[k].x - w.y * v[k].y);
+        neumaier(s.y, c.y, w.x * v[k].y + w.y * v[k].x);
+    }
+    if (any) {
         *S = s;
         *Cc = c;
     }
@@ -560,12 +579,18 @@ hipError_t pulse_launch_box_flush(const pstd_solver* s, int count, hipStream_t s
     const PulseState* ps = s->pulse;
     if (!ps || !ps->box) return hipSuccess;
     if (count < 1 || count > kStageSteps) return hipErrorInvalidValue;
+    const int nk = (int)ps->kbar.size();
+    BoxFlush bf{};
+    int blocks = 0;
     for (int a = 0; a < 3; ++a) {
-        const int64_t n = 4 * s->points[a];
-        hipLaunchKernelGGL(box_flush_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, s->ctr, count,
-                           s->dft_tab, s->w_tab, s->tab_cap, (int)ps->kbar.size(), ps->bstage[a], s->points[a],
-                           ps->bacc[a]);
+        bf.stage[a] = ps->bstage[a];
+        bf.acc[a] = ps->bacc[a];
+        bf.points[a] = s->points[a];
+        bf.blocks[a] = (int)((nk * 4 * s->points[a] + 255) / 256);
+        blocks += bf.blocks[a];
     }
+    hipLaunchKernelGGL(box_flush_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s->ctr, count, s->dft_tab,
+                       s->w_tab, s->tab_cap, nk, bf);
     return hipGetLastError();
 }
 
