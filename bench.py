@@ -548,7 +548,7 @@ def bench_subdomain(args):
 
 
 def bench_fdtd(args):
-    """The eighth-order FDTD variant of the step (Section 2.3) on the 160^3
+    """The eighth-order FDTD variant of the step (Section 2.2.1) on the 160^3
     square-barrier grid (same physics, TF/SF box, absorber), no surface DFT:
     one stencil kernel per step.  Its algorithmic bytes are the step's floor,
     28 B/cell (read psi^n, psi^{n-1}, V; write psi^{n+1})."""

@@ -104,7 +104,7 @@ typedef struct pstd_problem {
     double  abc_UR;
     double  abc_alphaR;
     /* Step scheme.  0: the spectral step of Eq. PSTDupdating.  1: the FDTD
-     * variant of Section 2.3: the eighth-order central stencil of Eq.
+     * variant of Section 2.2.1: the eighth-order central stencil of Eq.
      * y_stencil (Eq. stencil_alpha) on the periodic grid, Eq.
      * FDTDupdatePsi with V multiplying psi^n, no eta correction, a sharp
      * total-field box y1 <= i <= y2 per axis whose walls carry the
@@ -268,7 +268,7 @@ pstd_status pstd_project(pstd_solver* s, const double* obs_xyz_dev, int64_t n_ob
 pstd_status pstd_far_field(pstd_solver* s, const double* dir_dev, int64_t n_dir, double* f_out_dev);
 
 /*
- * Pulsed (broadband) incidence: Section 2.4, calculation of the incident
+ * Pulsed (broadband) incidence: Section 2.2.3, calculation of the incident
  * wave (Eqs. Oinc, inc_d, pstd_psiinc, pstd_dpsiinc), and Section 3.3 with
  * several frequencies (Eqs. psiphasor-scaleddpsiphasor repeated per
  * frequency).

@@ -1,4 +1,4 @@
-"""FP64 oracle of the FDTD variant of the internal model (Section 2.3, FDTD
+"""FP64 oracle of the FDTD variant of the internal model (Section 2.2.1, FDTD
 version of TF/SF).  Test infrastructure only: imported by tests, never by
 the product.
 

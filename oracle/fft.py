@@ -8,14 +8,45 @@ inverse (1/N) sum_m X_m exp(+2 pi i j m/N).
   fft        radix-2 recursion for N = 2^p, Bluestein's chirp-z (built on the
              radix-2 transform) for every other N, the naive sum for N <= 8.
 
-A module switch lets long physics runs use numpy's pocketfft as the FFT step
-(same definition); the default is the library-free transform.
+A backend switch lets long physics runs take the FFT step from a library
+(SciPy's pocketfft, same definition, optionally threaded over the batch of
+pencils); the default is the library-free transform, which the tests pin to
+the definition and to the library.
+
+    with fft.backend("pocketfft", workers=16):
+        ...   # every transform of the oracle inside goes through the library
 """
 from __future__ import annotations
 
+import contextlib
+
 import numpy as np
 
-USE_NUMPY_FFT = False
+BACKENDS = ("library-free", "pocketfft")
+_backend = {"name": "library-free", "workers": 1}
+
+
+def get_backend():
+    """(name, workers) of the transform in use."""
+    return _backend["name"], _backend["workers"]
+
+
+def set_backend(name, workers=1):
+    if name not in BACKENDS:
+        raise ValueError(f"unknown FFT backend {name!r}")
+    _backend["name"] = name
+    _backend["workers"] = max(1, int(workers))
+
+
+@contextlib.contextmanager
+def backend(name, workers=1):
+    """Use `name` for every transform inside the block, then restore."""
+    old = get_backend()
+    set_backend(name, workers)
+    try:
+        yield
+    finally:
+        set_backend(*old)
 
 
 def naive_dft(x, axis=-1, inverse=False):
@@ -62,8 +93,10 @@ def _bluestein(x, sign):
 
 def _lastaxis(x, sign):
     N = x.shape[-1]
-    if USE_NUMPY_FFT:
-        return np.fft.fft(x, axis=-1) if sign < 0 else np.fft.ifft(x, axis=-1) * N
+    if _backend["name"] == "pocketfft":
+        import scipy.fft as sfft
+        w = _backend["workers"]
+        return sfft.fft(x, axis=-1, workers=w) if sign < 0 else sfft.ifft(x, axis=-1, workers=w) * N
     if N <= 8:
         W = np.exp(sign * 2j * np.pi * (np.outer(np.arange(N), np.arange(N)) % N) / N)
         return x @ W

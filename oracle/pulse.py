@@ -1,7 +1,7 @@
 """FP64 oracle of pulsed (broadband) incidence.  Test infrastructure only:
 imported by tests, never by the product.
 
-Section 2.4, calculation of the incident wave: a plane-wave packet of any
+Section 2.2.3, calculation of the incident wave: a plane-wave packet of any
 shape reaches the transition layer; since cells on one wavefront share its
 value, the packet is a 1D problem along k_hat, solved in free space next to
 the 3D model and deployed to the layer each step.  The 1D axis starts at the
@@ -33,6 +33,7 @@ import math
 
 import numpy as np
 
+from . import fft as _fft
 from . import pstd as _pstd
 
 
@@ -63,11 +64,11 @@ class Pulse1D:
         if np.max(dtau * eta * self.k ** 2) >= 1.0:
             raise ValueError("the 1D grid holds modes beyond the leapfrog's bound")
         th = scheme_frequency(self.k, dtau, eta) * dtau
-        self.prev = np.fft.ifft(np.exp(1j * th) * np.fft.fft(self.psi0))
+        self.prev = _fft.ifft(np.exp(1j * th) * _fft.fft(self.psi0))
         self.cur = self.psi0.copy()
 
     def step(self):
-        lap = np.fft.ifft(self.k ** 2 * np.fft.fft(self.cur))
+        lap = _fft.ifft(self.k ** 2 * _fft.fft(self.cur))
         nxt = self.prev - 2j * self.eta * self.dtau * lap
         self.prev, self.cur = self.cur, nxt
 
@@ -75,7 +76,7 @@ class Pulse1D:
         """Eqs. pstd_psiinc and pstd_dpsiinc: the packet and its derivative
         along the axis at the points d (any shape)."""
         d = np.asarray(d, dtype=np.float64)
-        F = np.fft.fft(self.cur)
+        F = _fft.fft(self.cur)
         E = np.exp(1j * np.multiply.outer(d.reshape(-1), self.k))
         psi = (E @ F) / self.N
         dpsi = (E @ (1j * self.k * F)) / self.N

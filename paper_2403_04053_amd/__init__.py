@@ -558,6 +558,8 @@ class Solver:
         tgt = torch.as_tensor(target, dtype=torch.float64, device=self.device).contiguous()
         if n_checkpoints is None:
             n_checkpoints = max(1, math.ceil(math.sqrt(n_steps)))
+        # the library keeps one misfit run per solver: a new run replaces it
+        self._misfit_run = getattr(self, "_misfit_run", 0) + 1
         return pstd_misfit_forward(self.handle, n_steps, pts, pts.shape[0], tgt, n_checkpoints)
 
     def misfit_gradient(self):
@@ -582,10 +584,16 @@ def _fresnel_misfit_class():
             solver.set_potential(V.detach())
             J = solver.misfit(n_steps, points, target, n_checkpoints)
             ctx.solver = solver
+            ctx.run = solver._misfit_run
             return torch.tensor(J, dtype=torch.float64, device=V.device)
 
         @staticmethod
         def backward(ctx, grad_out):
+            # the solver holds only its latest misfit run's checkpoints: a
+            # later forward on the same solver would answer for another V
+            if getattr(ctx.solver, "_misfit_run", None) != ctx.run:
+                raise RuntimeError("FresnelMisfit.backward: the solver has run another misfit since this "
+                                   "forward; use one solver per misfit term of a graph")
             g = ctx.solver.misfit_gradient()
             return (g * grad_out.to(g.dtype)).reshape(g.shape), None, None, None, None, None
 

@@ -1,4 +1,4 @@
-// FDTD variant of the step (Section 2.3): the eighth-order central stencil of
+// FDTD variant of the step (Section 2.2.1; its bound Section 2.3.1): the eighth-order central stencil of
 // Eq. y_stencil (coefficients of Eq. stencil_alpha) along every axis, the
 // central-difference update of Eq. FDTDupdatePsi with the potential, the
 // wall consistency terms of Eqs. FDTDpsi_extraJminus1-FDTDpsiJplus4 and the

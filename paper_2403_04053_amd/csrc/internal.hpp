@@ -58,7 +58,7 @@ struct PassArgs {
     float2* const* stash_tab;
 };
 
-// One FDTD-variant step (eighth-order stencil, Section 2.3) for one solver:
+// One FDTD-variant step (eighth-order stencil, Section 2.2.1) for one solver:
 // psi^{n+1} = Gamma (psi^{n-1} - i q), q = kc psi + sum_a sum_l k[a][l-1]
 // (psi(-l e_a) + psi(+l e_a)) + v2 psi + sigma_n sum_a dz_a prod_{b != a} zt_b
 struct FdtdArgs {

@@ -1,4 +1,4 @@
-// Pulsed incidence (Section 2.4, calculation of the incident wave; Section
+// Pulsed incidence (Section 2.2.3, calculation of the incident wave; Section
 // 3.3 at several frequencies).  A plane-wave packet of any shape travels
 // along k_hat; cells on one wavefront share its value, so the packet is a 1D
 // problem on the axis that starts at the corner of the taper box the front

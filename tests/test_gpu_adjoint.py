@@ -136,6 +136,26 @@ def test_autograd_function(P, setup):
     s.close()
 
 
+def test_autograd_refuses_a_replaced_misfit_run(P, setup):
+    """Two misfit terms on one solver: the first term's backward would read
+    the second run's checkpoints, so it raises; one solver per term works."""
+    prob, V, pts, target, _, g_ref = setup
+    s = P.Solver(prob)
+    V1 = torch.tensor(V, dtype=torch.float32, device="cuda", requires_grad=True)
+    J1 = P.FresnelMisfit.apply(V1, s, N_STEPS, pts, target, 5)
+    J2 = P.FresnelMisfit.apply(V1 * 0.5, s, N_STEPS, pts, target, 5)
+    with pytest.raises(RuntimeError, match="another misfit"):
+        (J1 + J2).backward()
+    s.close()
+    s1, s2 = P.Solver(prob), P.Solver(prob)
+    V2 = torch.tensor(V, dtype=torch.float32, device="cuda", requires_grad=True)
+    J = P.FresnelMisfit.apply(V2, s1, N_STEPS, pts, target, 5) + P.FresnelMisfit.apply(V2, s2, N_STEPS, pts, target, 5)
+    J.backward()
+    assert rel_l2(V2.grad.cpu().numpy().astype(np.float64), 2.0 * g_ref) <= 1e-3
+    s1.close()
+    s2.close()
+
+
 def test_gradient_matches_gpu_finite_differences(P, setup):
     """Central differences of the GPU misfit itself at core voxels where the
     gradient is large (FP32 forward runs: a large step, 2e-2 E0)."""

@@ -1,4 +1,4 @@
-"""GPU parity of the FDTD variant (Section 2.3: eighth-order stencil, wall
+"""GPU parity of the FDTD variant (Section 2.2.1, bound of Section 2.3.1: eighth-order stencil, wall
 consistency terms, mask) against the FP64 oracle `oracle/fdtd.py`, through
 the C ABI, and its far field through the spherical surface.  Tolerances as
 for the spectral step: one FP32 step within 1e-5 of max|psi|, runs and

@@ -1,4 +1,4 @@
-"""GPU parity of pulsed incidence (Section 2.4, calculation of the incident
+"""GPU parity of pulsed incidence (Section 2.2.3, calculation of the incident
 wave; Section 3.3 with several frequencies) against the FP64 oracle
 `oracle/pulse.py`, through the C ABI, and the far field of one pulsed run
 at several wavenumbers against the partial-wave series."""

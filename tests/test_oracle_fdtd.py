@@ -1,4 +1,4 @@
-"""Pins of the FDTD-variant oracle (Section 2.3: Eqs. y_stencil,
+"""Pins of the FDTD-variant oracle (Section 2.2.1, bound of Section 2.3.1: Eqs. y_stencil,
 stencil_alpha, FDTDupdatePsi and the consistency terms of the walls)."""
 import math
 

@@ -1,5 +1,7 @@
 """Pins of the oracle's library-free FFTs against the DFT definition, an
-independent library (numpy's pocketfft), Parseval and the round trip."""
+independent library (numpy's pocketfft), Parseval and the round trip; and of
+the library backend (SciPy's pocketfft, threaded) that long runs may select,
+against the library-free transform and the definition."""
 import numpy as np
 import pytest
 
@@ -41,3 +43,25 @@ def test_fft_along_axis():
     for ax in range(3):
         assert np.allclose(fft.fft(x, axis=ax), np.fft.fft(x, axis=ax), atol=1e-12)
         assert np.allclose(fft.ifft(x, axis=ax), np.fft.ifft(x, axis=ax), atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [12, 48, 160, 288])
+@pytest.mark.parametrize("workers", [1, 4])
+def test_library_backend_matches_library_free(N, workers):
+    rng = np.random.default_rng(N + workers)
+    x = rng.normal(size=(5, 3, N)) + 1j * rng.normal(size=(5, 3, N))
+    ref_f, ref_i = fft.fft(x, axis=2), fft.ifft(x, axis=0)
+    assert fft.get_backend() == ("library-free", 1)
+    with fft.backend("pocketfft", workers=workers):
+        assert fft.get_backend() == ("pocketfft", workers)
+        got_f, got_i = fft.fft(x, axis=2), fft.ifft(x, axis=0)
+    assert fft.get_backend() == ("library-free", 1)
+    assert np.abs(got_f - ref_f).max() <= 1e-12 * np.abs(ref_f).max()
+    assert np.abs(got_i - ref_i).max() <= 1e-12 * np.abs(ref_i).max()
+    # and against the definition directly
+    assert np.abs(got_f - fft.naive_dft(x, axis=2)).max() <= 1e-12 * np.abs(ref_f).max()
+
+
+def test_unknown_backend_is_refused():
+    with pytest.raises(ValueError):
+        fft.set_backend("fftw")

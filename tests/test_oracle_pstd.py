@@ -145,6 +145,64 @@ def test_tfsf_reproduces_incident_wave_without_potential():
     assert np.abs(cur).max() > 0.5
 
 
+def test_source_is_laplacian_of_product_minus_product_of_laplacian():
+    """The source of Eq. dimlesstildeSchrodinger is what the taper adds to the
+    free equation: S = lap(zeta psi_inc) - zeta lap(psi_inc).  Check it at
+    every wall cell of an oblique-incidence grid against that right-hand
+    side differentiated numerically (Richardson-extrapolated central
+    differences of the continuous taper of Eq. zeta_y times the plane wave),
+    so a wrong coefficient, sign, index shift or length scale in the
+    oracle's analytic derivatives fails by O(1)."""
+    prob, V = synth.tiny(n=(24, 20, 28), P=3, transition=4, theta=0.7, phi=2.1, v0=0.0, radius_cells=0)
+    prob = prob.replace(ramp_periods=0.0)
+    m = pstd.build(prob, V)
+    dxb = m.dxb
+    kh = m.kh
+
+    def zeta_c(a, u):
+        """Eq. zeta_y at the continuous index position u of axis a."""
+        y0, y1, y2, y3 = prob.tfsf[a]
+        if u <= y0 or u >= y3:
+            return 0.0
+        if u < y1:
+            return float(pstd.xi((u - y0) / (y1 - y0)))
+        if u <= y2:
+            return 1.0
+        return 1.0 - float(pstd.xi((u - y2) / (y3 - y2)))
+
+    def f(xb):
+        """zeta(x_bar) exp(i k_hat . x_bar) at a reduced position."""
+        z = 1.0
+        for a in range(3):
+            z *= zeta_c(a, xb[a] / dxb[a] + prob.n[a] // 2)
+        return z * np.exp(1j * float(np.dot(kh, xb)))
+
+    def lap(xb, h):
+        out = 0.0
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            out += (f(xb + e) - 2 * f(xb) + f(xb - e)) / h ** 2
+        return out
+
+    n = 123
+    S = pstd.source(m, n) / np.exp(-1j * n * m.dtau)   # ramp off: R = 1
+    wall = (m.zeta > 0) & (m.zeta < 1)
+    ks, js, is_ = np.nonzero(wall)
+    rng = np.random.default_rng(8)
+    pick = rng.choice(ks.size, size=60, replace=False)
+    smax = np.abs(S).max()
+    worst = 0.0
+    for p_ in pick:
+        k, j, i = ks[p_], js[p_], is_[p_]
+        xb = np.array([(i - prob.n[0] // 2) * dxb[0], (j - prob.n[1] // 2) * dxb[1], (k - prob.n[2] // 2) * dxb[2]])
+        h = 4e-3
+        d = (4 * lap(xb, h / 2) - lap(xb, h)) / 3
+        expect = d - f(xb) * (-1.0)            # lap(psi_inc) = -|k_hat|^2 psi_inc
+        worst = max(worst, abs(S[k, j, i] - expect) / smax)
+    assert worst < 1e-6, worst
+
+
 def test_surface_dft_of_monochromatic_field():
     """psi^n = A exp(-i tau_n) over M steps gives Phi = M A; the normalised
     phasor (incident phasor at the origin, R = 1) is A."""

@@ -1,4 +1,4 @@
-"""Pins of the pulsed-incidence oracle (Section 2.4, calculation of the
+"""Pins of the pulsed-incidence oracle (Section 2.2.3, calculation of the
 incident wave: Eqs. Oinc, inc_d, pstd_psiinc, pstd_dpsiinc; Section 3.3
 phasors at several frequencies)."""
 import math
