@@ -110,6 +110,11 @@ def main():
                     help="single: equivalence surface (sphere r = 5 with a shell DFT, or the box planes at "
                          "N/2 -+ 40 with the plane sums inside the passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="single: skip the whole-grid comparison with the FP64 oracle (and the CPU baseline)")
+    ap.add_argument("--parity-steps", type=int, default=64,
+                    help="single: steps of the whole-grid comparison with the FP64 oracle")
+    ap.add_argument("--no-288", action="store_true", help="single: skip the 288^3 line beside the 160^3 one")
     ap.add_argument("--workload", choices=["single", "batch", "adjoint", "project", "subdomain", "x3", "fdtd", "pulse"],
                     default="single",
                     help="single: the 160^3 square-barrier solve; batch: 64 uneven instances in one batch; "
@@ -194,7 +199,11 @@ def main():
     # bracketed by HIP events on the solver's stream (the in-step events
     # above also hold the dispatch gap between kernels)
     dom_us = s.pass_time("xyz".index(dom), reps=100)
-    achieved = PASS_BYTES[dom] * cells / (dom_us / 1e6) / 1e9
+    # algorithmic bytes: the step's 28 B per cell-update (read psi^{n-1},
+    # psi^n, V; write psi^{n+1}) over the dominant kernel's launch; the
+    # kernel's own inputs and outputs (PASS_BYTES) are reported beside it
+    achieved = STEP_BYTES * cells / (dom_us / 1e6) / 1e9
+    own = PASS_BYTES[dom] * cells / (dom_us / 1e6) / 1e9
     finite = bool(torch.isfinite(torch.view_as_real(s.psi(0))).all().item())
 
     out = {
@@ -226,8 +235,11 @@ def main():
             # the counters were taken on the sphere workload, whose passes carry no plane sums
             "traffic": (measured_traffic(tuple(tiles["xyz".index(dom)]), "xyz".index(dom))
                         if args.surface == "sphere" else None),
-            "bytes_per_cell": PASS_BYTES[dom],
+            "bytes_per_cell": STEP_BYTES,
             "kernel_us": round(dom_us, 3),
+            "own_bytes_per_cell": PASS_BYTES[dom],
+            "own_achieved": round(own, 1),
+            "own_frac": round(own / HBM_PEAK_GBS, 4),
             "pass_ms_in_steps": {k: round(v, 5) for k, v in avg.items()},
             "tiles": {k: list(tiles[i]) for i, k in enumerate("xyz")},
             "step_frac_28B": round(STEP_BYTES * cells / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -239,9 +251,133 @@ def main():
         "finite": finite,
     }
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, V)
+    if not args.no_parity:
+        # validity of the timed configuration: a whole-grid comparison with the
+        # FP64 oracle over a few steps of this solver (the oracle's time is
+        # the CPU baseline)
+        parity, base = oracle_parity(s, prob, V, n0=3000, k_steps=args.parity_steps,
+                                     with_baseline=not args.no_cpu_baseline)
+        out["parity"] = parity
+        out["valid"] = parity["ok"] and finite
+        if base is not None:
+            out["cpu_baseline"] = base
+    s.close()
+    del s
+    if args.n == 160 and not args.no_288:
+        out["hbm_resident_288"] = step_288(args, stream)
     print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    """(CPU model, logical CPUs of the machine, CPUs this process may use,
+    threads the oracle's library transform uses)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(usable, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else usable
+    return model, os.cpu_count(), usable, threads
+
+
+def oracle_parity(s, prob, V, n0, k_steps, with_baseline):
+    """Run k_steps of the benchmarked solver from a seeded state at step n0
+    (source at full amplitude) and the same steps of the FP64 oracle; the
+    whole-grid relative L2 difference of psi must be <= 1e-4.  The oracle's
+    steps, timed on all usable host cores (library FFT threaded over the
+    pencils), are the CPU baseline; one more step on one thread is reported
+    beside it."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fft as offt
+    from oracle import pstd as opstd
+    import synth
+    V32 = np.asarray(V, dtype=np.float32).astype(np.float64)   # what the solver holds
+    prev = synth.random_state(prob.n, 31).astype(np.complex64)
+    cur = synth.random_state(prob.n, 32).astype(np.complex64)
+    s.set_state(prev, cur, n0)
+    s.run(k_steps)
+    got = s.psi(0).cpu().numpy()
+    model, ncpu, usable, threads = host_cpu()
+    m = opstd.build(prob, V32)
+    a, b = prev.astype(np.complex128), cur.astype(np.complex128)
+    with offt.backend("pocketfft", workers=threads):
+        t0 = time.perf_counter()
+        for k in range(k_steps):
+            a, b = b, opstd.step(m, a, b, n0 + k)
+        dt = time.perf_counter() - t0
+    rel = float(np.linalg.norm(got - b) / np.linalg.norm(b))
+    parity = {"psi_rel_l2": rel, "bar": 1e-4, "ok": bool(rel <= 1e-4), "steps": k_steps, "from_step": n0,
+              "state": "seeded complex normal psi^{n0-1}, psi^n0 (seeds 31, 32), rounded to complex64",
+              "oracle": "FP64 numpy, FFT step from SciPy pocketfft"}
+    if not with_baseline:
+        return parity, None
+    with offt.backend("pocketfft", workers=1), threadpool_limits(1):
+        t1 = time.perf_counter()
+        opstd.step(m, prev.astype(np.complex128), cur.astype(np.complex128), n0)
+        dt1 = time.perf_counter() - t1
+    base = {
+        "value": round(prob.cells * k_steps / dt / 1e9, 6),
+        "unit": "Gcell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{k_steps} leapfrog steps of the {prob.n[0]}^3 grid from step {n0} (FP64 numpy oracle, "
+                  f"FFT step from pocketfft with {threads} threads; elementwise work on one thread), {dt:.2f} s; "
+                  f"these steps are also the parity check",
+        "single_thread_value": round(prob.cells / dt1 / 1e9, 6),
+        "cpu_model": model,
+        "nproc": ncpu,
+        "usable_cpus": usable,
+    }
+    return parity, base
+
+
+def step_288(args, stream):
+    """The same workload on a 288^3 FFT grid (256^3 inside the absorber,
+    669 MB working set: beyond the 256 MB Infinity Cache, so the passes move
+    their bytes to and from HBM), timed like the main line."""
+    import torch
+
+    import paper_2403_04053_amd as P
+    import synth
+    prob, V = synth.square_barrier_160(n_fft=288)
+    prob = prob.replace(dft_begin=0, dft_end=10 ** 12, surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
+    s = P.Solver(prob, stream=stream)
+    s.set_potential(V)
+    tiles = s.autotune(reps=10)
+    steps = 100
+    s.run(16)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    us = {k: s.pass_time(i, reps=50) for i, k in enumerate("xyz")}
+    dom = max(us, key=us.get)
+    out = {
+        "grid": [288] * 3,
+        "value": round(prob.cells / (ms / 1e3) / 1e9, 3),
+        "unit": "Gcell-updates/s",
+        "ms_per_step": round(ms, 5),
+        "step_frac_28B": round(STEP_BYTES * prob.cells / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "pass_us": {k: round(v, 2) for k, v in us.items()},
+        "dominant": f"pass_{dom}",
+        "frac_28B": round(STEP_BYTES * prob.cells / (us[dom] / 1e6) / 1e9 / HBM_PEAK_GBS, 4),
+        "own_frac": round(PASS_BYTES[dom] * prob.cells / (us[dom] / 1e6) / 1e9 / HBM_PEAK_GBS, 4),
+        "tiles": {k: list(tiles[i]) for i, k in enumerate("xyz")},
+    }
+    s.close()
+    return out
 
 
 def bench_batch(args):
@@ -749,31 +885,6 @@ def bench_project(args):
         "fp64_mfma_peak_tflops": 78.6,
     }
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline(prob, V):
-    """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: one full step of the 160^3 grid."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle import pstd as opstd
-    import synth
-    m = opstd.build(prob, V)
-    prev = np.zeros((prob.n[2], prob.n[1], prob.n[0]), np.complex128)
-    cur = synth.random_state(prob.n, 1)
-    with threadpool_limits(1):  # the library calls inside numpy stay on one thread
-        t0 = time.perf_counter()
-        opstd.step(m, prev, cur, 100)
-        dt = time.perf_counter() - t0
-    return {
-        "value": round(prob.cells / dt / 1e9, 6),
-        "unit": "Gcell-updates/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"1 leapfrog step of the {prob.n[0]}^3 grid (FP64 numpy, library-free Bluestein/radix-2 FFT, "
-                  f"single-threaded; host has {os.cpu_count()} logical CPUs), {dt:.2f} s",
-    }
 
 
 def cpu_baseline_fdtd(prob, V):
