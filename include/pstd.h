@@ -185,6 +185,18 @@ pstd_status pstd_autotune(pstd_solver* s, int32_t reps);
  * bound of Eq. PSTDstability with force_dt).  Synchronises. */
 pstd_status pstd_check_state(pstd_solver* s, double* norm2_out_host);
 
+/* pstd_check_state for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same result, errors
+ * and synchronisation, with the reduction's partial sums in a fixed device
+ * array of 4096 doubles (32 KiB) per device, which the library holds until
+ * the process ends, instead of a buffer allocated and freed per call.  Calls
+ * no hipMalloc, hipFree or other allocating routine (the array's address on
+ * each device is looked up once, by pstd_create on that device).  Calls on
+ * one device share its array: the library serialises them with a lock held
+ * until the result is read (overlapping uses of one device's array would
+ * race).  EINVAL if the reduction needed more than the array holds. */
+pstd_status pstd_check_state_noalloc(pstd_solver* s, double* norm2_out_host);
+
 /* Average duration (microseconds) of one launch of the pass along `axis`
  * with its current tile shape: `reps` back-to-back launches on scratch
  * buffers of the solver's size, bracketed by HIP events on the solver's

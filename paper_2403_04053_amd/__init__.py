@@ -16,7 +16,7 @@ __all__ = [
     "pstd_set_potential", "pstd_set_state", "pstd_run", "pstd_run_timed", "pstd_step_index",
     "pstd_get_psi", "pstd_surface_size", "pstd_get_surface_phasors", "pstd_project",
     "pstd_far_field", "pstd_set_pulse", "pstd_get_surface_phasors_k", "pstd_get_sphere_phasors_k", "pstd_project_k", "pstd_far_field_k",
-    "pstd_pass_time", "pstd_check_state", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
+    "pstd_pass_time", "pstd_check_state", "pstd_check_state_noalloc", "pstd_sphere_size", "pstd_get_sphere_phasors", "pstd_state_size", "pstd_save_state", "pstd_load_state", "pstd_misfit_forward", "pstd_misfit_backward", "FresnelMisfit", "pstd_destroy", "pstd_autotune", "pstd_tile_info", "pstd_set_tile",
     "pstd_tile_variants", "pstd_batch_create",
     "pstd_batch_size", "pstd_batch_solver", "pstd_batch_set_potential", "pstd_batch_autotune",
     "pstd_batch_run", "pstd_batch_destroy", "pstd_batch_last_error", "Batch", "pstd_status_string", "pstd_last_error", "Solver",
@@ -151,6 +151,7 @@ _SIGS = {
     "pstd_autotune": [_vp, ctypes.c_int32],
     "pstd_pass_time": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pstd_check_state": [_vp, ctypes.POINTER(ctypes.c_double)],
+    "pstd_check_state_noalloc": [_vp, ctypes.POINTER(ctypes.c_double)],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "pstd_set_tile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "pstd_tile_variants": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
@@ -341,6 +342,12 @@ def pstd_misfit_backward(solver, out_dev, n_cells):
 def pstd_check_state(solver):
     out = ctypes.c_double()
     _check(lib.pstd_check_state(solver, ctypes.byref(out)), solver)
+    return out.value
+
+
+def pstd_check_state_noalloc(solver):
+    out = ctypes.c_double()
+    _check(lib.pstd_check_state_noalloc(solver, ctypes.byref(out)), solver)
     return out.value
 
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,28 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kGraphSteps = 16;  // steps per replayed graph
 
 thread_local std::string g_create_error;
+
+// Device scratch of pstd_check_state_noalloc: the two FP64 norm reductions
+// (result and per-workgroup partials of each).  One copy per device, held
+// until the process ends; host code uses only the address each device
+// reports for it (g_scratch_dev), never the array's name.
+constexpr int kStaticScratchDoubles = 4096;  // 32 KiB
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+std::mutex g_scratch_mu;                      // one user of the array at a time
+double* g_scratch_dev[kMaxDevices] = {};      // its address on each device
+
+// Look up the array's address on `device`, which must be current; once per device.
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
 
 pstd_status fail(pstd_solver* s, pstd_status st, const std::string& msg) {
     if (s) s->err = msg;
@@ -589,6 +612,8 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
         return e;
     };
     hipError_t e;
+    // the first device call: set-up of this device's static scratch
+    if ((e = static_scratch_init(s->device))) return cleanup(hip_fail(s, e, "static scratch address"));
     if ((e = hipMalloc(&s->buf[0], s->cells * sizeof(float2))) || (e = hipMalloc(&s->buf[1], s->cells * sizeof(float2))) ||
         (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))))
         return cleanup(hip_fail(s, e, "hipMalloc state"));
@@ -902,23 +927,53 @@ pstd_status pstd_run_timed(pstd_solver* s, int64_t n_steps, double* pass_ms) {
     return st;
 }
 
-pstd_status pstd_check_state(pstd_solver* s, double* norm2_out) {
-    if (!s || !norm2_out) return PSTD_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The FP64 norms of psi^n and psi^{n-1} through `d` (2 norm_scratch_doubles()
+// doubles of device memory); synchronises the solver's stream.
+pstd_status check_state_with(pstd_solver* s, double* d, double* norm2_out) {
     const int m = norm_scratch_doubles();
-    double* d = nullptr;
-    HIP_TRY(s, hipMalloc(&d, 2 * m * sizeof(double)));
     double h[2] = {0, 0};
     hipError_t e = launch_norm(s->buf[s->step & 1], s->cells, d, s->stream);          // psi^n
     if (!e) e = launch_norm(s->buf[(s->step + 1) & 1], s->cells, d + m, s->stream);   // psi^{n-1}
     if (!e) e = hipMemcpyAsync(&h[0], d, sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (!e) e = hipMemcpyAsync(&h[1], d + m, sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (!e) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(d);
     if (e) return hip_fail(s, e, "state check");
     *norm2_out = h[0];
     if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
         return fail(s, PSTD_ENONFINITE, "the wave function holds NaN or Inf values");
     return PSTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pstd_status pstd_check_state(pstd_solver* s, double* norm2_out) {
+    if (!s || !norm2_out) return PSTD_EINVAL;
+    double* d = nullptr;
+    HIP_TRY(s, hipMalloc(&d, 2 * norm_scratch_doubles() * sizeof(double)));
+    const pstd_status st = check_state_with(s, d, norm2_out);
+    (void)hipFree(d);
+    return st;
+}
+
+pstd_status pstd_check_state_noalloc(pstd_solver* s, double* norm2_out) {
+    if (!s || !norm2_out) return PSTD_EINVAL;
+    const int need = 2 * norm_scratch_doubles();
+    if (need > kStaticScratchDoubles)
+        return fail(s, PSTD_EINVAL, "state check: the reduction needs " + std::to_string(need) +
+                                        " doubles of scratch, more than the static " +
+                                        std::to_string(kStaticScratchDoubles));
+    if (s->device < 0 || s->device >= kMaxDevices) return fail(s, PSTD_EINVAL, "state check: device out of range");
+    // one call at a time in this process uses a device's array
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    double* d = g_scratch_dev[s->device];
+    if (!d) return fail(s, PSTD_ESTATE, "state check: no static scratch address for this device");
+    return check_state_with(s, d, norm2_out);
 }
 
 pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* us_out) {
