@@ -21,9 +21,10 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell of each pass kernel (its own inputs and outputs,
-# each touched once): x reads psi^n, writes L; y reads psi^n and L, writes L;
-# z reads psi^n, L, psi^{n-1}, V and writes psi^{n+1}
-PASS_BYTES = {"x": 16, "y": 24, "z": 36}
+# each touched once): x reads psi^n, writes L (with the potential term; V is
+# read only on the taper's core box, 0.1 B per cell of the 160^3 grid); y
+# reads psi^n and L, writes L; z reads psi^n, L, psi^{n-1} and writes psi^{n+1}
+PASS_BYTES = {"x": 16, "y": 24, "z": 32}
 STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 
 # HBM traffic per launch of the pass kernels on the 160^3 workload below, from

@@ -168,21 +168,31 @@ std::vector<double> absorber_real(const pstd_problem& p, int a) {
     return w;
 }
 
-// v2 = 2 dtau (V / E0 + sum_a w_a) per cell, V in energy units (null: V = 0)
+// The box where V may be non-zero: the taper's core y1 <= i <= y2 per axis
+// (Section 2.2.2: (zeta - 1) V = 0)
+void potential_box(const pstd_problem& p, int lo[3], int n[3]) {
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = p.tfsf[a][1];
+        n[a] = p.tfsf[a][2] - p.tfsf[a][1] + 1;
+    }
+}
+
+// 2 dtau V / E0 on that box, [z][y][x]; V in energy units over the whole
+// grid (null: V = 0)
 std::vector<float> scaled_potential(const pstd_solver* s, const float* V) {
     const pstd_problem& p = s->prob;
-    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    const std::vector<double> wx = absorber_real(p, 0), wy = absorber_real(p, 1), wz = absorber_real(p, 2);
-    const double scale = 2.0 * s->dtau / s->E0, sw = 2.0 * s->dtau;
-    std::vector<float> v2((size_t)s->cells);
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                const int64_t id = i + (int64_t)nx * (j + (int64_t)ny * k);
-                const double v = V ? (double)V[id] : 0.0;
-                v2[id] = (float)(scale * v + sw * (wx[i] + wy[j] + wz[k]));
+    int lo[3], n[3];
+    potential_box(p, lo, n);
+    const double scale = 2.0 * s->dtau / s->E0;
+    std::vector<float> box((size_t)n[0] * n[1] * n[2], 0.0f);
+    if (!V) return box;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                const int64_t id = (i + lo[0]) + (int64_t)p.n[0] * ((j + lo[1]) + (int64_t)p.n[1] * (k + lo[2]));
+                box[i + (size_t)n[0] * (j + (size_t)n[1] * k)] = (float)(scale * (double)V[id]);
             }
-    return v2;
+    return box;
 }
 
 template <class T>
@@ -350,7 +360,7 @@ pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
     pstd::FdtdArgs a{};
     a.buf[0] = s->buf[0];
     a.buf[1] = s->buf[1];
-    a.v2 = s->v2;
+    a.pot = s->pot;
     a.nx = s->prob.n[0];
     a.ny = s->prob.n[1];
     a.nz = s->prob.n[2];
@@ -485,7 +495,7 @@ void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
     a.buf[0] = s->buf[0];
     a.buf[1] = s->buf[1];
     a.L = s->L;
-    a.v2 = s->v2;
+    a.pot = s->pot;
     a.nx = p.n[0];
     a.ny = p.n[1];
     a.nz = p.n[2];
@@ -615,7 +625,7 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     // the first device call: set-up of this device's static scratch
     if ((e = static_scratch_init(s->device))) return cleanup(hip_fail(s, e, "static scratch address"));
     if ((e = hipMalloc(&s->buf[0], s->cells * sizeof(float2))) || (e = hipMalloc(&s->buf[1], s->cells * sizeof(float2))) ||
-        (e = hipMalloc(&s->L, s->cells * sizeof(float2))) || (e = hipMalloc(&s->v2, s->cells * sizeof(float))))
+        (e = hipMalloc(&s->L, s->cells * sizeof(float2))))
         return cleanup(hip_fail(s, e, "hipMalloc state"));
     if (ext_ctr) {
         s->ctr = ext_ctr;
@@ -637,9 +647,24 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     if ((e = hipMemcpy(s->ctr, c0, sizeof(c0), hipMemcpyHostToDevice))) return cleanup(hip_fail(s, e, "counters"));
     if ((e = hipMemset(s->buf[0], 0, s->cells * sizeof(float2))) || (e = hipMemset(s->buf[1], 0, s->cells * sizeof(float2))))
         return cleanup(hip_fail(s, e, "hipMemset"));
-    if (p->abc_UR == 0.0) e = hipMemset(s->v2, 0, s->cells * sizeof(float));
-    else e = hipMemcpy(s->v2, scaled_potential(s, nullptr).data(), s->cells * sizeof(float), hipMemcpyHostToDevice);
-    if (e) return cleanup(hip_fail(s, e, "potential"));
+    // the potential term: V on the taper's core (zero until set), and the
+    // complex absorber's real part as one table per axis
+    potential_box(*p, s->pot.lo, s->pot.n);
+    const int64_t nbox = (int64_t)s->pot.n[0] * s->pot.n[1] * s->pot.n[2];
+    if ((e = hipMalloc(&s->vbox, nbox * sizeof(float))) || (e = hipMemset(s->vbox, 0, nbox * sizeof(float))))
+        return cleanup(hip_fail(s, e, "potential"));
+    s->pot.box = s->vbox;
+    if (p->abc_UR != 0.0) {
+        std::vector<float> wr;
+        for (int a = 0; a < 3; ++a)
+            for (double w : absorber_real(*p, a)) wr.push_back((float)(2.0 * s->dtau * w));
+        if ((e = hipMalloc(&s->wr, wr.size() * sizeof(float))) ||
+            (e = hipMemcpy(s->wr, wr.data(), wr.size() * sizeof(float), hipMemcpyHostToDevice)))
+            return cleanup(hip_fail(s, e, "absorber tables"));
+        s->pot.wr[0] = s->wr;
+        s->pot.wr[1] = s->wr + p->n[0];
+        s->pot.wr[2] = s->wr + p->n[0] + p->n[1];
+    }
     for (int a = 0; a < 3; ++a)
         if ((e = hipMemset(s->acc[a], 0, 8 * s->points[a] * sizeof(double2)))) return cleanup(hip_fail(s, e, "hipMemset acc"));
     // per-step tables through the end of the DFT window (up to 2^18 steps),
@@ -842,8 +867,8 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
     }
     if (vmax > p.v_max * (1 + 1e-6) && !p.force_dt)
         return fail(s, PSTD_EUNSTABLE, "max |V| exceeds v_max used to size the step");
-    const std::vector<float> v2 = scaled_potential(s, V.data());
-    HIP_TRY(s, hipMemcpy(s->v2, v2.data(), n_cells * sizeof(float), hipMemcpyHostToDevice));
+    const std::vector<float> box = scaled_potential(s, V.data());
+    HIP_TRY(s, hipMemcpy(s->vbox, box.data(), box.size() * sizeof(float), hipMemcpyHostToDevice));
     return PSTD_OK;
 }
 
@@ -1288,7 +1313,8 @@ pstd_status pstd_destroy(pstd_solver* s) {
     (void)hipFree(s->buf[0]);
     (void)hipFree(s->buf[1]);
     (void)hipFree(s->L);
-    (void)hipFree(s->v2);
+    (void)hipFree(s->vbox);
+    (void)hipFree(s->wr);
     (void)hipFree(s->tables);
     (void)hipFree(s->sigma_tab);
     (void)hipFree(s->w_tab);

@@ -19,14 +19,27 @@ struct AxisTables {
     const float2* dhi;   // spectral-derivative row for the high plane
 };
 
+// The potential term's factor 2 dtau (V / E0 + sum_a w_a) of Eq. PSTDupdating.
+// V may be non-zero only where the taper is one (Section 2.2.2: (zeta - 1) V
+// = 0), the box y1 <= i <= y2 of every axis, so it is stored on that box
+// alone; w_a, the real part of a complex absorbing potential along axis a,
+// is separable and comes from one table per axis (all null without it).
+struct PotentialArgs {
+    const float* box;      // 2 dtau V / E0 on the box, [z][y][x], x fastest
+    int lo[3];             // first grid index of the box per axis
+    int n[3];              // extent of the box per axis
+    const float* wr[3];    // 2 dtau w_a(i) per grid index, or null
+};
+
 // Everything a pass launch needs for one solver instance and one axis.  The
 // structs live in device memory and stay fixed while the solver runs; the
 // per-step quantities are read on the device from the step counter:
 // psi^n = buf[n & 1], psi^{n-1} = buf[(n + 1) & 1], and the tables below.
 struct PassArgs {
     float2* buf[2];            // psi ping-pong
-    float2* L;                 // kinetic accumulator (scaled by 2 eta dtau)
-    const float* v2;           // 2 dtau V / E0
+    float2* L;                 // kinetic accumulator (scaled by 2 eta dtau) plus, from the x
+                               // pass, the potential term 2 dtau v psi^n
+    PotentialArgs pot;
     int nx, ny, nz;
     AxisTables ax[3];
     const int64_t* ctr;        // device counters: ctr[0] = step n, ctr[1] = end (n >= end: no work)
@@ -63,7 +76,7 @@ struct PassArgs {
 // (psi(-l e_a) + psi(+l e_a)) + v2 psi + sigma_n sum_a dz_a prod_{b != a} zt_b
 struct FdtdArgs {
     float2* buf[2];
-    const float* v2;
+    PotentialArgs pot;
     int nx, ny, nz;
     const float* gam[3];       // mask factors per axis
     const float2* zt[3];       // T_a e^{i kh_a x_a}

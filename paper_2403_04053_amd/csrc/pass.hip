@@ -12,12 +12,15 @@
 // Loads and stores are coalesced without an LDS transpose: the x pass gives
 // consecutive lanes consecutive elements of a row; the y and z passes give
 // consecutive lanes consecutive x of a tile of P pencils.  The per-axis
-// tables (twiddles, kbar^2, derivative rows) are staged in LDS once per
-// workgroup.
+// twiddles and kbar^2 are staged in LDS once per workgroup; the derivative
+// rows of the surface planes (used only inside the DFT window) are read from
+// global memory, where neighbouring lanes read neighbouring entries.
 //
-// Epilogues: x pass writes L; y pass adds to L (which it reads at the start,
-// with the field); z pass adds its term and applies the leapfrog update with
-// potential, TF/SF source and absorber, writing psi^{n+1} over psi^{n-1}.
+// Epilogues: x pass writes L = (its kinetic term) + 2 dtau v psi^n, the
+// potential term taken from the field it already holds (V is read only on the
+// box where it may be non-zero); y pass adds to L (which it reads at the
+// start, with the field); z pass adds its term and applies the leapfrog
+// update with TF/SF source and absorber, writing psi^{n+1} over psi^{n-1}.
 // Inside the DFT window each pass also accumulates, in FP64 with Neumaier
 // compensation, the DFT of psi and of its spectral normal derivative on the
 // two planes normal to its axis (Eqs. psiphasor, dpsiphasor).
@@ -60,7 +63,9 @@ struct Fields {
     GMEM float2* buf0;
     GMEM float2* buf1;
     GMEM float2* L;
-    GMEM const float* v2;
+    GMEM const float* vbox;
+    int vlo0, vlo1, vlo2, vn0, vn1, vn2;
+    GMEM const float *wr0, *wr1, *wr2;
     int nx, ny, nz;
     GMEM const float *kk, *gam;
     GMEM const float2 *tw, *zt, *dz, *dlo, *dhi;
@@ -89,7 +94,16 @@ __device__ __forceinline__ Fields fields(const PassArgs& a) {
     f.buf0 = gmem(a.buf[0]);
     f.buf1 = gmem(a.buf[1]);
     f.L = gmem(a.L);
-    f.v2 = gmem(a.v2);
+    f.vbox = gmem(a.pot.box);
+    f.vlo0 = a.pot.lo[0];
+    f.vlo1 = a.pot.lo[1];
+    f.vlo2 = a.pot.lo[2];
+    f.vn0 = a.pot.n[0];
+    f.vn1 = a.pot.n[1];
+    f.vn2 = a.pot.n[2];
+    f.wr0 = gmem(a.pot.wr[0]);
+    f.wr1 = gmem(a.pot.wr[1]);
+    f.wr2 = gmem(a.pot.wr[2]);
     f.nx = a.nx;
     f.ny = a.ny;
     f.nz = a.nz;
@@ -138,6 +152,7 @@ struct TileGeo {
     bool valid;
     int seg, g0, Ng;
     int px, py;   // (x, y) of the pencil (z pass update)
+    int row;      // row index y + ny z (x pass)
     int tx, tq;   // x tile and (other, segment) of the y, z passes
 };
 
@@ -152,9 +167,11 @@ __device__ __forceinline__ TileGeo tile_geo(const Fields& f, int tile, int pA, b
     g.py = 0;
     g.tx = 0;
     g.tq = 0;
+    g.row = 0;
     if constexpr (AXIS == 0) {
         const int64_t q = (int64_t)tile * P + pA;
         const int64_t row = q / nseg;
+        g.row = (int)row;   // rows of a grid number fewer than 2^31
         g.seg = (int)(q % nseg);
         g.valid = activeA && q < (int64_t)ny * nz * nseg;
         g.base = row * nx + (g.seg * C - H);
@@ -213,7 +230,6 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     __shared__ float2 ex[P * STRIDE];
     __shared__ float2 s_tw[N];
     __shared__ float s_kk[N];
-    __shared__ float2 s_dl[N], s_dh[N];
 
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
@@ -251,10 +267,6 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     for (int i = t; i < N; i += NT) {
         s_tw[i] = f.tw[i];
         s_kk[i] = f.kk[i];
-        if (surf) {
-            s_dl[i] = f.dlo[i];
-            s_dh[i] = f.dhi[i];
-        }
     }
 
     {
@@ -303,8 +315,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
                 if (e < N) {
-                    dlo = cadd(dlo, cmul(s_dl[e], v[n1]));
-                    dhi = cadd(dhi, cmul(s_dh[e], v[n1]));
+                    dlo = cadd(dlo, cmul(f.dlo[e], v[n1]));
+                    dhi = cadd(dhi, cmul(f.dhi[e], v[n1]));
                 }
             });
         }
@@ -371,7 +383,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     constexpr int n1 = decltype(i)::value;
                     const int e = n2 + N2 * n1;
                     if (e < N) {
-                        float2 x = cadd(cmul(s_dl[e], hdl), cmul(s_dh[e], hdh));
+                        float2 x = cadd(cmul(f.dlo[e], hdl), cmul(f.dhi[e], hdh));
                         if (e == plane_lo) x = cadd(x, hpl);
                         if (e == plane_hi) x = cadd(x, hph);
                         v[n1] = cadd(v[n1], x);
@@ -386,11 +398,44 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         GMEM float2* __restrict__ Lbuf = f.L;
         if (geo.valid) {
             if constexpr (AXIS == 0) {
-                unroll<N1>([&](auto i) {
-                    constexpr int n1 = decltype(i)::value;
-                    const int e = n2 + N2 * n1;
-                    if (e < N && (!SEG || (e >= H && e < H + C))) Lbuf[geo.base + e] = v[n1];
-                });
+                // the potential term 2 dtau (V / E0 + sum_a w_a) psi^n of the row's cells:
+                // rows off the potential's box (most of them) store the kinetic term
+                // alone; the others read psi^n again (the tile was just read, so this
+                // hits the cache) rather than hold it in registers through the transforms
+                const int z = (int)((unsigned)geo.row / (unsigned)f.ny), y = geo.row - z * f.ny;
+                const bool brow = (unsigned)(y - f.vlo1) < (unsigned)f.vn1 && (unsigned)(z - f.vlo2) < (unsigned)f.vn2;
+                GMEM const float* __restrict__ wr0 = f.wr0;
+                if (!brow && !wr0) {
+                    unroll<N1>([&](auto i) {
+                        constexpr int n1 = decltype(i)::value;
+                        const int e = n2 + N2 * n1;
+                        if (e < N && (!SEG || (e >= H && e < H + C))) Lbuf[geo.base + e] = v[n1];
+                    });
+                } else {
+                    // every load first (the box value through a clamped index), then
+                    // the products and stores, so the loads overlap
+                    const int64_t vrow = ((int64_t)(z - f.vlo2) * f.vn1 + (y - f.vlo1)) * f.vn0 - f.vlo0;
+                    const float wyz = wr0 ? f.wr1[y] + f.wr2[z] : 0.f;
+                    float2 pv[N1];
+                    float vv[N1];
+                    unroll<N1>([&](auto i) {
+                        constexpr int n1 = decltype(i)::value;
+                        const int e = n2 + N2 * n1;
+                        const int x = geo.g0 + e;
+                        const bool own = e < N && (!SEG || (e >= H && e < H + C));
+                        const bool inb = own && brow && (unsigned)(x - f.vlo0) < (unsigned)f.vn0;
+                        pv[n1] = make_float2(0.f, 0.f);
+                        if (own) pv[n1] = psi[geo.base + e];
+                        const float b = f.vbox[inb ? vrow + x : 0];
+                        vv[n1] = (inb ? b : 0.f) + (wr0 && own ? wr0[x] + wyz : 0.f);
+                    });
+                    unroll<N1>([&](auto i) {
+                        constexpr int n1 = decltype(i)::value;
+                        const int e = n2 + N2 * n1;
+                        if (e < N && (!SEG || (e >= H && e < H + C)))
+                            Lbuf[geo.base + e] = cadd(v[n1], cscale(pv[n1], vv[n1]));
+                    });
+                }
             } else if constexpr (AXIS == 1) {
                 unroll<N1>([&](auto i) {
                     constexpr int n1 = decltype(i)::value;
@@ -401,7 +446,6 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     }
                 });
             } else {
-                GMEM const float* __restrict__ v2 = f.v2;
                 GMEM const float* __restrict__ t_gam = f.gam;
                 GMEM const float2* __restrict__ t_zt = f.zt;
                 GMEM const float2* __restrict__ t_dz = f.dz;
@@ -425,8 +469,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                         const int64_t ad = geo.base + (int64_t)e * geo.estride;
                         const float2 Lt = cadd(Lbuf[ad], v[n1]);
                         const float2 po = psi_old[ad];
-                        const float vv = v2[ad];
-                        float2 q = cadd(Lt, cscale(raw[n1], vv));
+                        float2 q = Lt;
                         if constexpr (!ADJ) {
                             const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
                             q = cadd(q, cmul(sigma, s));
@@ -529,6 +572,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     X(160, 16, 10, 16, 0)       \
     X(160, 10, 16, 32, 0)       \
     X(160, 10, 16, 8, 0)        \
+    X(160, 8, 20, 16, 0)        \
+    X(160, 20, 8, 16, 0)        \
     X(162, 9, 18, 16, 0)        \
     X(162, 9, 18, 32, 0)        \
     X(180, 12, 15, 16, 0)       \
@@ -537,7 +582,11 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     X(256, 16, 16, 16, 0)       \
     X(288, 16, 18, 16, 0)       \
     X(288, 18, 16, 16, 0)       \
-    X(288, 16, 18, 32, 0)
+    X(288, 16, 18, 32, 0)       \
+    X(288, 12, 24, 8, 0)        \
+    X(288, 24, 12, 8, 0)        \
+    X(288, 12, 24, 16, 0)       \
+    X(288, 24, 12, 16, 0)
 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);

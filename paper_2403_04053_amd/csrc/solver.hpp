@@ -31,7 +31,9 @@ struct pstd_solver {
     int64_t win_steps = 0; // window steps run so far
     float2* buf[2] = {nullptr, nullptr};
     float2* L = nullptr;
-    float* v2 = nullptr;
+    float* vbox = nullptr;       // 2 dtau V / E0 on the taper's core
+    float* wr = nullptr;         // complex absorber: 2 dtau w_a per axis (null without it)
+    pstd::PotentialArgs pot{};
     void* tables = nullptr;
     pstd::AxisTables ax[3]{};
     const float* wloc[3] = {nullptr, nullptr, nullptr};
