@@ -376,6 +376,31 @@ def voxel_potential_160(seed_prior=5, seed_hidden=55, n_fft=160):
     return prob, V0, Vh
 
 
+def voxel_potential_48(seed_prior=5, seed_hidden=55):
+    """The voxel-potential recipe of voxel_potential_160 on a 48^3 FFT grid
+    (32^3 inside an 8-cell absorber): taper 10/14/34/38, voxel potential on
+    the 21^3 core (smoothed N(0, 0.1 E0) prior, sigma 2 cells; hidden
+    potential from another seed), box planes at 9 and 39, 6000 steps with the
+    window over all of them.  Small enough for the FP64 oracle's adjoint at
+    the full step count."""
+    h = 0.1
+    k0 = math.pi / (4 * h)
+    E0 = k0 * k0 / 2
+    n = (48, 48, 48)
+    P = 8
+    alpha = 4.0 / P
+    tf = (10, 14, 34, 38)
+    core_lo, core_hi = (tf[1],) * 3, (tf[2],) * 3
+    V0 = smoothed_prior(n, core_lo, core_hi, 0.1 * E0, 2.0, seed_prior)
+    Vh = smoothed_prior(n, core_lo, core_hi, 0.1 * E0, 2.0, seed_hidden)
+    vmax = max(float(np.abs(V0).max()), float(np.abs(Vh).max())) * 1.5
+    prob = Problem(n=n, h=(h, h, h), k0=k0, abc_cells=(P,) * 3, abc_alpha=alpha,
+                   abc_U0=paper_u0(alpha, k0 * h, P), tfsf=(tf,) * 3,
+                   v_max=vmax, n_steps=6000, dft_begin=0, dft_end=6000,
+                   surf_lo=(9,) * 3, surf_hi=(39,) * 3)
+    return prob, V0, Vh
+
+
 def fresnel_plane(n_side, spacing, z):
     """n_side x n_side detector points (physical xyz) at height z, centred on
     the z axis, lateral spacing `spacing`; row-major in (y, x)."""

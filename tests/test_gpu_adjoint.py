@@ -186,19 +186,56 @@ def test_gradient_matches_gpu_finite_differences(P, setup):
     s.close()
 
 
-def test_full_size_gradient_finite_differences(P):
-    """The 160^3 voxel-potential workload in its benchmark configuration
-    (128x128 detector plane at z = 39.2, sqrt(N) checkpoints), cut to 600
-    steps: central differences of the GPU misfit at the seed-chosen core
-    voxels with the largest gradient.  FD in FP32 has a noise floor near
-    5e-7 in J differences, so the step is large (5e-2 E0) and the bar 1e-2."""
+# ---------------------------------------------------------------------------
+# the voxel-potential workload at its configured length (6000 steps)
+# ---------------------------------------------------------------------------
+
+def test_voxel_recipe_full_length_matches_oracle_adjoint(P):
+    """The voxel-potential recipe on a 48^3 grid over the configured 6000
+    steps (window all, 32 x 32 detector at z = 3.0): J and dJ/dV of the FP32
+    GPU path against the FP64 oracle's discrete adjoint, stored by
+    golden/make_voxel_adjoint_reference.py (which calls only oracle/)."""
+    import math
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "voxel_adjoint_48.npz")
+    if not os.path.exists(path):
+        pytest.skip("voxel_adjoint_48.npz not written yet")
+    ref = np.load(path)
+    prob, V0, _ = synth.voxel_potential_48()
+    N = prob.n_steps
+    assert int(ref["steps"]) == N
+    print(f"adjoint vs FP64 oracle: grid {prob.n}, {N} steps", flush=True)
+    s = P.Solver(prob)
+    s.set_potential(V0.astype(np.float32))
+    J = s.misfit(N, ref["points"], ref["target"], math.ceil(math.sqrt(N)))
+    g = s.misfit_gradient().cpu().numpy().astype(np.float64)
+    eJ = abs(J - float(ref["J"])) / float(ref["J"])
+    eg = rel_l2(g, ref["grad"])
+    print(f"  J {J:.10e} (oracle {float(ref['J']):.10e}, rel {eJ:.2e}), gradient rel-L2 {eg:.2e}", flush=True)
+    assert eJ <= 1e-4
+    assert eg <= 1e-3
+    s.close()
+
+
+FD_DELTAS = (0.1, 0.2)           # steps of the central differences, units of E0
+FD_CHUNKS = 4                    # the 64 voxels in four tests of 16
+
+
+@pytest.fixture(scope="module")
+def voxel160(P):
+    """The 160^3 voxel-potential workload as configured: 6000 steps with the
+    window over all of them, 128 x 128 detector points at z = 39.2, sqrt(N)
+    checkpoints; target = total-field intensity of the hidden potential; the
+    adjoint gradient at the 64 seed-555 core voxels; and the rounding noise
+    eps_J of the FP32 misfit, the spread of J over six perturbations of one
+    voxel by 1e-7 E0 (linear change below 1e-9 of J)."""
     import math
     prob, V0, Vh = synth.voxel_potential_160()
-    N = 600
-    prob = prob.replace(dft_end=N)
+    N = prob.n_steps
     pts = synth.fresnel_plane(128, prob.h[0], 39.2)
     print(f"adjoint full size: grid {prob.n}, {N} steps, {len(pts)} points", flush=True)
     s = P.Solver(prob)
+    s.autotune(reps=5)
     s.set_potential(Vh.astype(np.float32))
     s.run(N)
     psi = s.project(pts).cpu().numpy()
@@ -206,23 +243,49 @@ def test_full_size_gradient_finite_differences(P):
     V = V0.astype(np.float32)
     s.set_potential(V)
     J = s.misfit(N, pts, target, math.ceil(math.sqrt(N)))
-    assert np.isfinite(J) and J > 0
     g = s.misfit_gradient().cpu().numpy().astype(np.float64)
-    assert np.isfinite(g).all()
     vox = synth.fd_voxels(prob, 64, 555)
-    vox = sorted(vox, key=lambda v: -abs(g[v]))[:3]
     E0 = prob.k0 ** 2 / 2
-    delta = 5e-2 * E0
-    for v in vox:
+
+    def J_at(v, d):
         Vp = V.copy()
-        Vp[v] += delta
-        Vm = V.copy()
-        Vm[v] -= delta
+        Vp[v] += d
         s.set_potential(Vp)
-        Jp = s.misfit(N, pts, target, 1)
-        s.set_potential(Vm)
-        Jm = s.misfit(N, pts, target, 1)
-        fd = (Jp - Jm) / (2 * delta)
-        print(f"  voxel {v}: adjoint {g[v]:.6e}, FD {fd:.6e}", flush=True)
-        assert abs(g[v] - fd) <= 1e-2 * abs(fd)
+        return s.misfit(N, pts, target, 1)
+
+    js = [J_at(vox[0], k * 1e-7 * E0) for k in range(-3, 3)]
+    eps_J = float(np.std(js, ddof=1))
+    print(f"  J {J:.10e}, |g| max {np.abs(g).max():.3e}, FP32 noise of J {eps_J:.2e}", flush=True)
+    yield dict(prob=prob, s=s, J=J, g=g, vox=vox, J_at=J_at, eps_J=eps_J, E0=E0, gmax=[])
     s.close()
+
+
+@pytest.mark.parametrize("chunk", range(FD_CHUNKS))
+def test_full_size_gradient_finite_differences(P, voxel160, chunk):
+    """Central differences of the GPU misfit at 16 of the 64 seed-555 core
+    voxels, Richardson-extrapolated from steps of 0.1 and 0.2 E0 (the O(delta^2)
+    term cancels; what is left is O(delta^4) and rounding).  Bar, per voxel:
+    |g_adj - g_fd| <= 1e-3 max(|g_fd|, 1e-3 max|g_adj|) + 3 sigma, where sigma =
+    1.37 eps_J / (2 delta) is the rounding noise that the extrapolated
+    difference carries from the FP32 run's measured scatter eps_J of J (it
+    dominates only at voxels whose gradient is below about 3 % of the
+    largest)."""
+    d = voxel160
+    s, g, vox, E0 = d["s"], d["g"], d["vox"], d["E0"]
+    per = len(vox) // FD_CHUNKS
+    mine = vox[chunk * per:(chunk + 1) * per]
+    gscale = float(np.max(np.abs([g[v] for v in vox])))
+    d1, d2 = FD_DELTAS[0] * E0, FD_DELTAS[1] * E0
+    sigma = 1.37 * d["eps_J"] / (2 * d1)
+    n_bar = 0
+    for v in mine:
+        f1 = (d["J_at"](v, d1) - d["J_at"](v, -d1)) / (2 * d1)
+        f2 = (d["J_at"](v, d2) - d["J_at"](v, -d2)) / (2 * d2)
+        fd = (4 * f1 - f2) / 3
+        err = abs(g[v] - fd)
+        bar = 1e-3 * max(abs(fd), 1e-3 * gscale)
+        n_bar += err <= bar
+        print(f"  voxel {v}: adjoint {g[v]:+.6e} fd {fd:+.6e} err {err:.2e} (1e-3 bar {bar:.2e}, noise {sigma:.2e})",
+              flush=True)
+        assert err <= bar + 3 * sigma, (v, g[v], fd, err, bar, sigma)
+    print(f"  chunk {chunk}: {n_bar} of {len(mine)} within 1e-3 without the noise allowance", flush=True)
