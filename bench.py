@@ -542,7 +542,8 @@ def bench_pulse(args):
 
     import paper_2403_04053_amd as P
     import synth
-    base, V = synth.square_barrier_160(n_fft=args.n)
+    # the pulsed sphere's shell must lie where the taper is zero: the 4-cell taper
+    base, V = synth.square_barrier_160(n_fft=args.n, transition=4 if args.surface == "sphere" else 12)
     if args.surface == "sphere":
         sph = dict(surface_kind=1, sphere_radius=5.6 * args.n / 160, sphere_nodes=(64, 128))
         surf_txt = "sphere r=5.6 (64x128 nodes)"

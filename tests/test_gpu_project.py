@@ -101,7 +101,10 @@ def test_plain_method_against_partial_waves(P):
     rel = math.sqrt(np.sum(w * np.abs(f - ref) ** 2) / np.sum(w * np.abs(ref) ** 2))
     print("plain method: solid-angle rel-L2 of f vs partial waves", rel)
     print("f(0)", f[0, 0], ref[0, 0], "f(90)", f[18, 0], ref[18, 0], "f(180)", f[-1, 0], ref[-1, 0])
-    assert rel < 0.05
+    # measured 3.5 %: TF/SF leakage and absorber reflection of the workload's
+    # thin layers plus the discretisation at 8 points per wavelength (the split
+    # is tests/test_gpu_accuracy.py's plain-method budget)
+    assert rel < 0.04
 
 
 def test_refined_plain_method_within_one_percent(P):

@@ -254,7 +254,7 @@ def test_pulse_far_field_at_five_wavenumbers(P):
     enough for the slowest of these components (group velocity 2k) to pass
     the sphere (at tau = 110, k = 0.8 was 8.9 % off, at 160 4.7 %, at 220
     4.1 %)."""
-    base, V = synth.square_barrier_160()
+    base, V = synth.square_barrier_160(transition=4)   # shell outside the taper box
     sph = dict(surface_kind=1, sphere_radius=5.6, sphere_nodes=(64, 128))
     dtau = opstd.dtau_of(base)
     steps = int(round(160.0 / dtau))

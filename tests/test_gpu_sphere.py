@@ -153,6 +153,8 @@ def test_square_barrier_sphere_far_field(P):
     r_sb, r_sp, r_bp = rel(f_s, f_b), rel(f_s, ref), rel(f_b, ref)
     print(f"  sphere vs box {r_sb:.4f}, sphere vs partial waves {r_sp:.4f}, box vs partial waves {r_bp:.4f}",
           flush=True)
-    assert r_sb < 0.02 and r_sp < 0.05
+    # with the 12-cell taper: sphere 1.2 %, box and sphere within 1 % (the
+    # error budget of this workload is tests/test_gpu_accuracy.py)
+    assert r_sb < 0.01 and r_sp < 0.015 and r_bp < 0.02
     s.close()
     box.close()
