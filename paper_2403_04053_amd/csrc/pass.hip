@@ -331,6 +331,10 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                 ex[pA * STRIDE + k1 * ROW + n2] = x;
             });
         }
+        // the values now live in LDS: clear the registers, so that threads idle
+        // in stage A (which skip the reload below) do not keep them alive
+        // through stage B
+        unroll<N1>([&](auto i) { v[decltype(i)::value] = make_float2(0.f, 0.f); });
         __syncthreads();
 
         // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
