@@ -496,6 +496,7 @@ void solver_args(const pstd_solver* s, int axis, PassArgs& a) {
     a.buf[1] = s->buf[1];
     a.L = s->L;
     a.pot = s->pot;
+    a.potx = s->potx;
     a.nx = p.n[0];
     a.ny = p.n[1];
     a.nz = p.n[2];
@@ -654,6 +655,13 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     if ((e = hipMalloc(&s->vbox, nbox * sizeof(float))) || (e = hipMemset(s->vbox, 0, nbox * sizeof(float))))
         return cleanup(hip_fail(s, e, "potential"));
     s->pot.box = s->vbox;
+    // where the potential term is taken: in the x pass (re-reading psi^n from
+    // the cache on the rows that cross V's box) when the box covers under a
+    // quarter of the rows, else in the z pass (psi^n held in registers); the
+    // complex absorber's real part (every cell) and segmented x pencils take
+    // the z pass (batch instances follow the same rule, grouped by it)
+    const double box_rows = (double)s->pot.n[1] * s->pot.n[2] / ((double)p->n[1] * p->n[2]);
+    s->potx = (p->abc_UR == 0.0 && p->sub_core[0] == 0 && box_rows < 0.25) ? 1 : 0;
     if (p->abc_UR != 0.0) {
         std::vector<float> wr;
         for (int a = 0; a < 3; ++a)

@@ -24,6 +24,7 @@ thread_local std::string g_batch_error;
 struct Group {
     int variant = 0;
     bool seg = false;
+    int potx = 0;       // x and z passes: where the members take the potential term
     std::vector<int> members;
     pstd::PassArgs* d_desc = nullptr;
     int* d_off = nullptr;
@@ -89,13 +90,16 @@ pstd_status build_groups(pstd_batch* b) {
         for (int i = 0; i < (int)b->inst.size(); ++i) {
             const pstd_solver* s = b->inst[i];
             const bool seg = s->prob.sub_core[axis] > 0;
-            auto it = std::find_if(gs.begin(), gs.end(),
-                                   [&](const Group& g) { return g.variant == s->variant[axis] && g.seg == seg; });
+            const int potx = axis == 1 ? 0 : s->potx;
+            auto it = std::find_if(gs.begin(), gs.end(), [&](const Group& g) {
+                return g.variant == s->variant[axis] && g.seg == seg && g.potx == potx;
+            });
             if (it == gs.end()) {
                 gs.push_back(Group{});
                 it = gs.end() - 1;
                 it->variant = s->variant[axis];
                 it->seg = seg;
+                it->potx = potx;
             }
             it->members.push_back(i);
         }
@@ -122,7 +126,7 @@ pstd_status launch_batch_steps(pstd_batch* b, hipStream_t stream, int count) {
         for (int axis = 0; axis < 3; ++axis)
             for (const Group& g : b->groups[axis]) {
                 hipError_t e = pstd::launch_variant(g.variant, g.seg, axis, g.d_desc, g.d_off, (int)g.members.size(),
-                                                    g.tiles, k, stream);
+                                                    g.tiles, k, g.potx, stream);
                 if (e != hipSuccess) return bhip(b, e, "batch pass launch");
             }
     hipError_t e = pstd::launch_advance(b->ctr, (int)b->inst.size(), count, stream);

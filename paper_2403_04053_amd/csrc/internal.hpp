@@ -37,9 +37,10 @@ struct PotentialArgs {
 // psi^n = buf[n & 1], psi^{n-1} = buf[(n + 1) & 1], and the tables below.
 struct PassArgs {
     float2* buf[2];            // psi ping-pong
-    float2* L;                 // kinetic accumulator (scaled by 2 eta dtau) plus, from the x
-                               // pass, the potential term 2 dtau v psi^n
+    float2* L;                 // kinetic accumulator (scaled by 2 eta dtau)
     PotentialArgs pot;
+    int potx;                  // 1: the x pass takes the potential term (V's box covers few rows,
+                               // no absorber real part, x unsegmented), else the z pass
     int nx, ny, nz;
     AxisTables ax[3];
     const int64_t* ctr;        // device counters: ctr[0] = step n, ctr[1] = end (n >= end: no work)
@@ -105,8 +106,10 @@ int variant_tiles(int v, int axis, PassArgs& args);
 // Launch variant v over a group of instances: descs[0..ninst) in device
 // memory, off[0..ninst] (device) = prefix sums of their tiles.  The launch
 // works on step ctr[0] + koff of each instance.
+// The group's members all take the potential term where `potx` says (their
+// PassArgs::potx).
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, int koff, hipStream_t stream);
+                          int total_tiles, int koff, int potx, hipStream_t stream);
 // Launch variant v for one instance described by `args` (passed by value)
 hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs& args, int koff, hipStream_t stream);
 // Adjoint step pass (plain pencils, one instance)

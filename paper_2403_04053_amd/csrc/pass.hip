@@ -16,11 +16,13 @@
 // rows of the surface planes (used only inside the DFT window) are read from
 // global memory, where neighbouring lanes read neighbouring entries.
 //
-// Epilogues: x pass writes L = (its kinetic term) + 2 dtau v psi^n, the
-// potential term taken from the field it already holds (V is read only on the
-// box where it may be non-zero); y pass adds to L (which it reads at the
-// start, with the field); z pass adds its term and applies the leapfrog
-// update with TF/SF source and absorber, writing psi^{n+1} over psi^{n-1}.
+// Epilogues: x pass writes L; y pass adds to L (which it reads at the start,
+// with the field); z pass adds its term and applies the leapfrog update with
+// the potential (V read only on the pencils that cross the box where it may
+// be non-zero), TF/SF source and absorber, writing psi^{n+1} over psi^{n-1}.
+// When that box covers few rows (PassArgs::potx), the x pass takes the
+// potential term instead, on the rows that cross the box, and the z pass
+// holds no copy of psi^n through its transforms.
 // Inside the DFT window each pass also accumulates, in FP64 with Neumaier
 // compensation, the DFT of psi and of its spectral normal derivative on the
 // two planes normal to its axis (Eqs. psiphasor, dpsiphasor).
@@ -152,7 +154,6 @@ struct TileGeo {
     bool valid;
     int seg, g0, Ng;
     int px, py;   // (x, y) of the pencil (z pass update)
-    int row;      // row index y + ny z (x pass)
     int tx, tq;   // x tile and (other, segment) of the y, z passes
 };
 
@@ -167,11 +168,9 @@ __device__ __forceinline__ TileGeo tile_geo(const Fields& f, int tile, int pA, b
     g.py = 0;
     g.tx = 0;
     g.tq = 0;
-    g.row = 0;
     if constexpr (AXIS == 0) {
         const int64_t q = (int64_t)tile * P + pA;
         const int64_t row = q / nseg;
-        g.row = (int)row;   // rows of a grid number fewer than 2^31
         g.seg = (int)(q % nseg);
         g.valid = activeA && q < (int64_t)ny * nz * nseg;
         g.base = row * nx + (g.seg * C - H);
@@ -218,7 +217,7 @@ __device__ __forceinline__ void load_tile(GMEM const float2* __restrict__ psi, c
 
 // One workgroup per tile of P pencils; MULTI launches find their instance
 // from the prefix table of tiles.
-template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ>
+template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
                                                                        const PassArgs* __restrict__ descs,
                                                                        const int* __restrict__ off, int ninst,
@@ -401,15 +400,15 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         const int H = SEG ? f.seg_halo : 0;
         GMEM float2* __restrict__ Lbuf = f.L;
         if (geo.valid) {
-            if constexpr (AXIS == 0) {
-                // the potential term 2 dtau (V / E0 + sum_a w_a) psi^n of the row's cells:
-                // rows off the potential's box (most of them) store the kinetic term
-                // alone; the others read psi^n again (the tile was just read, so this
-                // hits the cache) rather than hold it in registers through the transforms
-                const int z = (int)((unsigned)geo.row / (unsigned)f.ny), y = geo.row - z * f.ny;
+            if constexpr (AXIS == 0 && POTX) {
+                // the potential term 2 dtau V / E0 psi^n of the row's cells when V's
+                // box covers few rows: rows off the box store the kinetic term alone,
+                // the others read psi^n again (the tile was just read, so this hits
+                // the cache) rather than hold it in registers through the transforms
+                const int64_t row = ((int64_t)tile * P + pA) / (SEG ? f.nseg : 1);
+                const int z = (int)((unsigned)row / (unsigned)f.ny), y = (int)row - z * f.ny;
                 const bool brow = (unsigned)(y - f.vlo1) < (unsigned)f.vn1 && (unsigned)(z - f.vlo2) < (unsigned)f.vn2;
-                GMEM const float* __restrict__ wr0 = f.wr0;
-                if (!brow && !wr0) {
+                if (!brow) {
                     unroll<N1>([&](auto i) {
                         constexpr int n1 = decltype(i)::value;
                         const int e = n2 + N2 * n1;
@@ -419,7 +418,6 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     // every load first (the box value through a clamped index), then
                     // the products and stores, so the loads overlap
                     const int64_t vrow = ((int64_t)(z - f.vlo2) * f.vn1 + (y - f.vlo1)) * f.vn0 - f.vlo0;
-                    const float wyz = wr0 ? f.wr1[y] + f.wr2[z] : 0.f;
                     float2 pv[N1];
                     float vv[N1];
                     unroll<N1>([&](auto i) {
@@ -427,11 +425,11 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                         const int e = n2 + N2 * n1;
                         const int x = geo.g0 + e;
                         const bool own = e < N && (!SEG || (e >= H && e < H + C));
-                        const bool inb = own && brow && (unsigned)(x - f.vlo0) < (unsigned)f.vn0;
+                        const bool inb = own && (unsigned)(x - f.vlo0) < (unsigned)f.vn0;
                         pv[n1] = make_float2(0.f, 0.f);
                         if (own) pv[n1] = psi[geo.base + e];
                         const float b = f.vbox[inb ? vrow + x : 0];
-                        vv[n1] = (inb ? b : 0.f) + (wr0 && own ? wr0[x] + wyz : 0.f);
+                        vv[n1] = inb ? b : 0.f;
                     });
                     unroll<N1>([&](auto i) {
                         constexpr int n1 = decltype(i)::value;
@@ -440,6 +438,12 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                             Lbuf[geo.base + e] = cadd(v[n1], cscale(pv[n1], vv[n1]));
                     });
                 }
+            } else if constexpr (AXIS == 0) {
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    if (e < N && (!SEG || (e >= H && e < H + C))) Lbuf[geo.base + e] = v[n1];
+                });
             } else if constexpr (AXIS == 1) {
                 unroll<N1>([&](auto i) {
                     constexpr int n1 = decltype(i)::value;
@@ -465,6 +469,26 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                 GMEM float2* __restrict__ stash = nullptr;
                 if constexpr (ADJ) fwd = gmem(f.fwd_tab[nstep]);
                 else if (f.stash_tab) stash = gmem(f.stash_tab[nstep]);
+                // the potential term 2 dtau (V / E0 + sum_a w_a) psi^n: V is read on
+                // the pencils that cross its box only (the box value through a
+                // clamped index, so the loads of a pencil are not branched apart)
+                const bool bpen = (unsigned)(px - f.vlo0) < (unsigned)f.vn0 && (unsigned)(py - f.vlo1) < (unsigned)f.vn1;
+                const int64_t vcol = (int64_t)(py - f.vlo1) * f.vn0 + (px - f.vlo0);
+                const int64_t vplane = (int64_t)f.vn0 * f.vn1;
+                GMEM const float* __restrict__ wr0 = f.wr0;
+                const float wxy = wr0 ? wr0[px] + f.wr1[py] : 0.f;
+                float vv[N1];
+                if (!POTX && (bpen || wr0)) {
+                    unroll<N1>([&](auto i) {
+                        constexpr int n1 = decltype(i)::value;
+                        const int z = geo.g0 + n2 + N2 * n1;
+                        const bool inb = bpen && (unsigned)(z - f.vlo2) < (unsigned)f.vn2;
+                        const float b = f.vbox[inb ? vcol + (int64_t)(z - f.vlo2) * vplane : 0];
+                        vv[n1] = (inb ? b : 0.f) + (wr0 && z >= 0 && z < f.nz ? wxy + f.wr2[z] : 0.f);
+                    });
+                } else {
+                    unroll<N1>([&](auto i) { vv[decltype(i)::value] = 0.f; });
+                }
                 unroll<N1>([&](auto i) {
                     constexpr int n1 = decltype(i)::value;
                     const int e = n2 + N2 * n1;
@@ -474,6 +498,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                         const float2 Lt = cadd(Lbuf[ad], v[n1]);
                         const float2 po = psi_old[ad];
                         float2 q = Lt;
+                        if constexpr (!POTX) q = cadd(q, cscale(raw[n1], vv[n1]));
                         if constexpr (!ADJ) {
                             const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
                             q = cadd(q, cmul(sigma, s));
@@ -595,13 +620,13 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);
 
-template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ>
+template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
 hipError_t launch_kernel(const PassArgs& single, const PassArgs* descs, const int* off, int ninst, int tiles,
                          int koff, hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, AXIS, SEG, MULTI, ADJ>), dim3(tiles), dim3(threads), 0, stream, single,
-                       descs, off, ninst, koff);
+    hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, AXIS, SEG, MULTI, ADJ, POTX>), dim3(tiles), dim3(threads), 0, stream,
+                       single, descs, off, ninst, koff);
     return hipGetLastError();
 }
 
@@ -609,9 +634,18 @@ template <int N, int N1, int N2, int P, bool SEG>
 static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                int tiles, int koff, hipStream_t stream) {
     if (ninst == 0) {
+        // unsegmented axes may take the potential in the x pass
+        if (!SEG && single.potx) {
+            if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
+            if (axis == 2) return launch_kernel<N, N1, N2, P, 2, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
+        }
         if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
         if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
         return launch_kernel<N, N1, N2, P, 2, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+    }
+    if (!SEG && single.potx) {
+        if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
+        if (axis == 2) return launch_kernel<N, N1, N2, P, 2, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
     }
     if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
     if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
@@ -680,11 +714,12 @@ int variant_tiles(int v, int axis, PassArgs& a) {
 }
 
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, int koff, hipStream_t stream) {
+                          int total_tiles, int koff, int potx, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants || ninst < 1) return hipErrorInvalidValue;
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
-    const PassArgs none{};
+    PassArgs none{};
+    none.potx = potx;   // only this field of the by-value argument is read in a group launch
     return f(axis, none, descs, off, ninst, total_tiles, koff, stream);
 }
 

@@ -36,6 +36,9 @@ CASES = {
     "cube24": dict(n=(24, 24, 24), P=4, transition=3),
     "aniso": dict(n=(24, 20, 32), P=3, transition=2, theta=0.7, phi=2.1),
     "ragged": dict(n=(48, 40, 32), P=4, transition=4, theta=2.3, phi=4.4),
+    # the taper's core covers 40 % of the x rows: the z pass takes the
+    # potential term (the other cases: the x pass, V's box being small)
+    "widebox": dict(n=(24, 20, 32), P=2, transition=1, theta=1.1, phi=0.3),
 }
 
 
