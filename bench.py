@@ -174,9 +174,11 @@ def main():
     # the whole timed region sits inside the surface-DFT window
     prob = prob.replace(dft_begin=0, dft_end=10 ** 12)
     if args.surface == "sphere":
-        # spherical equivalence surface of radius 5
-        prob = prob.replace(surface_kind=1, sphere_radius=5.0, sphere_nodes=(64, 128))
-        surface = "spherical equivalence surface r=5.0 (64x128 nodes, shell DFT every step)"
+        # spherical equivalence surface of radius 5 (on grids under 160 points
+        # the largest radius whose shell stays out of the absorber: 4.3 at 128)
+        radius = min(5.0, round((args.n // 2 - 16 - 5) * prob.h[0], 6))
+        prob = prob.replace(surface_kind=1, sphere_radius=radius, sphere_nodes=(64, 128))
+        surface = f"spherical equivalence surface r={radius} (64x128 nodes, shell DFT every step)"
     else:
         surface = "box equivalence surface at N/2-+40 (plane DFT sums inside the passes every step)"
     dev = torch.device("cuda:0")
@@ -231,7 +233,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 FFT grid (128^3 inside a 16-cell absorber), "
+            "workload": f"square barrier r=2.4 V0=E0/2, {args.n}^3 FFT grid ({args.n - 32}^3 inside a 16-cell absorber), "
                         f"k0=pi/(4h), TF/SF + absorber, {surface}",
             "grid": [args.n] * 3,
             "cells": cells,

@@ -195,6 +195,24 @@ std::vector<float> scaled_potential(const pstd_solver* s, const float* V) {
     return box;
 }
 
+// 2 dtau (V / E0 + sum_a w_a) on every cell, [k][j][i] (the FDTD scheme's
+// potential array; null V: the absorber's real part alone)
+std::vector<float> scaled_potential_full(const pstd_solver* s, const float* V) {
+    const pstd_problem& p = s->prob;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const std::vector<double> wx = absorber_real(p, 0), wy = absorber_real(p, 1), wz = absorber_real(p, 2);
+    const double scale = 2.0 * s->dtau / s->E0, sw = 2.0 * s->dtau;
+    std::vector<float> v2((size_t)s->cells);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t id = i + (int64_t)nx * (j + (int64_t)ny * k);
+                const double v = V ? (double)V[id] : 0.0;
+                v2[id] = (float)(scale * v + sw * (wx[i] + wy[j] + wz[k]));
+            }
+    return v2;
+}
+
 template <class T>
 pstd_status upload(pstd_solver* s, T* dst, const std::vector<T>& src) {
     HIP_TRY(s, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -360,7 +378,7 @@ pstd::FdtdArgs fdtd_args(const pstd_solver* s) {
     pstd::FdtdArgs a{};
     a.buf[0] = s->buf[0];
     a.buf[1] = s->buf[1];
-    a.pot = s->pot;
+    a.v2 = s->v2full;
     a.nx = s->prob.n[0];
     a.ny = s->prob.n[1];
     a.nz = s->prob.n[2];
@@ -655,6 +673,12 @@ pstd_status solver_create(const pstd_problem* p, hipStream_t stream, int64_t* ex
     if ((e = hipMalloc(&s->vbox, nbox * sizeof(float))) || (e = hipMemset(s->vbox, 0, nbox * sizeof(float))))
         return cleanup(hip_fail(s, e, "potential"));
     s->pot.box = s->vbox;
+    if (p->scheme == 1) {
+        const std::vector<float> full = scaled_potential_full(s, nullptr);
+        if ((e = hipMalloc(&s->v2full, full.size() * sizeof(float))) ||
+            (e = hipMemcpy(s->v2full, full.data(), full.size() * sizeof(float), hipMemcpyHostToDevice)))
+            return cleanup(hip_fail(s, e, "potential"));
+    }
     // where the potential term is taken: in the x pass (re-reading psi^n from
     // the cache on the rows that cross V's box) when the box covers under a
     // quarter of the rows, else in the z pass (psi^n held in registers); the
@@ -877,6 +901,10 @@ pstd_status pstd_set_potential(pstd_solver* s, const float* V_dev, int64_t n_cel
         return fail(s, PSTD_EUNSTABLE, "max |V| exceeds v_max used to size the step");
     const std::vector<float> box = scaled_potential(s, V.data());
     HIP_TRY(s, hipMemcpy(s->vbox, box.data(), box.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (s->v2full) {
+        const std::vector<float> full = scaled_potential_full(s, V.data());
+        HIP_TRY(s, hipMemcpy(s->v2full, full.data(), full.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     return PSTD_OK;
 }
 
@@ -1322,6 +1350,7 @@ pstd_status pstd_destroy(pstd_solver* s) {
     (void)hipFree(s->buf[1]);
     (void)hipFree(s->L);
     (void)hipFree(s->vbox);
+    (void)hipFree(s->v2full);
     (void)hipFree(s->wr);
     (void)hipFree(s->tables);
     (void)hipFree(s->sigma_tab);

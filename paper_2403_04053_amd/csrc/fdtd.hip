@@ -107,12 +107,7 @@ __global__ __launch_bounds__(kFX * kFY) __attribute__((amdgpu_waves_per_eu(5))) 
         if (valid) {
             const int64_t ad = x + (int64_t)nx * y + plane * z;
             po_n = old[ad];
-            vv_n = 0.f;
-            if ((unsigned)(x - a.pot.lo[0]) < (unsigned)a.pot.n[0] && (unsigned)(y - a.pot.lo[1]) < (unsigned)a.pot.n[1] &&
-                (unsigned)(z - a.pot.lo[2]) < (unsigned)a.pot.n[2])
-                vv_n = a.pot.box[(x - a.pot.lo[0]) +
-                                 (int64_t)a.pot.n[0] * ((y - a.pot.lo[1]) + (int64_t)a.pot.n[1] * (z - a.pot.lo[2]))];
-            if (a.pot.wr[0]) vv_n += a.pot.wr[0][x] + a.pot.wr[1][y] + a.pot.wr[2][z];
+            vv_n = a.v2[ad];
         }
     };
     if (z0 < z1) load_plane(z0);

@@ -77,7 +77,8 @@ struct PassArgs {
 // (psi(-l e_a) + psi(+l e_a)) + v2 psi + sigma_n sum_a dz_a prod_{b != a} zt_b
 struct FdtdArgs {
     float2* buf[2];
-    PotentialArgs pot;
+    const float* v2;           // 2 dtau (V / E0 + sum_a w_a) on every cell (the stencil step reads it
+                               // beside psi^{n-1}, at the same address)
     int nx, ny, nz;
     const float* gam[3];       // mask factors per axis
     const float2* zt[3];       // T_a e^{i kh_a x_a}

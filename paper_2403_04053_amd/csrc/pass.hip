@@ -12,9 +12,10 @@
 // Loads and stores are coalesced without an LDS transpose: the x pass gives
 // consecutive lanes consecutive elements of a row; the y and z passes give
 // consecutive lanes consecutive x of a tile of P pencils.  The per-axis
-// twiddles and kbar^2 are staged in LDS once per workgroup; the derivative
-// rows of the surface planes (used only inside the DFT window) are read from
-// global memory, where neighbouring lanes read neighbouring entries.
+// twiddles and kbar^2 are staged in LDS once per workgroup, and so are the
+// derivative rows of the surface planes (used only inside the DFT window)
+// for N <= 200; longer pencils read those rows from global memory, where
+// neighbouring lanes read neighbouring entries, to keep their occupancy.
 //
 // Epilogues: x pass writes L; y pass adds to L (which it reads at the start,
 // with the field); z pass adds its term and applies the leapfrog update with
@@ -229,6 +230,10 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     __shared__ float2 ex[P * STRIDE];
     __shared__ float2 s_tw[N];
     __shared__ float s_kk[N];
+    // derivative rows of the surface planes: staged in LDS where that costs
+    // no occupancy (N <= 200), read from global memory otherwise
+    constexpr bool kRowsInLds = N <= 200;
+    __shared__ float2 s_dl[kRowsInLds ? N : 1], s_dh[kRowsInLds ? N : 1];
 
     const int t = threadIdx.x;
     const bool activeA = t < P * N2;
@@ -266,7 +271,20 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     for (int i = t; i < N; i += NT) {
         s_tw[i] = f.tw[i];
         s_kk[i] = f.kk[i];
+        if (kRowsInLds && surf) {
+            s_dl[i] = f.dlo[i];
+            s_dh[i] = f.dhi[i];
+        }
     }
+    // entry e of the low (hi = false) or high plane's derivative row
+    auto drow = [&](bool hi, int e) -> float2 {
+        if constexpr (kRowsInLds) {
+            return hi ? s_dh[e] : s_dl[e];
+        } else {
+            const float2 r = hi ? f.dhi[e] : f.dlo[e];
+            return r;
+        }
+    };
 
     {
         const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
@@ -314,8 +332,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                 constexpr int n1 = decltype(i)::value;
                 const int e = n2 + N2 * n1;
                 if (e < N) {
-                    dlo = cadd(dlo, cmul(f.dlo[e], v[n1]));
-                    dhi = cadd(dhi, cmul(f.dhi[e], v[n1]));
+                    dlo = cadd(dlo, cmul(drow(false, e), v[n1]));
+                    dhi = cadd(dhi, cmul(drow(true, e), v[n1]));
                 }
             });
         }
@@ -386,7 +404,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     constexpr int n1 = decltype(i)::value;
                     const int e = n2 + N2 * n1;
                     if (e < N) {
-                        float2 x = cadd(cmul(f.dlo[e], hdl), cmul(f.dhi[e], hdh));
+                        float2 x = cadd(cmul(drow(false, e), hdl), cmul(drow(true, e), hdh));
                         if (e == plane_lo) x = cadd(x, hpl);
                         if (e == plane_hi) x = cadd(x, hph);
                         v[n1] = cadd(v[n1], x);

@@ -34,6 +34,7 @@ struct pstd_solver {
     float* vbox = nullptr;       // 2 dtau V / E0 on the taper's core
     float* wr = nullptr;         // complex absorber: 2 dtau w_a per axis (null without it)
     pstd::PotentialArgs pot{};
+    float* v2full = nullptr;     // FDTD scheme only: 2 dtau (V / E0 + sum_a w_a) on every cell
     int potx = 0;                // the x pass takes the potential term (see solver_create)
     void* tables = nullptr;
     pstd::AxisTables ax[3]{};
