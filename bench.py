@@ -33,22 +33,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # dispatch, scaled by what the same counters read for a plain copy of 512 MiB:
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
-# (N, N1, N2, pencils per workgroup, axis).
+# (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
 TRAFFIC_SRC_SHA256 = "d535bf9fa113b6b4b7852c9756d52863edd769c279bd263dfc533ae028657c86"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 10, 16, 16, 0): (33646, 32000), (160, 10, 16, 16, 1): (64170, 32000), (160, 10, 16, 16, 2): (96294, 32000),
-    (160, 10, 16, 32, 0): (33164, 32000), (160, 10, 16, 32, 1): (64158, 32000), (160, 10, 16, 32, 2): (96276, 32000),
-    (160, 10, 16, 8, 0): (33776, 32000), (160, 10, 16, 8, 1): (64192, 32230), (160, 10, 16, 8, 2): (96286, 32138),
-    (160, 16, 10, 16, 0): (32944, 32000), (160, 16, 10, 16, 1): (64188, 32000), (160, 16, 10, 16, 2): (96326, 32000),
-    (160, 20, 8, 16, 0): (32676, 32000), (160, 20, 8, 16, 1): (64180, 32000), (160, 20, 8, 16, 2): (96318, 32000),
-    (160, 8, 20, 16, 0): (33354, 32000), (160, 8, 20, 16, 1): (64168, 32000), (160, 8, 20, 16, 2): (96294, 32000),
-    (288, 12, 24, 16, 0): (187998, 186624), (288, 12, 24, 16, 1): (373486, 186624), (288, 12, 24, 16, 2): (560562, 186624),
-    (288, 12, 24, 8, 0): (190298, 186625), (288, 12, 24, 8, 1): (373878, 190626), (288, 12, 24, 8, 2): (561532, 190005),
-    (288, 16, 18, 16, 0): (187424, 186625), (288, 16, 18, 16, 1): (373492, 186624), (288, 16, 18, 16, 2): (560726, 186624),
-    (288, 16, 18, 32, 0): (188130, 186632), (288, 16, 18, 32, 1): (373560, 186624), (288, 16, 18, 32, 2): (560992, 186624),
-    (288, 18, 16, 16, 0): (187432, 186624), (288, 18, 16, 16, 1): (373476, 186624), (288, 18, 16, 16, 2): (560508, 186624),
-    (288, 24, 12, 16, 0): (187342, 186625), (288, 24, 12, 16, 1): (373482, 186624), (288, 24, 12, 16, 2): (560612, 186624),
-    (288, 24, 12, 8, 0): (187400, 186624), (288, 24, 12, 8, 1): (373524, 190302), (288, 24, 12, 8, 2): (560460, 186681),
+    (160, 10, 16, 16, 0, 0): (33646, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96294, 32000),
+    (160, 10, 16, 32, 0, 0): (33164, 32000), (160, 10, 16, 32, 0, 1): (64158, 32000), (160, 10, 16, 32, 0, 2): (96276, 32000),
+    (160, 10, 16, 8, 0, 0): (33776, 32000), (160, 10, 16, 8, 0, 1): (64192, 32230), (160, 10, 16, 8, 0, 2): (96286, 32138),
+    (160, 16, 10, 16, 0, 0): (32944, 32000), (160, 16, 10, 16, 0, 1): (64188, 32000), (160, 16, 10, 16, 0, 2): (96326, 32000),
+    (160, 20, 8, 16, 0, 0): (32676, 32000), (160, 20, 8, 16, 0, 1): (64180, 32000), (160, 20, 8, 16, 0, 2): (96318, 32000),
+    (160, 8, 20, 16, 0, 0): (33354, 32000), (160, 8, 20, 16, 0, 1): (64168, 32000), (160, 8, 20, 16, 0, 2): (96294, 32000),
+    (288, 12, 24, 16, 0, 0): (187998, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560562, 186624),
+    (288, 12, 24, 8, 0, 0): (190298, 186625), (288, 12, 24, 8, 0, 1): (373878, 190626), (288, 12, 24, 8, 0, 2): (561532, 190005),
+    (288, 16, 18, 16, 0, 0): (187424, 186625), (288, 16, 18, 16, 0, 1): (373492, 186624), (288, 16, 18, 16, 0, 2): (560726, 186624),
+    (288, 16, 18, 32, 0, 0): (188130, 186632), (288, 16, 18, 32, 0, 1): (373560, 186624), (288, 16, 18, 32, 0, 2): (560992, 186624),
+    (288, 18, 16, 16, 0, 0): (187432, 186624), (288, 18, 16, 16, 0, 1): (373476, 186624), (288, 18, 16, 16, 0, 2): (560508, 186624),
+    (288, 24, 12, 16, 0, 0): (187342, 186625), (288, 24, 12, 16, 0, 1): (373482, 186624), (288, 24, 12, 16, 0, 2): (560612, 186624),
+    (288, 24, 12, 8, 0, 0): (187400, 186624), (288, 24, 12, 8, 0, 1): (373524, 190302), (288, 24, 12, 8, 0, 2): (560460, 186681),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")
@@ -581,7 +581,7 @@ def bench_pulse(args):
         s.set_potential(V)
         if tune is not None:
             for axis in range(3):
-                s.set_tile(axis, *tune[axis][1:2], *tune[axis][3:4])
+                s.set_tile(axis, tune[axis][1], tune[axis][3], tune[axis][4])
         else:
             tune = s.autotune(reps=20)
         if pulse:

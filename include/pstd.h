@@ -204,18 +204,20 @@ pstd_status pstd_check_state_noalloc(pstd_solver* s, double* norm2_out_host);
  * touched.  Synchronises. */
 pstd_status pstd_pass_time(pstd_solver* s, int32_t axis, int32_t reps, double* us_out_host);
 
-/* Tile shape used by the pass along axis (0, 1, 2): info_host[4] =
- * {N, N1, N2, pencils per workgroup}.  Host only. */
+/* Tile shape used by the pass along axis (0, 1, 2): info_host[5] =
+ * {N, N1, N2, pencils per workgroup, M1}; M1 > 0 when stage B (the N2-point
+ * DFTs) is split as N2 = M1 * (N2 / M1) over all N2 threads of a pencil, 0
+ * otherwise.  Host only. */
 pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_host);
 
-/* Use the compiled tile shape of axis `axis` with stage-A factor n1 and
- * `pencils` pencils per workgroup.  EUNSUPPORTED if there is none.
- * Synchronises. */
-pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils);
+/* Use the compiled tile shape of axis `axis` with stage-A factor n1,
+ * `pencils` pencils per workgroup and stage-B split m1 (0: none).
+ * EUNSUPPORTED if there is none.  Synchronises. */
+pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils, int32_t m1);
 
 /* Compiled tile shapes for pass length n (segmented != 0: subdomain mode):
- * writes up to cap triples {N1, N2, pencils} to shapes_host[3*cap] and the
- * total number to *count_out.  Host only. */
+ * writes up to cap quadruples {N1, N2, pencils, M1} to shapes_host[4*cap]
+ * and the total number to *count_out.  Host only. */
 pstd_status pstd_tile_variants(int32_t n, int32_t segmented, int32_t* shapes_host, int32_t cap, int32_t* count_out);
 
 /* Number of steps taken (the current level is psi^step). */

@@ -153,7 +153,7 @@ _SIGS = {
     "pstd_check_state": [_vp, ctypes.POINTER(ctypes.c_double)],
     "pstd_check_state_noalloc": [_vp, ctypes.POINTER(ctypes.c_double)],
     "pstd_tile_info": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
-    "pstd_set_tile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "pstd_set_tile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "pstd_tile_variants": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                            ctypes.POINTER(ctypes.c_int32)],
     "pstd_batch_create": [ctypes.c_void_p, ctypes.c_int32, _vp, ctypes.POINTER(_vp)],
@@ -362,20 +362,21 @@ def pstd_autotune(solver, reps=5):
 
 
 def pstd_tile_info(solver, axis):
-    out = (ctypes.c_int32 * 4)()
+    """(N, N1, N2, pencils, M1) of the pass along `axis`."""
+    out = (ctypes.c_int32 * 5)()
     _check(lib.pstd_tile_info(solver, int(axis), out), solver)
     return tuple(out)
 
 
-def pstd_set_tile(solver, axis, n1, pencils):
-    _check(lib.pstd_set_tile(solver, int(axis), int(n1), int(pencils)), solver)
+def pstd_set_tile(solver, axis, n1, pencils, m1=0):
+    _check(lib.pstd_set_tile(solver, int(axis), int(n1), int(pencils), int(m1)), solver)
 
 
 def pstd_tile_variants(n, segmented=False):
     cnt = ctypes.c_int32()
-    buf = (ctypes.c_int32 * 48)()
+    buf = (ctypes.c_int32 * 64)()
     _check(lib.pstd_tile_variants(int(n), int(bool(segmented)), buf, 16, ctypes.byref(cnt)))
-    return [tuple(buf[3 * k:3 * k + 3]) for k in range(min(cnt.value, 16))]
+    return [tuple(buf[4 * k:4 * k + 4]) for k in range(min(cnt.value, 16))]
 
 
 def pstd_destroy(solver):
@@ -474,8 +475,8 @@ class Solver:
         pstd_autotune(self.handle, reps)
         return [pstd_tile_info(self.handle, a) for a in range(3)]
 
-    def set_tile(self, axis, n1, pencils):
-        pstd_set_tile(self.handle, axis, n1, pencils)
+    def set_tile(self, axis, n1, pencils, m1=0):
+        pstd_set_tile(self.handle, axis, n1, pencils, m1)
 
     def tiles(self):
         return [pstd_tile_info(self.handle, a) for a in range(3)]

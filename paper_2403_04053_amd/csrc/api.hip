@@ -1061,24 +1061,25 @@ pstd_status pstd_tile_info(const pstd_solver* s, int32_t axis, int32_t* info_hos
     info_host[1] = sh.N1;
     info_host[2] = sh.N2;
     info_host[3] = sh.P;
+    info_host[4] = sh.M1;
     return PSTD_OK;
 }
 
-pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils) {
+pstd_status pstd_set_tile(pstd_solver* s, int32_t axis, int32_t n1, int32_t pencils, int32_t m1) {
     if (!s || axis < 0 || axis > 2) return PSTD_EINVAL;
     const bool seg = s->prob.sub_core[axis] > 0;
     int ids[16];
     const int nv = std::min(16, pass_variants(local_len(s->prob, axis), seg, ids, 16));
     for (int k = 0; k < nv; ++k) {
         const PassShape sh = variant_shape(ids[k]);
-        if (sh.N1 == n1 && sh.P == pencils) {
+        if (sh.N1 == n1 && sh.P == pencils && sh.M1 == m1) {
             HIP_TRY(s, hipStreamSynchronize(s->stream));
             s->variant[axis] = ids[k];
             solver_drop_graph(s);
             return PSTD_OK;
         }
     }
-    return fail(s, PSTD_EUNSUPPORTED, "no compiled tile shape with that factor and pencil count");
+    return fail(s, PSTD_EUNSUPPORTED, "no compiled tile shape with that factor, pencil count and stage-B split");
 }
 
 pstd_status pstd_tile_variants(int32_t n, int32_t segmented, int32_t* shapes_host, int32_t cap, int32_t* count_out) {
@@ -1087,9 +1088,10 @@ pstd_status pstd_tile_variants(int32_t n, int32_t segmented, int32_t* shapes_hos
     const int nv = std::min(16, pass_variants(n, segmented != 0, ids, 16));
     for (int k = 0; k < nv && k < cap; ++k) {
         const PassShape sh = variant_shape(ids[k]);
-        shapes_host[3 * k] = sh.N1;
-        shapes_host[3 * k + 1] = sh.N2;
-        shapes_host[3 * k + 2] = sh.P;
+        shapes_host[4 * k] = sh.N1;
+        shapes_host[4 * k + 1] = sh.N2;
+        shapes_host[4 * k + 2] = sh.P;
+        shapes_host[4 * k + 3] = sh.M1;
     }
     *count_out = nv;
     return PSTD_OK;

@@ -92,9 +92,10 @@ hipError_t launch_fdtd(const FdtdArgs& args, int koff, hipStream_t stream);
 // the stencil coefficients of Eq. stencil_alpha
 extern const double kFdtdAlpha[5];
 
-// FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup
+// FFT-length configuration of a pass: N = N1 * N2, P pencils per workgroup;
+// M1 > 0: stage B split as N2 = M1 * (N2 / M1) over all N2 threads of a pencil
 struct PassShape {
-    int N, N1, N2, P, threads;
+    int N, N1, N2, P, threads, M1;
 };
 
 // Compiled tile-shape variants for local length N (segmented: with a

@@ -9,6 +9,13 @@
 // the same stages backwards, so no digit-reversal pass is needed and the
 // result returns to the registers it was loaded into.
 //
+// Where N1 < N2, N2 - N1 of a pencil's threads idle in stage B.  Shapes with
+// M1 > 0 split stage B once more, N2 = M1 M2 (M1 and M2 both dividing N1):
+// every thread of the pencil does N1/M1 M1-point DFTs (B1), then, after a
+// second exchange in the same LDS rows, N1/M2 M2-point DFTs (B2) with the
+// kbar^2 scaling between the forward and inverse M2-point DFTs; so all N2
+// threads work in every stage and no thread holds more than N1 elements.
+//
 // Loads and stores are coalesced without an LDS transpose: the x pass gives
 // consecutive lanes consecutive elements of a row; the y and z passes give
 // consecutive lanes consecutive x of a tile of P pencils.  The per-axis
@@ -218,7 +225,7 @@ __device__ __forceinline__ void load_tile(GMEM const float2* __restrict__ psi, c
 
 // One workgroup per tile of P pencils; MULTI launches find their instance
 // from the prefix table of tiles.
-template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
+template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
                                                                        const PassArgs* __restrict__ descs,
                                                                        const int* __restrict__ off, int ninst,
@@ -355,25 +362,96 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         __syncthreads();
 
         // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
-        if (t < P * N1) {
-            const int pB = AXIS == 0 ? t / N1 : t % P;
-            const int k1 = AXIS == 0 ? t % N1 : t / P;
-            float2 u[N2];
-            unroll<N2>([&](auto i) { u[decltype(i)::value] = ex[pB * STRIDE + k1 * ROW + decltype(i)::value]; });
-            dft<N2, -1>(u);
-            unroll<N2>([&](auto i) {
-                constexpr int k2 = decltype(i)::value;
-                u[k2] = cscale(u[k2], s_kk[k1 + N1 * k2]);
-            });
-            dft<N2, 1>(u);
-            unroll<N2>([&](auto i) {
-                constexpr int nn = decltype(i)::value;
-                float2 x = u[nn];
-                if constexpr (nn != 0) x = cmulc(x, s_tw[nn * k1]);
-                ex[pB * STRIDE + k1 * ROW + nn] = x;
-            });
+        if constexpr (M1 == 0) {
+            if (t < P * N1) {
+                // consecutive lanes on consecutive pencils (odd LDS stride) on
+                // every axis: stage B touches LDS only
+                const int pB = t % P;
+                const int k1 = t / P;
+                float2 u[N2];
+                unroll<N2>([&](auto i) { u[decltype(i)::value] = ex[pB * STRIDE + k1 * ROW + decltype(i)::value]; });
+                dft<N2, -1>(u);
+                unroll<N2>([&](auto i) {
+                    constexpr int k2 = decltype(i)::value;
+                    u[k2] = cscale(u[k2], s_kk[k1 + N1 * k2]);
+                });
+                dft<N2, 1>(u);
+                unroll<N2>([&](auto i) {
+                    constexpr int nn = decltype(i)::value;
+                    float2 x = u[nn];
+                    if constexpr (nn != 0) x = cmulc(x, s_tw[nn * k1]);
+                    ex[pB * STRIDE + k1 * ROW + nn] = x;
+                });
+            }
+            __syncthreads();
+        } else {
+            // n2 = m2 + M2 m1, k2 = j1 + M1 j2: the N2-point DFT of row k1 is
+            // M1-point DFTs over m1 (B1), the twiddle w_N2^{m2 j1}, and M2-point
+            // DFTs over m2 (B2).  B1 works on the pairs (k1, m2) and writes
+            // output j1 to slot m2 + M2 j1 of the row, so B2's inputs for
+            // (k1, j1) are the M2 consecutive slots from M2 j1.
+            constexpr int M2 = N2 / M1;
+            static_assert(M1 * M2 == N2 && N1 % M1 == 0 && N1 % M2 == 0, "stage-B split");
+            constexpr int R1 = N1 / M1;  // B1 pairs per thread
+            constexpr int R2 = N1 / M2;  // B2 pairs per thread
+            if (activeA) {
+                unroll<R1>([&](auto ri) {
+                    const int q = n2 + N2 * decltype(ri)::value;
+                    const int k1 = q / M2, m2 = q - (q / M2) * M2;
+                    float2* row = &ex[pA * STRIDE + k1 * ROW + m2];
+                    float2 w[M1];
+                    unroll<M1>([&](auto i) { w[decltype(i)::value] = row[M2 * decltype(i)::value]; });
+                    dft<M1, -1>(w);
+                    unroll<M1>([&](auto i) {
+                        constexpr int j1 = decltype(i)::value;
+                        float2 x = w[j1];
+                        if constexpr (j1 != 0) x = cmul(x, s_tw[N1 * m2 * j1]);
+                        row[M2 * j1] = x;
+                    });
+                });
+            }
+            __syncthreads();
+            if (activeA) {
+                unroll<R2>([&](auto ri) {
+                    const int q = n2 + N2 * decltype(ri)::value;
+                    const int k1 = q / M1, j1 = q - (q / M1) * M1;
+                    float2* row = &ex[pA * STRIDE + k1 * ROW + M2 * j1];
+                    float2 u[M2];
+                    unroll<M2>([&](auto i) { u[decltype(i)::value] = row[decltype(i)::value]; });
+                    dft<M2, -1>(u);
+                    unroll<M2>([&](auto i) {
+                        constexpr int j2 = decltype(i)::value;
+                        u[j2] = cscale(u[j2], s_kk[k1 + N1 * (j1 + M1 * j2)]);
+                    });
+                    dft<M2, 1>(u);
+                    unroll<M2>([&](auto i) { row[decltype(i)::value] = u[decltype(i)::value]; });
+                });
+            }
+            __syncthreads();
+            if (activeA) {
+                unroll<R1>([&](auto ri) {
+                    const int q = n2 + N2 * decltype(ri)::value;
+                    const int k1 = q / M2, m2 = q - (q / M2) * M2;
+                    float2* row = &ex[pA * STRIDE + k1 * ROW + m2];
+                    float2 w[M1];
+                    unroll<M1>([&](auto i) {
+                        constexpr int j1 = decltype(i)::value;
+                        float2 x = row[M2 * j1];
+                        if constexpr (j1 != 0) x = cmulc(x, s_tw[N1 * m2 * j1]);
+                        w[j1] = x;
+                    });
+                    dft<M1, 1>(w);
+                    // back in slot n2 = m2 + M2 m1, with stage A's inverse twiddle
+                    unroll<M1>([&](auto i) {
+                        constexpr int m1 = decltype(i)::value;
+                        float2 x = w[m1];
+                        x = cmulc(x, s_tw[(m2 + M2 * m1) * k1]);
+                        row[M2 * m1] = x;
+                    });
+                });
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         // ---- inverse: stage A ----
         if (activeA) {
@@ -589,92 +667,95 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
 }
 
 // ---------------------------------------------------------------------------
-// compiled tile shapes: (N, N1, N2, P, with a segmented instance)
+// compiled tile shapes: (N, N1, N2, M1 (stage-B split, 0: none), P, with a
+// segmented instance)
 // ---------------------------------------------------------------------------
 
 #define PSTD_VARIANTS(X)        \
-    X(8, 2, 4, 64, 0)           \
-    X(12, 3, 4, 64, 0)          \
-    X(16, 4, 4, 64, 0)          \
-    X(20, 4, 5, 32, 0)          \
-    X(24, 4, 6, 32, 0)          \
-    X(32, 4, 8, 32, 1)          \
-    X(40, 5, 8, 32, 0)          \
-    X(48, 6, 8, 32, 1)          \
-    X(48, 8, 6, 32, 0)          \
-    X(64, 8, 8, 32, 1)          \
-    X(64, 8, 8, 16, 1)          \
-    X(80, 8, 10, 16, 0)         \
-    X(96, 8, 12, 16, 1)         \
-    X(100, 10, 10, 16, 0)       \
-    X(108, 9, 12, 16, 0)        \
-    X(120, 10, 12, 16, 0)       \
-    X(128, 8, 16, 16, 1)        \
-    X(128, 16, 8, 16, 0)        \
-    X(128, 8, 16, 32, 0)        \
-    X(144, 12, 12, 16, 0)       \
-    X(150, 10, 15, 16, 0)       \
-    X(150, 15, 10, 16, 0)       \
-    X(160, 10, 16, 16, 0)       \
-    X(160, 16, 10, 16, 0)       \
-    X(160, 10, 16, 32, 0)       \
-    X(160, 10, 16, 8, 0)        \
-    X(160, 8, 20, 16, 0)        \
-    X(160, 20, 8, 16, 0)        \
-    X(162, 9, 18, 16, 0)        \
-    X(162, 9, 18, 32, 0)        \
-    X(180, 12, 15, 16, 0)       \
-    X(180, 15, 12, 16, 0)       \
-    X(192, 12, 16, 16, 0)       \
-    X(256, 16, 16, 16, 0)       \
-    X(288, 16, 18, 16, 0)       \
-    X(288, 18, 16, 16, 0)       \
-    X(288, 16, 18, 32, 0)       \
-    X(288, 12, 24, 8, 0)        \
-    X(288, 24, 12, 8, 0)        \
-    X(288, 12, 24, 16, 0)       \
-    X(288, 24, 12, 16, 0)
+    X(8, 2, 4, 0, 64, 0)           \
+    X(12, 3, 4, 0, 64, 0)          \
+    X(16, 4, 4, 0, 64, 0)          \
+    X(20, 4, 5, 0, 32, 0)          \
+    X(24, 4, 6, 0, 32, 0)          \
+    X(32, 4, 8, 0, 32, 1)          \
+    X(40, 5, 8, 0, 32, 0)          \
+    X(48, 6, 8, 0, 32, 1)          \
+    X(48, 8, 6, 0, 32, 0)          \
+    X(64, 8, 8, 0, 32, 1)          \
+    X(64, 8, 8, 0, 16, 1)          \
+    X(80, 8, 10, 0, 16, 0)         \
+    X(96, 8, 12, 0, 16, 1)         \
+    X(100, 10, 10, 0, 16, 0)       \
+    X(108, 9, 12, 0, 16, 0)        \
+    X(120, 10, 12, 0, 16, 0)       \
+    X(128, 8, 16, 0, 16, 1)        \
+    X(128, 16, 8, 0, 16, 0)        \
+    X(128, 8, 16, 0, 32, 0)        \
+    X(128, 8, 16, 4, 16, 0)        \
+    X(144, 12, 12, 0, 16, 0)       \
+    X(150, 10, 15, 0, 16, 0)       \
+    X(150, 15, 10, 0, 16, 0)       \
+    X(160, 10, 16, 0, 16, 0)       \
+    X(160, 16, 10, 0, 16, 0)       \
+    X(160, 10, 16, 0, 32, 0)       \
+    X(160, 10, 16, 0, 8, 0)        \
+    X(160, 8, 20, 0, 16, 0)        \
+    X(160, 20, 8, 0, 16, 0)        \
+    X(162, 9, 18, 0, 16, 0)        \
+    X(162, 9, 18, 0, 32, 0)        \
+    X(180, 12, 15, 0, 16, 0)       \
+    X(180, 15, 12, 0, 16, 0)       \
+    X(192, 12, 16, 0, 16, 0)       \
+    X(256, 16, 16, 0, 16, 0)       \
+    X(288, 16, 18, 0, 16, 0)       \
+    X(288, 18, 16, 0, 16, 0)       \
+    X(288, 16, 18, 0, 32, 0)       \
+    X(288, 12, 24, 0, 8, 0)        \
+    X(288, 24, 12, 0, 8, 0)        \
+    X(288, 12, 24, 0, 16, 0)       \
+    X(288, 24, 12, 0, 16, 0)       \
+    X(288, 12, 24, 4, 8, 0)
 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);
 
-template <int N, int N1, int N2, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
+template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
 hipError_t launch_kernel(const PassArgs& single, const PassArgs* descs, const int* off, int ninst, int tiles,
                          int koff, hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((pass_kernel<N, N1, N2, P, AXIS, SEG, MULTI, ADJ, POTX>), dim3(tiles), dim3(threads), 0, stream,
+    hipLaunchKernelGGL((pass_kernel<N, N1, N2, M1, P, AXIS, SEG, MULTI, ADJ, POTX>), dim3(tiles), dim3(threads), 0, stream,
                        single, descs, off, ninst, koff);
     return hipGetLastError();
 }
 
-template <int N, int N1, int N2, int P, bool SEG>
+template <int N, int N1, int N2, int M1, int P, bool SEG>
 static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                int tiles, int koff, hipStream_t stream) {
     if (ninst == 0) {
         // unsegmented axes may take the potential in the x pass
         if (!SEG && single.potx) {
-            if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
-            if (axis == 2) return launch_kernel<N, N1, N2, P, 2, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
+            if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
+            if (axis == 2) return launch_kernel<N, N1, N2, M1, P, 2, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
         }
-        if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
-        if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
-        return launch_kernel<N, N1, N2, P, 2, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        if (axis == 1) return launch_kernel<N, N1, N2, M1, P, 1, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        return launch_kernel<N, N1, N2, M1, P, 2, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
     }
     if (!SEG && single.potx) {
-        if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
-        if (axis == 2) return launch_kernel<N, N1, N2, P, 2, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
+        if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
+        if (axis == 2) return launch_kernel<N, N1, N2, M1, P, 2, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
     }
-    if (axis == 0) return launch_kernel<N, N1, N2, P, 0, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
-    if (axis == 1) return launch_kernel<N, N1, N2, P, 1, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
-    return launch_kernel<N, N1, N2, P, 2, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    if (axis == 1) return launch_kernel<N, N1, N2, M1, P, 1, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    return launch_kernel<N, N1, N2, M1, P, 2, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
 }
 
-template <int N, int N1, int N2, int P>
+template <int N, int N1, int N2, int M1, int P>
 static hipError_t launch_adjoint_shape(int axis, const PassArgs& a, int koff, hipStream_t stream) {
-    if (axis == 0) return launch_kernel<N, N1, N2, P, 0, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
-    if (axis == 1) return launch_kernel<N, N1, N2, P, 1, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
-    return launch_kernel<N, N1, N2, P, 2, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
+    if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
+    if (axis == 1) return launch_kernel<N, N1, N2, M1, P, 1, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
+    return launch_kernel<N, N1, N2, M1, P, 2, false, false, true>(a, nullptr, nullptr, 0, a.tiles, koff, stream);
 }
 
 using AdjFn = hipError_t (*)(int axis, const PassArgs& a, int koff, hipStream_t stream);
@@ -688,16 +769,16 @@ struct VariantEntry {
     AdjFn adj;
 };
 
-template <int N, int N1, int N2, int P, int S>
+template <int N, int N1, int N2, int M1, int P, int S>
 constexpr LaunchFn seg_fn() {
-    if constexpr (S != 0) return &launch_shape<N, N1, N2, P, true>;
+    if constexpr (S != 0) return &launch_shape<N, N1, N2, M1, P, true>;
     else return nullptr;
 }
 
 const VariantEntry kVariants[] = {
-#define PSTD_ENTRY(n, a, b, p, s)                                                                             \
-    {PassShape{n, a, b, p, p * (a > b ? a : b)}, &launch_shape<n, a, b, p, false>, seg_fn<n, a, b, p, s>(), \
-     &launch_adjoint_shape<n, a, b, p>},
+#define PSTD_ENTRY(n, a, b, m, p, s)                                                                           \
+    {PassShape{n, a, b, p, p * (a > b ? a : b), m}, &launch_shape<n, a, b, m, p, false>, seg_fn<n, a, b, m, p, s>(), \
+     &launch_adjoint_shape<n, a, b, m, p>},
     PSTD_VARIANTS(PSTD_ENTRY)
 #undef PSTD_ENTRY
 };

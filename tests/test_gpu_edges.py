@@ -76,7 +76,7 @@ def test_autotune_keeps_state_and_results(P):
     b = solver(P, prob, V)
     b.run(7)
     for ax, t in enumerate(tiles):
-        b.set_tile(ax, t[1], t[3])
+        b.set_tile(ax, t[1], t[3], t[4])
     b.run(33)
     assert torch.equal(a.psi(0), b.psi(0))
     _, _, cur, _ = opstd.run(prob, V)

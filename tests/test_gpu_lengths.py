@@ -30,14 +30,14 @@ def variants():
     import paper_2403_04053_amd as mod
     out = []
     for L in LENGTHS:
-        for (n1, n2, p) in mod.pstd_tile_variants(L):
-            out.append((L, n1, p))
+        for (n1, n2, p, m1) in mod.pstd_tile_variants(L):
+            out.append((L, n1, p, m1))
     return out
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("L,n1,pencils", variants())
-def test_length_single_step(P, L, n1, pencils, axis):
+@pytest.mark.parametrize("L,n1,pencils,m1", variants())
+def test_length_single_step(P, L, n1, pencils, m1, axis):
     n = [12, 12, 12]
     n[axis] = L
     prob = geometry(tuple(n))
@@ -46,8 +46,8 @@ def test_length_single_step(P, L, n1, pencils, axis):
     V[c[2] - 1:c[2] + 1, c[1] - 1:c[1] + 1, c[0] - 1:c[0] + 1] = 5.0
     s = P.Solver(prob)
     s.set_potential(V)
-    s.set_tile(axis, n1, pencils)
-    assert s.tiles()[axis] == (L, n1, L // n1, pencils)
+    s.set_tile(axis, n1, pencils, m1)
+    assert s.tiles()[axis] == (L, n1, L // n1, pencils, m1)
     prev = synth.random_state(prob.n, 1).astype(np.complex64)
     cur = synth.random_state(prob.n, 2).astype(np.complex64)
     s.set_state(prev, cur, 7)

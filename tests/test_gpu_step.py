@@ -165,13 +165,13 @@ def test_full_size_single_step_sampled(P, n):
             assert abs(gdphi[f][v, u] - w * d) <= 2e-5 * scale * np.abs(m.kb[a]).max() / R
     if n[0] in (160, 288):
         # every compiled tile shape (the autotuner may pick any), on all three axes
-        for (n1, n2, pencils) in P.pstd_tile_variants(n[0]):
+        for (n1, n2, pencils, m1) in P.pstd_tile_variants(n[0]):
             for ax in range(3):
-                s.set_tile(ax, n1, pencils)
+                s.set_tile(ax, n1, pencils, m1)
             s.set_state(prev, cur, step)
             s.run(1)
             e = sampled_err(s.psi(0).cpu().numpy())
-            print(n, "tile", (n1, n2, pencils), "sampled max err", e, flush=True)
+            print(n, "tile", (n1, n2, pencils, m1), "sampled max err", e, flush=True)
             assert e < 1e-5
 
 
