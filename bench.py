@@ -34,21 +34,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "d535bf9fa113b6b4b7852c9756d52863edd769c279bd263dfc533ae028657c86"
+TRAFFIC_SRC_SHA256 = "bccb734c87391127dbfa398827070aa91f80bac2bff2af0440181852b6aecab2"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 10, 16, 16, 0, 0): (33646, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96294, 32000),
-    (160, 10, 16, 32, 0, 0): (33164, 32000), (160, 10, 16, 32, 0, 1): (64158, 32000), (160, 10, 16, 32, 0, 2): (96276, 32000),
-    (160, 10, 16, 8, 0, 0): (33776, 32000), (160, 10, 16, 8, 0, 1): (64192, 32230), (160, 10, 16, 8, 0, 2): (96286, 32138),
-    (160, 16, 10, 16, 0, 0): (32944, 32000), (160, 16, 10, 16, 0, 1): (64188, 32000), (160, 16, 10, 16, 0, 2): (96326, 32000),
-    (160, 20, 8, 16, 0, 0): (32676, 32000), (160, 20, 8, 16, 0, 1): (64180, 32000), (160, 20, 8, 16, 0, 2): (96318, 32000),
-    (160, 8, 20, 16, 0, 0): (33354, 32000), (160, 8, 20, 16, 0, 1): (64168, 32000), (160, 8, 20, 16, 0, 2): (96294, 32000),
-    (288, 12, 24, 16, 0, 0): (187998, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560562, 186624),
-    (288, 12, 24, 8, 0, 0): (190298, 186625), (288, 12, 24, 8, 0, 1): (373878, 190626), (288, 12, 24, 8, 0, 2): (561532, 190005),
-    (288, 16, 18, 16, 0, 0): (187424, 186625), (288, 16, 18, 16, 0, 1): (373492, 186624), (288, 16, 18, 16, 0, 2): (560726, 186624),
-    (288, 16, 18, 32, 0, 0): (188130, 186632), (288, 16, 18, 32, 0, 1): (373560, 186624), (288, 16, 18, 32, 0, 2): (560992, 186624),
-    (288, 18, 16, 16, 0, 0): (187432, 186624), (288, 18, 16, 16, 0, 1): (373476, 186624), (288, 18, 16, 16, 0, 2): (560508, 186624),
-    (288, 24, 12, 16, 0, 0): (187342, 186625), (288, 24, 12, 16, 0, 1): (373482, 186624), (288, 24, 12, 16, 0, 2): (560612, 186624),
-    (288, 24, 12, 8, 0, 0): (187400, 186624), (288, 24, 12, 8, 0, 1): (373524, 190302), (288, 24, 12, 8, 0, 2): (560460, 186681),
+    (160, 8, 20, 16, 0, 0): (33371, 32001), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96301, 32000),
+    (160, 10, 16, 8, 0, 0): (33414, 32000), (160, 10, 16, 8, 0, 1): (64176, 32054), (160, 10, 16, 8, 0, 2): (96300, 32111),
+    (160, 10, 16, 16, 0, 0): (34372, 32000), (160, 10, 16, 16, 0, 1): (64157, 32000), (160, 10, 16, 16, 0, 2): (96277, 32000),
+    (160, 10, 16, 32, 0, 0): (34680, 32000), (160, 10, 16, 32, 0, 1): (64166, 32000), (160, 10, 16, 32, 0, 2): (96294, 32000),
+    (160, 16, 10, 16, 0, 0): (33545, 32000), (160, 16, 10, 16, 0, 1): (64187, 32000), (160, 16, 10, 16, 0, 2): (96319, 32000),
+    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96329, 32000),
+    (288, 12, 24, 8, 0, 0): (190110, 186626), (288, 12, 24, 8, 0, 1): (373932, 190745), (288, 12, 24, 8, 0, 2): (561497, 190025),
+    (288, 12, 24, 8, 4, 0): (190641, 186625), (288, 12, 24, 8, 4, 1): (373687, 190239), (288, 12, 24, 8, 4, 2): (561646, 189929),
+    (288, 12, 24, 16, 0, 0): (188159, 186624), (288, 12, 24, 16, 0, 1): (373487, 186624), (288, 12, 24, 16, 0, 2): (560585, 186624),
+    (288, 16, 18, 16, 0, 0): (187490, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560729, 186624),
+    (288, 16, 18, 32, 0, 0): (188623, 186640), (288, 16, 18, 32, 0, 1): (373555, 186624), (288, 16, 18, 32, 0, 2): (561010, 186624),
+    (288, 18, 16, 16, 0, 0): (187471, 186624), (288, 18, 16, 16, 0, 1): (373478, 186624), (288, 18, 16, 16, 0, 2): (560495, 186624),
+    (288, 24, 12, 8, 0, 0): (187452, 186624), (288, 24, 12, 8, 0, 1): (373523, 190359), (288, 24, 12, 8, 0, 2): (560450, 186683),
+    (288, 24, 12, 16, 0, 0): (187345, 186626), (288, 24, 12, 16, 0, 1): (373479, 186624), (288, 24, 12, 16, 0, 2): (560621, 186624),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                   "paper_2403_04053_amd/csrc/internal.hpp")
@@ -63,8 +64,8 @@ SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "79e21e1a9c32f67ab2d2768c6748464077f311f8847277ef525f346c447c8bfc"
-FDTD_TRAFFIC_KIB = {160: (105887, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "80e90e9187d093ca4bddfda5ab98ca2d1a8cc6a4cfd3a4872e9b73debf51310c"
+FDTD_TRAFFIC_KIB = {160: (105772, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 
