@@ -34,25 +34,25 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "bccb734c87391127dbfa398827070aa91f80bac2bff2af0440181852b6aecab2"
+TRAFFIC_SRC_SHA256 = "a15d1ae41abef152432eba1433e9a1bc9e7c3d750c2d802ff1f3d9394aad0ad1"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 8, 20, 16, 0, 0): (33371, 32001), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96301, 32000),
-    (160, 10, 16, 8, 0, 0): (33414, 32000), (160, 10, 16, 8, 0, 1): (64176, 32054), (160, 10, 16, 8, 0, 2): (96300, 32111),
-    (160, 10, 16, 16, 0, 0): (34372, 32000), (160, 10, 16, 16, 0, 1): (64157, 32000), (160, 10, 16, 16, 0, 2): (96277, 32000),
-    (160, 10, 16, 32, 0, 0): (34680, 32000), (160, 10, 16, 32, 0, 1): (64166, 32000), (160, 10, 16, 32, 0, 2): (96294, 32000),
-    (160, 16, 10, 16, 0, 0): (33545, 32000), (160, 16, 10, 16, 0, 1): (64187, 32000), (160, 16, 10, 16, 0, 2): (96319, 32000),
-    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96329, 32000),
-    (288, 12, 24, 8, 0, 0): (190110, 186626), (288, 12, 24, 8, 0, 1): (373932, 190745), (288, 12, 24, 8, 0, 2): (561497, 190025),
-    (288, 12, 24, 8, 4, 0): (190641, 186625), (288, 12, 24, 8, 4, 1): (373687, 190239), (288, 12, 24, 8, 4, 2): (561646, 189929),
-    (288, 12, 24, 16, 0, 0): (188159, 186624), (288, 12, 24, 16, 0, 1): (373487, 186624), (288, 12, 24, 16, 0, 2): (560585, 186624),
-    (288, 16, 18, 16, 0, 0): (187490, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560729, 186624),
-    (288, 16, 18, 32, 0, 0): (188623, 186640), (288, 16, 18, 32, 0, 1): (373555, 186624), (288, 16, 18, 32, 0, 2): (561010, 186624),
-    (288, 18, 16, 16, 0, 0): (187471, 186624), (288, 18, 16, 16, 0, 1): (373478, 186624), (288, 18, 16, 16, 0, 2): (560495, 186624),
-    (288, 24, 12, 8, 0, 0): (187452, 186624), (288, 24, 12, 8, 0, 1): (373523, 190359), (288, 24, 12, 8, 0, 2): (560450, 186683),
-    (288, 24, 12, 16, 0, 0): (187345, 186626), (288, 24, 12, 16, 0, 1): (373479, 186624), (288, 24, 12, 16, 0, 2): (560621, 186624),
+    (160, 8, 20, 16, 0, 0): (33299, 32000), (160, 8, 20, 16, 0, 1): (64166, 32000), (160, 8, 20, 16, 0, 2): (96298, 32000),
+    (160, 10, 16, 8, 0, 0): (33300, 32000), (160, 10, 16, 8, 0, 1): (64211, 32059), (160, 10, 16, 8, 0, 2): (96296, 32109),
+    (160, 10, 16, 16, 0, 0): (34500, 32000), (160, 10, 16, 16, 0, 1): (64166, 32000), (160, 10, 16, 16, 0, 2): (96294, 32000),
+    (160, 10, 16, 32, 0, 0): (34344, 32000), (160, 10, 16, 32, 0, 1): (64166, 32000), (160, 10, 16, 32, 0, 2): (96291, 32000),
+    (160, 16, 10, 16, 0, 0): (33613, 32000), (160, 16, 10, 16, 0, 1): (64173, 32000), (160, 16, 10, 16, 0, 2): (96336, 32000),
+    (160, 20, 8, 16, 0, 0): (32655, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96330, 32000),
+    (288, 12, 24, 8, 0, 0): (190343, 186626), (288, 12, 24, 8, 0, 1): (373851, 190508), (288, 12, 24, 8, 0, 2): (561315, 189901),
+    (288, 12, 24, 8, 4, 0): (190886, 186624), (288, 12, 24, 8, 4, 1): (373673, 190031), (288, 12, 24, 8, 4, 2): (561392, 189846),
+    (288, 12, 24, 16, 0, 0): (188494, 186624), (288, 12, 24, 16, 0, 1): (373482, 186624), (288, 12, 24, 16, 0, 2): (560597, 186624),
+    (288, 16, 18, 16, 0, 0): (187606, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560774, 186624),
+    (288, 16, 18, 32, 0, 0): (188943, 186650), (288, 16, 18, 32, 0, 1): (373558, 186624), (288, 16, 18, 32, 0, 2): (561032, 186624),
+    (288, 18, 16, 16, 0, 0): (187608, 186624), (288, 18, 16, 16, 0, 1): (373467, 186624), (288, 18, 16, 16, 0, 2): (560533, 186624),
+    (288, 24, 12, 8, 0, 0): (187562, 186624), (288, 24, 12, 8, 0, 1): (373518, 190383), (288, 24, 12, 8, 0, 2): (560468, 186683),
+    (288, 24, 12, 16, 0, 0): (187359, 186626), (288, 24, 12, 16, 0, 1): (373477, 186624), (288, 24, 12, 16, 0, 2): (560621, 186624),
 }
-KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass.hip", "paper_2403_04053_amd/csrc/dft.hpp",
-                  "paper_2403_04053_amd/csrc/internal.hpp")
+KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053_amd/csrc/pass_variants.hpp",
+                  "paper_2403_04053_amd/csrc/dft.hpp", "paper_2403_04053_amd/csrc/internal.hpp")
 
 
 # The shell DFT of the spherical surface (r = 5, 64 x 128 nodes) on the same

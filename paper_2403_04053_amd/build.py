@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpstd.so")
 # longest compile first, so the parallel jobs finish together
-SOURCES = ["pass.hip", "project.hip", "api.hip", "batch.hip", "adjoint.hip", "sphere.hip", "fdtd.hip", "pulse.hip"]
+SOURCES = ["pass_inst0.hip", "pass_inst1.hip", "pass_inst2.hip", "pass_inst3.hip", "pass_inst4.hip", "pass_inst5.hip",
+           "project.hip", "api.hip", "batch.hip", "adjoint.hip", "sphere.hip", "fdtd.hip", "pulse.hip", "pass.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
