@@ -41,6 +41,7 @@ struct pstd_batch {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     std::vector<int> gen;  // table generation of each instance when the groups were built
+    int nt = 0;            // the instances' fields together outgrow the Infinity Cache
     std::string err;
 };
 
@@ -84,7 +85,13 @@ pstd_status build_groups(pstd_batch* b) {
     drop_graph(b);  // the graph holds the old descriptor buffers
     free_groups(b);
     b->gen.resize(b->inst.size());
-    for (size_t i = 0; i < b->inst.size(); ++i) b->gen[i] = b->inst[i]->tab_gen;
+    double field_bytes = 0;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        b->gen[i] = b->inst[i]->tab_gen;
+        const pstd_problem& p = b->inst[i]->prob;
+        field_bytes += 24.0 * p.n[0] * p.n[1] * p.n[2];
+    }
+    b->nt = field_bytes > pstd::kInfinityCacheBytes ? 1 : 0;
     for (int axis = 0; axis < 3; ++axis) {
         std::vector<Group>& gs = b->groups[axis];
         for (int i = 0; i < (int)b->inst.size(); ++i) {
@@ -126,7 +133,7 @@ pstd_status launch_batch_steps(pstd_batch* b, hipStream_t stream, int count) {
         for (int axis = 0; axis < 3; ++axis)
             for (const Group& g : b->groups[axis]) {
                 hipError_t e = pstd::launch_variant(g.variant, g.seg, axis, g.d_desc, g.d_off, (int)g.members.size(),
-                                                    g.tiles, k, g.potx, stream);
+                                                    g.tiles, k, g.potx, b->nt, stream);
                 if (e != hipSuccess) return bhip(b, e, "batch pass launch");
             }
     hipError_t e = pstd::launch_advance(b->ctr, (int)b->inst.size(), count, stream);

@@ -41,6 +41,8 @@ struct PassArgs {
     PotentialArgs pot;
     int potx;                  // 1: the x pass takes the potential term (V's box covers few rows,
                                // no absorber real part, x unsegmented), else the z pass
+    int nt;                    // 1: the fields outgrow the Infinity Cache; the z pass reads its
+                               // last-use operands (psi^n, L, psi^{n-1}) with non-temporal loads
     int nx, ny, nz;
     AxisTables ax[3];
     const int64_t* ctr;        // device counters: ctr[0] = step n, ctr[1] = end (n >= end: no work)
@@ -109,9 +111,12 @@ int variant_tiles(int v, int axis, PassArgs& args);
 // memory, off[0..ninst] (device) = prefix sums of their tiles.  The launch
 // works on step ctr[0] + koff of each instance.
 // The group's members all take the potential term where `potx` says (their
-// PassArgs::potx).
+// PassArgs::potx); nt selects the z pass's non-temporal loads (PassArgs::nt).
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, int koff, int potx, hipStream_t stream);
+                          int total_tiles, int koff, int potx, int nt, hipStream_t stream);
+// Bytes of the memory-side Infinity Cache of one MI355X; fields larger than
+// this run their z passes with non-temporal loads.
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 // Launch variant v for one instance described by `args` (passed by value)
 hipError_t launch_variant_single(int v, bool segmented, int axis, const PassArgs& args, int koff, hipStream_t stream);
 // Adjoint step pass (plain pencils, one instance)

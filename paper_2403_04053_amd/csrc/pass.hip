@@ -55,12 +55,13 @@ int variant_tiles(int v, int axis, PassArgs& a) {
 }
 
 hipError_t launch_variant(int v, bool segmented, int axis, const PassArgs* descs, const int* off, int ninst,
-                          int total_tiles, int koff, int potx, hipStream_t stream) {
+                          int total_tiles, int koff, int potx, int nt, hipStream_t stream) {
     if (v < 0 || v >= kNumVariants || ninst < 1) return hipErrorInvalidValue;
     LaunchFn f = segmented ? kVariants[v].seg : kVariants[v].plain;
     if (!f) return hipErrorInvalidValue;
     PassArgs none{};
-    none.potx = potx;   // only this field of the by-value argument is read in a group launch
+    none.potx = potx;   // only these fields of the by-value argument are read in a group launch
+    none.nt = nt;
     return f(axis, none, descs, off, ninst, total_tiles, koff, stream);
 }
 

@@ -71,6 +71,20 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 template <class T>
 __device__ __forceinline__ GMEM T* gmem(T* p) { return (GMEM T*)p; }
 
+// a value's last use in this step, read with a non-temporal load when NTL:
+// fields beyond the Infinity Cache then leave it to the lines the next pass
+// reads (within the cache the hint costs time, so it is a launch choice: NTL)
+typedef float float2_vec __attribute__((ext_vector_type(2)));
+template <bool NTL>
+__device__ __forceinline__ float2 load_last(GMEM const float2* p) {
+    if constexpr (NTL) {
+        const float2_vec v = __builtin_nontemporal_load((GMEM const float2_vec*)p);
+        return make_float2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
 using PtrF2 = float2*;
 using CPtrF2 = const float2*;
 
@@ -217,7 +231,7 @@ __device__ __forceinline__ TileGeo tile_geo(const Fields& f, int tile, int pA, b
 }
 
 // raw pencil values of one tile (zero outside the grid and for idle lanes)
-template <int N, int N1, int N2, bool SEG>
+template <int N, int N1, int N2, bool SEG, bool NTL = false>
 __device__ __forceinline__ void load_tile(GMEM const float2* __restrict__ psi, const TileGeo& g, int n2,
                                           float2 (&x)[N1]) {
     unroll<N1>([&](auto i) {
@@ -225,14 +239,15 @@ __device__ __forceinline__ void load_tile(GMEM const float2* __restrict__ psi, c
         const int e = n2 + N2 * n1;
         const bool in = g.valid && (e < N) && (!SEG || (g.g0 + e >= 0 && g.g0 + e < g.Ng));
         float2 val = make_float2(0.f, 0.f);
-        if (in) val = psi[g.base + (int64_t)e * g.estride];
+        if (in) val = load_last<NTL>(psi + g.base + (int64_t)e * g.estride);
         x[n1] = val;
     });
 }
 
 // One workgroup per tile of P pencils; MULTI launches find their instance
 // from the prefix table of tiles.
-template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
+template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false,
+          bool NTL = false>
 __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs single,
                                                                        const PassArgs* __restrict__ descs,
                                                                        const int* __restrict__ off, int ninst,
@@ -267,7 +282,9 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     int tile;
     if constexpr (!MULTI) {
         f = fields<AXIS>(single);
-        tile = gt;
+        // the y pass walks the planes from the last to the first, so that it
+        // starts on the lines the x pass wrote last, still in the caches
+        tile = AXIS == 1 ? G - 1 - gt : gt;
     } else {
         int inst = 0;
         for (int i = 1; i < ninst; ++i)
@@ -303,7 +320,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     {
         const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
         float2 raw[N1];
-        load_tile<N, N1, N2, SEG>(psi, geo, n2, raw);
+        load_tile<N, N1, N2, SEG, NTL && AXIS == 2>(psi, geo, n2, raw);
         // the y pass's epilogue operand (L from the x pass), issued with the
         // field loads so that its latency hides behind the transforms; the
         // same elements the epilogue writes, read by the thread that writes them
@@ -598,8 +615,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                     if (e < N && (!SEG || (e >= H && e < H + C))) {
                         const int z = geo.g0 + e;
                         const int64_t ad = geo.base + (int64_t)e * geo.estride;
-                        const float2 Lt = cadd(Lbuf[ad], v[n1]);
-                        const float2 po = psi_old[ad];
+                        const float2 Lt = cadd(load_last<NTL>(Lbuf + ad), v[n1]);
+                        const float2 po = load_last<NTL>(psi_old + ad);
                         float2 q = Lt;
                         if constexpr (!POTX) q = cadd(q, cscale(raw[n1], vv[n1]));
                         if constexpr (!ADJ) {
@@ -676,14 +693,26 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
 using LaunchFn = hipError_t (*)(int axis, const PassArgs& single, const PassArgs* descs, const int* off, int ninst,
                                 int tiles, int koff, hipStream_t stream);
 
-template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false>
+template <int N, int N1, int N2, int M1, int P, int AXIS, bool SEG, bool MULTI, bool ADJ, bool POTX = false,
+          bool NTL = false>
 hipError_t launch_kernel(const PassArgs& single, const PassArgs* descs, const int* off, int ninst, int tiles,
                          int koff, hipStream_t stream) {
     constexpr int threads = P * (N1 > N2 ? N1 : N2);
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((pass_kernel<N, N1, N2, M1, P, AXIS, SEG, MULTI, ADJ, POTX>), dim3(tiles), dim3(threads), 0, stream,
-                       single, descs, off, ninst, koff);
+    hipLaunchKernelGGL((pass_kernel<N, N1, N2, M1, P, AXIS, SEG, MULTI, ADJ, POTX, NTL>), dim3(tiles), dim3(threads), 0,
+                       stream, single, descs, off, ninst, koff);
     return hipGetLastError();
+}
+
+// the z pass, with or without non-temporal loads of its last-use operands
+template <int N, int N1, int N2, int M1, int P, bool SEG, bool MULTI, bool POTX>
+hipError_t launch_z(const PassArgs& single, const PassArgs* descs, const int* off, int ninst, int tiles, int koff,
+                    hipStream_t stream) {
+    if (single.nt)
+        return launch_kernel<N, N1, N2, M1, P, 2, SEG, MULTI, false, POTX, true>(single, descs, off, ninst, tiles, koff,
+                                                                                  stream);
+    return launch_kernel<N, N1, N2, M1, P, 2, SEG, MULTI, false, POTX, false>(single, descs, off, ninst, tiles, koff,
+                                                                               stream);
 }
 
 template <int N, int N1, int N2, int M1, int P, bool SEG>
@@ -693,19 +722,19 @@ static hipError_t launch_shape(int axis, const PassArgs& single, const PassArgs*
         // unsegmented axes may take the potential in the x pass
         if (!SEG && single.potx) {
             if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
-            if (axis == 2) return launch_kernel<N, N1, N2, M1, P, 2, false, false, false, true>(single, descs, off, 0, tiles, koff, stream);
+            if (axis == 2) return launch_z<N, N1, N2, M1, P, false, false, true>(single, descs, off, 0, tiles, koff, stream);
         }
         if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
         if (axis == 1) return launch_kernel<N, N1, N2, M1, P, 1, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
-        return launch_kernel<N, N1, N2, M1, P, 2, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
+        return launch_z<N, N1, N2, M1, P, SEG, false, false>(single, descs, off, 0, tiles, koff, stream);
     }
     if (!SEG && single.potx) {
         if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
-        if (axis == 2) return launch_kernel<N, N1, N2, M1, P, 2, false, true, false, true>(single, descs, off, ninst, tiles, koff, stream);
+        if (axis == 2) return launch_z<N, N1, N2, M1, P, false, true, true>(single, descs, off, ninst, tiles, koff, stream);
     }
     if (axis == 0) return launch_kernel<N, N1, N2, M1, P, 0, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
     if (axis == 1) return launch_kernel<N, N1, N2, M1, P, 1, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
-    return launch_kernel<N, N1, N2, M1, P, 2, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
+    return launch_z<N, N1, N2, M1, P, SEG, true, false>(single, descs, off, ninst, tiles, koff, stream);
 }
 
 template <int N, int N1, int N2, int M1, int P>

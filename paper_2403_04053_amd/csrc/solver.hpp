@@ -36,6 +36,7 @@ struct pstd_solver {
     pstd::PotentialArgs pot{};
     float* v2full = nullptr;     // FDTD scheme only: 2 dtau (V / E0 + sum_a w_a) on every cell
     int potx = 0;                // the x pass takes the potential term (see solver_create)
+    int nt = 0;                  // non-temporal loads in the z pass (see solver_create)
     void* tables = nullptr;
     pstd::AxisTables ax[3]{};
     const float* wloc[3] = {nullptr, nullptr, nullptr};
