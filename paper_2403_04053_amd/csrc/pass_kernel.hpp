@@ -273,8 +273,12 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     // each XCD a contiguous run of tiles instead, so that neighbouring tiles,
     // which share cache lines (the 4-byte potential of a 16-pencil tile is
     // half a 128-byte line), meet in the same L2.  A bijection of [0, G).
+    // The y pass walks each XCD's run backwards: the x pass gave that XCD the
+    // same planes and ended on the lines it wrote last, which are still in
+    // its L2 and in the Infinity Cache.
     const int G = (int)gridDim.x, gb = (int)blockIdx.x, xcd = gb & 7;
-    const int gt = xcd * (G >> 3) + min(xcd, G & 7) + (gb >> 3);
+    const int run0 = xcd * (G >> 3) + min(xcd, G & 7), runlen = (G >> 3) + (xcd < (G & 7) ? 1 : 0);
+    const int gt = run0 + (AXIS == 1 && !MULTI ? runlen - 1 - (gb >> 3) : (gb >> 3));
 
     // instance of this workgroup (uniform), its tile, its step: the base
     // counter plus this launch's offset in its group of steps
@@ -282,9 +286,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
     int tile;
     if constexpr (!MULTI) {
         f = fields<AXIS>(single);
-        // the y pass walks the planes from the last to the first, so that it
-        // starts on the lines the x pass wrote last, still in the caches
-        tile = AXIS == 1 ? G - 1 - gt : gt;
+        tile = gt;
     } else {
         int inst = 0;
         for (int i = 1; i < ninst; ++i)
