@@ -34,22 +34,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "a15d1ae41abef152432eba1433e9a1bc9e7c3d750c2d802ff1f3d9394aad0ad1"
+TRAFFIC_SRC_SHA256 = "d8980280358e292a956a19af604098795307e534333d035ce8c7fc83d6f1ebb7"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 8, 20, 16, 0, 0): (33299, 32000), (160, 8, 20, 16, 0, 1): (64166, 32000), (160, 8, 20, 16, 0, 2): (96298, 32000),
-    (160, 10, 16, 8, 0, 0): (33300, 32000), (160, 10, 16, 8, 0, 1): (64211, 32059), (160, 10, 16, 8, 0, 2): (96296, 32109),
-    (160, 10, 16, 16, 0, 0): (34500, 32000), (160, 10, 16, 16, 0, 1): (64166, 32000), (160, 10, 16, 16, 0, 2): (96294, 32000),
-    (160, 10, 16, 32, 0, 0): (34344, 32000), (160, 10, 16, 32, 0, 1): (64166, 32000), (160, 10, 16, 32, 0, 2): (96291, 32000),
-    (160, 16, 10, 16, 0, 0): (33613, 32000), (160, 16, 10, 16, 0, 1): (64173, 32000), (160, 16, 10, 16, 0, 2): (96336, 32000),
-    (160, 20, 8, 16, 0, 0): (32655, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96330, 32000),
-    (288, 12, 24, 8, 0, 0): (190343, 186626), (288, 12, 24, 8, 0, 1): (373851, 190508), (288, 12, 24, 8, 0, 2): (561315, 189901),
-    (288, 12, 24, 8, 4, 0): (190886, 186624), (288, 12, 24, 8, 4, 1): (373673, 190031), (288, 12, 24, 8, 4, 2): (561392, 189846),
-    (288, 12, 24, 16, 0, 0): (188494, 186624), (288, 12, 24, 16, 0, 1): (373482, 186624), (288, 12, 24, 16, 0, 2): (560597, 186624),
-    (288, 16, 18, 16, 0, 0): (187606, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560774, 186624),
-    (288, 16, 18, 32, 0, 0): (188943, 186650), (288, 16, 18, 32, 0, 1): (373558, 186624), (288, 16, 18, 32, 0, 2): (561032, 186624),
-    (288, 18, 16, 16, 0, 0): (187608, 186624), (288, 18, 16, 16, 0, 1): (373467, 186624), (288, 18, 16, 16, 0, 2): (560533, 186624),
-    (288, 24, 12, 8, 0, 0): (187562, 186624), (288, 24, 12, 8, 0, 1): (373518, 190383), (288, 24, 12, 8, 0, 2): (560468, 186683),
-    (288, 24, 12, 16, 0, 0): (187359, 186626), (288, 24, 12, 16, 0, 1): (373477, 186624), (288, 24, 12, 16, 0, 2): (560621, 186624),
+    (160, 8, 20, 16, 0, 0): (33400, 32000), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96286, 32000),
+    (160, 10, 16, 8, 0, 0): (33377, 32000), (160, 10, 16, 8, 0, 1): (64172, 32059), (160, 10, 16, 8, 0, 2): (96299, 32086),
+    (160, 10, 16, 16, 0, 0): (34399, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96280, 32000),
+    (160, 10, 16, 32, 0, 0): (34381, 32000), (160, 10, 16, 32, 0, 1): (64153, 32000), (160, 10, 16, 32, 0, 2): (96278, 32000),
+    (160, 16, 10, 16, 0, 0): (33648, 32000), (160, 16, 10, 16, 0, 1): (64184, 32000), (160, 16, 10, 16, 0, 2): (96324, 32000),
+    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64193, 32000), (160, 20, 8, 16, 0, 2): (96329, 32000),
+    (288, 12, 24, 8, 0, 0): (190106, 186625), (288, 12, 24, 8, 0, 1): (373922, 190714), (288, 12, 24, 8, 0, 2): (769576, 188429),
+    (288, 12, 24, 8, 4, 0): (190749, 186624), (288, 12, 24, 8, 4, 1): (373755, 190219), (288, 12, 24, 8, 4, 2): (767935, 188450),
+    (288, 12, 24, 16, 0, 0): (188175, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560242, 186624),
+    (288, 16, 18, 16, 0, 0): (187492, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560268, 186624),
+    (288, 16, 18, 32, 0, 0): (188584, 186642), (288, 16, 18, 32, 0, 1): (373581, 186624), (288, 16, 18, 32, 0, 2): (560286, 186624),
+    (288, 18, 16, 16, 0, 0): (187471, 186624), (288, 18, 16, 16, 0, 1): (373477, 186624), (288, 18, 16, 16, 0, 2): (560261, 186624),
+    (288, 24, 12, 8, 0, 0): (187437, 186624), (288, 24, 12, 8, 0, 1): (373523, 190172), (288, 24, 12, 8, 0, 2): (643008, 186636),
+    (288, 24, 12, 16, 0, 0): (187340, 186626), (288, 24, 12, 16, 0, 1): (373482, 186624), (288, 24, 12, 16, 0, 2): (560297, 186624),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053_amd/csrc/pass_variants.hpp",
                   "paper_2403_04053_amd/csrc/dft.hpp", "paper_2403_04053_amd/csrc/internal.hpp")
@@ -64,8 +64,8 @@ SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "80e90e9187d093ca4bddfda5ab98ca2d1a8cc6a4cfd3a4872e9b73debf51310c"
-FDTD_TRAFFIC_KIB = {160: (105772, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "7a56c7611e63e84e3f650aa3a0a8e09238759a64e490b64c31588ced84f30e38"
+FDTD_TRAFFIC_KIB = {160: (105708, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 
