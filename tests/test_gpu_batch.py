@@ -153,3 +153,29 @@ def test_uneven_batch_full_size_sampled(P):
         err = np.abs(g - ref).max() / np.abs(cur).max()
         print("batch instance", i, prob.n, "sampled err", err)
         assert err < 1e-5
+
+
+def test_non_temporal_z_pass_changes_no_bits(P):
+    """A batch whose largest instance outgrows the Infinity Cache runs every
+    z pass with non-temporal loads (a cache hint only); its small instance
+    must equal the same problem solved alone, which runs without the hint,
+    bit for bit, and its large instance the large problem solved alone."""
+    big, Vb = synth.square_barrier_160(n_fft=256)
+    big = big.replace(n_steps=12, dft_begin=4, dft_end=12)
+    small, Vs = synth.tiny(n=(24, 20, 32), P=3, transition=2, v0=0.5, radius_cells=3, steps=12, dft=(4, 12))
+    Vb, Vs = Vb.astype(np.float32), Vs.astype(np.float32)
+    batch = P.Batch([big, small])
+    batch.set_potential(0, Vb)
+    batch.set_potential(1, Vs)
+    batch.run([12, 12])
+    for i, (prob, V) in enumerate(((big, Vb), (small, Vs))):
+        alone = P.Solver(prob)
+        alone.set_potential(V)
+        alone.run(12)
+        view = batch.instance(i)
+        print(f"instance {prob.n}: batch vs alone", flush=True)
+        assert np.array_equal(view.psi(0).cpu().numpy(), alone.psi(0).cpu().numpy()), i
+        assert np.array_equal(view.psi(1).cpu().numpy(), alone.psi(1).cpu().numpy()), i
+        assert np.array_equal(view.phasors().cpu().numpy(), alone.phasors().cpu().numpy()), i
+        alone.close()
+    batch.close()
