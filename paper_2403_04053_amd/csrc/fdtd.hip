@@ -39,8 +39,14 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+typedef float float2_vec __attribute__((ext_vector_type(2)));
+
 // Five waves per SIMD: the prefetched plane needs about 96 VGPRs, and the
-// register cap of six or more waves serialises its loads or spills.
+// register cap of six or more waves serialises its loads or spills.  NTL:
+// psi^{n-1}, read here for the last time, comes in with non-temporal loads
+// (chosen for fields beyond the Infinity Cache, which then keeps the
+// psi^{n+1} this step writes for the next).
+template <bool NTL>
 __global__ __launch_bounds__(kFX * kFY) __attribute__((amdgpu_waves_per_eu(5))) void fdtd_kernel(FdtdArgs a, int koff) {
     __shared__ float2 s[kSY][kSX + 1];
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -106,7 +112,12 @@ __global__ __launch_bounds__(kFX * kFY) __attribute__((amdgpu_waves_per_eu(5))) 
         });
         if (valid) {
             const int64_t ad = x + (int64_t)nx * y + plane * z;
-            po_n = old[ad];
+            if constexpr (NTL) {
+                const float2_vec v = __builtin_nontemporal_load((const float2_vec*)(old + ad));
+                po_n = make_float2(v.x, v.y);
+            } else {
+                po_n = old[ad];
+            }
             vv_n = a.v2[ad];
         }
     };
@@ -155,7 +166,12 @@ const double kFdtdAlpha[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0,
 
 hipError_t launch_fdtd(const FdtdArgs& a, int koff, hipStream_t stream) {
     const int tiles = ((a.nx + kFX - 1) / kFX) * ((a.ny + kFY - 1) / kFY) * ((a.nz + kFZ - 1) / kFZ);
-    hipLaunchKernelGGL(fdtd_kernel, dim3((unsigned)tiles), dim3(kFX, kFY), 0, stream, a, koff);
+    // psi pair and V: 20 B per cell
+    const bool ntl = 20.0 * (double)a.nx * a.ny * a.nz > kInfinityCacheBytes;
+    if (ntl)
+        hipLaunchKernelGGL(fdtd_kernel<true>, dim3((unsigned)tiles), dim3(kFX, kFY), 0, stream, a, koff);
+    else
+        hipLaunchKernelGGL(fdtd_kernel<false>, dim3((unsigned)tiles), dim3(kFX, kFY), 0, stream, a, koff);
     return hipGetLastError();
 }
 
