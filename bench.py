@@ -64,8 +64,8 @@ SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "7a56c7611e63e84e3f650aa3a0a8e09238759a64e490b64c31588ced84f30e38"
-FDTD_TRAFFIC_KIB = {160: (105708, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "50d9d8527c848b4a26a55a77004f61c05a952424927c6716e8ebe7941d2b111d"
+FDTD_TRAFFIC_KIB = {160: (105820, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 
