@@ -35,6 +35,14 @@
 // compensation, the DFT of psi and of its spectral normal derivative on the
 // two planes normal to its axis (Eqs. psiphasor, dpsiphasor).
 //
+// Order and caches: workgroups are mapped to tiles so that each of the 8
+// XCDs walks a contiguous run of tiles; the x and y passes both number their
+// tiles plane by plane, so an XCD meets the same planes in both, and the y
+// pass walks its run backwards, starting on the lines its x pass wrote last.
+// For fields beyond the Infinity Cache the z pass reads its last-use
+// operands with non-temporal loads (NTL), leaving the cache to the
+// psi^{n+1} it writes for the next step's x pass.
+//
 // Segmented mode (overlapping subdomains, Section 2.6): a pencil is split
 // into segments of C core points; each segment is transformed as a local
 // array of N = C + 2H points read from the global array with the halo
@@ -323,22 +331,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
         float2 raw[N1];
         load_tile<N, N1, N2, SEG, NTL && AXIS == 2>(psi, geo, n2, raw);
-        // the y pass's epilogue operand (L from the x pass), issued with the
-        // field loads so that its latency hides behind the transforms; the
-        // same elements the epilogue writes, read by the thread that writes them
         float2 Lin[N1];
-        if constexpr (AXIS == 1) {
-            const int C = SEG ? f.seg_core : N;
-            const int H = SEG ? f.seg_halo : 0;
-            unroll<N1>([&](auto i) {
-                constexpr int n1 = decltype(i)::value;
-                const int e = n2 + N2 * n1;
-                Lin[n1] = make_float2(0.f, 0.f);
-                if (geo.valid && e < N && (!SEG || (e >= H && e < H + C)))
-                    Lin[n1] = f.L[geo.base + (int64_t)e * geo.estride];
-            });
-        }
-
         GMEM const float* __restrict__ wloc = f.wloc;
         const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
         float2 v[N1];
@@ -385,6 +378,24 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         // in stage A (which skip the reload below) do not keep them alive
         // through stage B
         unroll<N1>([&](auto i) { v[decltype(i)::value] = make_float2(0.f, 0.f); });
+        // the y pass's epilogue operand (L from the x pass), issued once stage
+        // A is done: the field loads then have the memory system to
+        // themselves, and L's latency still hides behind stage B and the
+        // inverse stage A (issued with the field loads it cost 2-7 %); the
+        // same elements the epilogue writes, read by the thread that writes
+        // them
+        if constexpr (AXIS == 1) {
+            const int C = SEG ? f.seg_core : N;
+            const int H = SEG ? f.seg_halo : 0;
+            unroll<N1>([&](auto i) {
+                constexpr int n1 = decltype(i)::value;
+                const int e = n2 + N2 * n1;
+                Lin[n1] = make_float2(0.f, 0.f);
+                if (geo.valid && e < N && (!SEG || (e >= H && e < H + C)))
+                    Lin[n1] = f.L[geo.base + (int64_t)e * geo.estride];
+            });
+        }
+
         __syncthreads();
 
         // ---- stage B: N2-point DFT, kbar^2, inverse N2-point DFT ----
