@@ -34,22 +34,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "d8980280358e292a956a19af604098795307e534333d035ce8c7fc83d6f1ebb7"
+TRAFFIC_SRC_SHA256 = "779a9c0f0bded3e2a6560644bd81fc12f4d9d4989141155e7443c824a6bc7f36"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 8, 20, 16, 0, 0): (33400, 32000), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96286, 32000),
-    (160, 10, 16, 8, 0, 0): (33377, 32000), (160, 10, 16, 8, 0, 1): (64172, 32059), (160, 10, 16, 8, 0, 2): (96299, 32086),
-    (160, 10, 16, 16, 0, 0): (34399, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96280, 32000),
-    (160, 10, 16, 32, 0, 0): (34381, 32000), (160, 10, 16, 32, 0, 1): (64153, 32000), (160, 10, 16, 32, 0, 2): (96278, 32000),
-    (160, 16, 10, 16, 0, 0): (33648, 32000), (160, 16, 10, 16, 0, 1): (64184, 32000), (160, 16, 10, 16, 0, 2): (96324, 32000),
-    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64193, 32000), (160, 20, 8, 16, 0, 2): (96329, 32000),
-    (288, 12, 24, 8, 0, 0): (190106, 186625), (288, 12, 24, 8, 0, 1): (373922, 190714), (288, 12, 24, 8, 0, 2): (769576, 188429),
-    (288, 12, 24, 8, 4, 0): (190749, 186624), (288, 12, 24, 8, 4, 1): (373755, 190219), (288, 12, 24, 8, 4, 2): (767935, 188450),
-    (288, 12, 24, 16, 0, 0): (188175, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560242, 186624),
-    (288, 16, 18, 16, 0, 0): (187492, 186624), (288, 16, 18, 16, 0, 1): (373493, 186624), (288, 16, 18, 16, 0, 2): (560268, 186624),
-    (288, 16, 18, 32, 0, 0): (188584, 186642), (288, 16, 18, 32, 0, 1): (373581, 186624), (288, 16, 18, 32, 0, 2): (560286, 186624),
-    (288, 18, 16, 16, 0, 0): (187471, 186624), (288, 18, 16, 16, 0, 1): (373477, 186624), (288, 18, 16, 16, 0, 2): (560261, 186624),
-    (288, 24, 12, 8, 0, 0): (187437, 186624), (288, 24, 12, 8, 0, 1): (373523, 190172), (288, 24, 12, 8, 0, 2): (643008, 186636),
-    (288, 24, 12, 16, 0, 0): (187340, 186626), (288, 24, 12, 16, 0, 1): (373482, 186624), (288, 24, 12, 16, 0, 2): (560297, 186624),
+    (160, 8, 20, 16, 0, 0): (33266, 32001), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96285, 32000),
+    (160, 10, 16, 8, 0, 0): (33389, 32000), (160, 10, 16, 8, 0, 1): (64174, 32099), (160, 10, 16, 8, 0, 2): (96302, 32078),
+    (160, 10, 16, 16, 0, 0): (34407, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96277, 32000),
+    (160, 10, 16, 32, 0, 0): (34845, 32000), (160, 10, 16, 32, 0, 1): (64168, 32000), (160, 10, 16, 32, 0, 2): (96293, 32000),
+    (160, 16, 10, 16, 0, 0): (33500, 32000), (160, 16, 10, 16, 0, 1): (64186, 32000), (160, 16, 10, 16, 0, 2): (96320, 32000),
+    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64193, 32000), (160, 20, 8, 16, 0, 2): (96330, 32000),
+    (288, 12, 24, 8, 0, 0): (190121, 186625), (288, 12, 24, 8, 0, 1): (373549, 192555), (288, 12, 24, 8, 0, 2): (768964, 188401),
+    (288, 12, 24, 8, 4, 0): (190714, 186624), (288, 12, 24, 8, 4, 1): (374086, 193860), (288, 12, 24, 8, 4, 2): (765849, 188401),
+    (288, 12, 24, 16, 0, 0): (188167, 186624), (288, 12, 24, 16, 0, 1): (373485, 186624), (288, 12, 24, 16, 0, 2): (560240, 186624),
+    (288, 16, 18, 16, 0, 0): (187479, 186624), (288, 16, 18, 16, 0, 1): (373477, 186624), (288, 16, 18, 16, 0, 2): (560266, 186624),
+    (288, 16, 18, 32, 0, 0): (188586, 186642), (288, 16, 18, 32, 0, 1): (373557, 186624), (288, 16, 18, 32, 0, 2): (560283, 186624),
+    (288, 18, 16, 16, 0, 0): (187467, 186624), (288, 18, 16, 16, 0, 1): (373499, 186624), (288, 18, 16, 16, 0, 2): (560259, 186624),
+    (288, 24, 12, 8, 0, 0): (187438, 186624), (288, 24, 12, 8, 0, 1): (373514, 191183), (288, 24, 12, 8, 0, 2): (644172, 186637),
+    (288, 24, 12, 16, 0, 0): (187339, 186626), (288, 24, 12, 16, 0, 1): (373487, 186624), (288, 24, 12, 16, 0, 2): (560295, 186624),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053_amd/csrc/pass_variants.hpp",
                   "paper_2403_04053_amd/csrc/dft.hpp", "paper_2403_04053_amd/csrc/internal.hpp")
