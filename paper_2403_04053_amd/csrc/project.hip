@@ -245,6 +245,7 @@ __global__ __launch_bounds__(64 * kDotWaves) void farfield_dot_kernel(const doub
 // ---------------------------------------------------------------------------
 
 constexpr int kNearThreads = 128;
+constexpr int kNearPoints = 4;  // observation points per thread in near_kernel
 constexpr int kCellChunk = 8;
 
 struct FaceGeo {
@@ -260,22 +261,40 @@ struct FaceGeo {
 // [y * cells_per_split, (y + 1) * cells_per_split), so that few points still
 // fill the chip.  Each row writes its partial sum (times the face prefactor)
 // to part[y * n_obs + point]; add_splits_kernel adds the rows in order.
+// K observation points per thread, kNearThreads apart (coalesced loads and
+// stores): each coefficient read from LDS serves K points, which takes the
+// kernel off the LDS read rate (one 16-byte broadcast per two FP64 FMAs
+// with one point per thread).  Each point's sums run in the same order as
+// with one point per thread.
+template <int K>
 __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __restrict__ obs, int64_t n_obs, double k0,
                                                             FaceGeo g, const double2* __restrict__ Q,
                                                             int64_t cells_per_split, double2* __restrict__ part) {
     __shared__ double2 sq[kCellChunk * 2 * kTerms * kTerms];
-    const int64_t pi = (int64_t)blockIdx.x * kNearThreads + threadIdx.x;
-    const bool live = pi < n_obs;
-    double ra_ = 0, rb_ = 0, rc_ = 0;  // point in the face frame (normal, b, c)
-    if (live) {
-        const double3 o = obs[pi];
-        const double x = o.x * k0, y = o.y * k0, z = o.z * k0;
-        ra_ = g.a == 0 ? x : g.a == 1 ? y : z;
-        rb_ = g.b == 0 ? x : g.b == 1 ? y : z;
-        rc_ = g.c == 0 ? x : g.c == 1 ? y : z;
+    bool live[K];
+    bool any_live = false;
+    double Ra[K], rb_[K], rc_[K];  // point in the face frame (normal, b, c)
+    double2 acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t pi = ((int64_t)blockIdx.x * K + k) * kNearThreads + threadIdx.x;
+        live[k] = pi < n_obs;
+        any_live |= live[k];
+        // an idle slot gets a point one unit off the face, so that its
+        // (discarded) sums stay finite
+        double ra = g.xa + 1.0, rb = 0, rc = 0;
+        if (live[k]) {
+            const double3 o = obs[pi];
+            const double x = o.x * k0, y = o.y * k0, z = o.z * k0;
+            ra = g.a == 0 ? x : g.a == 1 ? y : z;
+            rb = g.b == 0 ? x : g.b == 1 ? y : z;
+            rc = g.c == 0 ? x : g.c == 1 ? y : z;
+        }
+        Ra[k] = ra - g.xa;
+        rb_[k] = rb;
+        rc_[k] = rc;
+        acc[k] = make_double2(0, 0);
     }
-    const double Ra = ra_ - g.xa;
-    double2 acc = make_double2(0, 0);
     const int64_t ncell = (int64_t)g.L * g.M;
     const int64_t c_lo = (int64_t)blockIdx.y * cells_per_split;
     const int64_t c_hi = min<int64_t>(ncell, c_lo + cells_per_split);
@@ -285,46 +304,72 @@ __global__ __launch_bounds__(kNearThreads) void near_kernel(const double3* __res
         __syncthreads();
         for (int e = threadIdx.x; e < nc * per_cell; e += kNearThreads) sq[e] = Q[c0 * per_cell + e];
         __syncthreads();
-        if (!live) continue;
+        if (!any_live) continue;
         for (int ci = 0; ci < nc; ++ci) {
             const int64_t cell = c0 + ci;
             const int m = (int)(cell / g.L), l = (int)(cell % g.L);
-            const double Rb = rb_ - (g.xb0 + l * g.db);
-            const double Rc = rc_ - (g.xc0 + m * g.dc);
-            const double R2 = Ra * Ra + Rb * Rb + Rc * Rc;
-            const double Rn = sqrt(R2);
-            const double inv = 1.0 / Rn;
-            const double ab = g.db * Rb * inv * 0.5, ac = g.dc * Rc * inv * 0.5;
+            double Rn[K], inv[K], ab[K], ac[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double Rb = rb_[k] - (g.xb0 + l * g.db);
+                const double Rc = rc_[k] - (g.xc0 + m * g.dc);
+                const double R2 = Ra[k] * Ra[k] + Rb * Rb + Rc * Rc;
+                Rn[k] = sqrt(R2);
+                inv[k] = 1.0 / Rn[k];
+                ab[k] = g.db * Rb * inv[k] * 0.5;
+                ac[k] = g.dc * Rc * inv[k] * 0.5;
+            }
             const double2* q = &sq[ci * per_cell];
-            double2 S0 = make_double2(0, 0), S1 = S0;
+            double2 S0[K], S1[K];
 #pragma unroll 1
             for (int fld = 0; fld < 2; ++fld) {
-                double2 outer = make_double2(0, 0);
+                double2 outer[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) outer[k] = make_double2(0, 0);
 #pragma unroll 1
                 for (int p = kOrder; p >= 0; --p) {
-                    double2 inner = make_double2(0, 0);
+                    double2 inner[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) inner[k] = make_double2(0, 0);
                     const double2* row = q + (fld * kTerms + p) * kTerms;
 #pragma unroll
                     for (int qq = kOrder; qq >= 0; --qq) {
-                        inner.x = inner.x * ac + row[qq].x;
-                        inner.y = inner.y * ac + row[qq].y;
+                        const double2 cq = row[qq];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            inner[k].x = inner[k].x * ac[k] + cq.x;
+                            inner[k].y = inner[k].y * ac[k] + cq.y;
+                        }
                     }
-                    outer.x = outer.x * ab + inner.x;
-                    outer.y = outer.y * ab + inner.y;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        outer[k].x = outer[k].x * ab[k] + inner[k].x;
+                        outer[k].y = outer[k].y * ab[k] + inner[k].y;
+                    }
                 }
-                if (fld == 0) S0 = outer;
-                else S1 = outer;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (fld == 0) S0[k] = outer[k];
+                    else S1[k] = outer[k];
+                }
             }
             // e^{iR}/R (S_dpsi + (i - 1/R) (R_a/R) S_psi)
-            const double ra = Ra * inv;
-            const double2 coef = make_double2(-inv * ra, ra);
-            const double2 inner = zadd(S1, zmul(coef, S0));
-            double sn, cs;
-            sincos(Rn, &sn, &cs);
-            acc = zadd(acc, zmul(make_double2(cs * inv, sn * inv), inner));
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double ra = Ra[k] * inv[k];
+                const double2 coef = make_double2(-inv[k] * ra, ra);
+                const double2 inner = zadd(S1[k], zmul(coef, S0[k]));
+                double sn, cs;
+                sincos(Rn[k], &sn, &cs);
+                acc[k] = zadd(acc[k], zmul(make_double2(cs * inv[k], sn * inv[k]), inner));
+            }
         }
     }
-    if (live) part[(int64_t)blockIdx.y * n_obs + pi] = make_double2(acc.x * g.pref, acc.y * g.pref);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t pi = ((int64_t)blockIdx.x * K + k) * kNearThreads + threadIdx.x;
+        if (live[k]) part[(int64_t)blockIdx.y * n_obs + pi] = make_double2(acc[k].x * g.pref, acc[k].y * g.pref);
+    }
 }
 
 // out[i] (+)= sum over the split rows k = 0, 1, ... of part[k * n + i], in
@@ -747,12 +792,12 @@ hipError_t project_points(ProjectState** pst, const pstd_problem& p, const doubl
         g.xb0 = (p.surf_lo[b] - Nb / 2 + 0.5) * dxb[b];
         g.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
         g.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
-        const int64_t bx = (n_obs + kNearThreads - 1) / kNearThreads;
+        const int64_t bx = (n_obs + kNearThreads * kNearPoints - 1) / (kNearThreads * kNearPoints);
         const int splits = split_count(bx * (kNearThreads / 64), (ncell + kCellChunk - 1) / kCellChunk);
         const int64_t per = (ncell + splits - 1) / splits;
         TRY(ensure(&s->part, &s->part_bytes, (size_t)splits * n_obs * sizeof(double2)));
-        hipLaunchKernelGGL(near_kernel, dim3((unsigned)bx, (unsigned)splits), dim3(kNearThreads), 0, stream, obs, n_obs,
-                           p.k0, g, dQ, per, s->part);
+        hipLaunchKernelGGL(near_kernel<kNearPoints>, dim3((unsigned)bx, (unsigned)splits), dim3(kNearThreads), 0, stream,
+                           obs, n_obs, p.k0, g, dQ, per, s->part);
         hipLaunchKernelGGL(add_splits_kernel, dim3((unsigned)((n_obs + 255) / 256)), dim3(256), 0, stream, s->part, splits,
                            n_obs, true, out);
         // the next face reuses the scratch after these kernels, in stream order
