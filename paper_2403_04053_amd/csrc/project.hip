@@ -387,25 +387,34 @@ __global__ void add_splits_kernel(const double2* __restrict__ part, int splits, 
 // Qbar[fld][p][q][cell] = sum_o conj(pref e^{iR}/R alpha_b^p alpha_c^q [coef]) g_o,
 // coef = (i - 1/R) R_a / R for the psi field (fld 0), 1 for dpsi (fld 1).
 constexpr int kAdjObsChunk = 256;
+constexpr int kAdjP = 3;  // values of p per thread in near_adjoint_kernel
 
 // Workgroup row blockIdx.y sums the points [y * obs_per_split, (y + 1) *
 // obs_per_split) into its own copy of Qbar (Qbar + y * 2 kTerms^2 ncell);
 // add_splits_kernel adds the copies in order.
+template <int KP>
 __global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __restrict__ obs, const double2* __restrict__ gv,
                                                            int64_t n_obs, double k0, FaceGeo g,
                                                            int64_t obs_per_split, double2* __restrict__ Qbar) {
+    // one thread per (cell, block of KP consecutive p): the distance, the
+    // square root and the sincos of a (cell, point) pair are taken once for
+    // KP values of p; each (field, p, q) sum runs over the points in the same
+    // order as with one p per thread
+    constexpr int kBlocks = (kTerms + KP - 1) / KP;
     __shared__ double3 so[kAdjObsChunk];
     __shared__ double2 sg[kAdjObsChunk];
     const int64_t ncell = (int64_t)g.L * g.M;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = id < ncell * kTerms;
+    const bool live = id < ncell * kBlocks;
     const int64_t cell = live ? id % ncell : 0;
-    const int p = live ? (int)(id / ncell) : 0;
+    const int p0 = live ? (int)(id / ncell) * KP : 0;
     const int m = (int)(cell / g.L), l = (int)(cell % g.L);
     const double yb = g.xb0 + l * g.db, yc = g.xc0 + m * g.dc;
-    double2 acc[2][kTerms];
-    for (int f = 0; f < 2; ++f)
-        for (int q = 0; q < kTerms; ++q) acc[f][q] = make_double2(0, 0);
+    double2 acc[KP][2][kTerms];
+#pragma unroll
+    for (int j = 0; j < KP; ++j)
+        for (int f = 0; f < 2; ++f)
+            for (int q = 0; q < kTerms; ++q) acc[j][f][q] = make_double2(0, 0);
     const int64_t o_lo = (int64_t)blockIdx.y * obs_per_split;
     const int64_t o_hi = min<int64_t>(n_obs, o_lo + obs_per_split);
     for (int64_t o0 = o_lo; o0 < o_hi; o0 += kAdjObsChunk) {
@@ -427,29 +436,40 @@ __global__ __launch_bounds__(128) void near_adjoint_kernel(const double3* __rest
             const double ab = g.db * Rb * inv * 0.5, ac = g.dc * Rc * inv * 0.5;
             double sn, cs;
             sincos(Rn, &sn, &cs);
-            // conj(pref e^{iR}/R alpha_b^p) g
-            double abp = 1.0;
-            for (int t = 0; t < p; ++t) abp *= ab;
-            const double wr = g.pref * inv * abp;
             const double2 gg = sg[e];
-            const double2 base = make_double2(wr * (cs * gg.x + sn * gg.y), wr * (cs * gg.y - sn * gg.x));
-            // conj(coef) = (-i - 1/R) R_a/R
             const double rr = Ra * inv;
-            const double2 cbase = make_double2(-inv * rr * base.x + rr * base.y, -inv * rr * base.y - rr * base.x);
-            double acq = 1.0;
-            for (int q = 0; q < kTerms; ++q) {
-                acc[0][q].x += acq * cbase.x;
-                acc[0][q].y += acq * cbase.y;
-                acc[1][q].x += acq * base.x;
-                acc[1][q].y += acq * base.y;
-                acq *= ac;
+            // alpha_b^p0 by the same product as with one p per thread
+            double abp = 1.0;
+            for (int t = 0; t < p0; ++t) abp *= ab;
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                // conj(pref e^{iR}/R alpha_b^p) g
+                const double wr = g.pref * inv * abp;
+                const double2 base = make_double2(wr * (cs * gg.x + sn * gg.y), wr * (cs * gg.y - sn * gg.x));
+                // conj(coef) = (-i - 1/R) R_a/R
+                const double2 cbase = make_double2(-inv * rr * base.x + rr * base.y, -inv * rr * base.y - rr * base.x);
+                double acq = 1.0;
+#pragma unroll
+                for (int q = 0; q < kTerms; ++q) {
+                    acc[j][0][q].x += acq * cbase.x;
+                    acc[j][0][q].y += acq * cbase.y;
+                    acc[j][1][q].x += acq * base.x;
+                    acc[j][1][q].y += acq * base.y;
+                    acq *= ac;
+                }
+                abp *= ab;
             }
         }
     }
     if (!live) return;
     double2* __restrict__ dst = Qbar + (int64_t)blockIdx.y * 2 * kTerms * kTerms * ncell;
-    for (int f = 0; f < 2; ++f)
-        for (int q = 0; q < kTerms; ++q) dst[(((int64_t)f * kTerms + p) * kTerms + q) * ncell + cell] = acc[f][q];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const int p = p0 + j;
+        if (p >= kTerms) break;
+        for (int f = 0; f < 2; ++f)
+            for (int q = 0; q < kTerms; ++q) dst[(((int64_t)f * kTerms + p) * kTerms + q) * ncell + cell] = acc[j][f][q];
+    }
 }
 
 // out = conj(x) * scale as complex64
@@ -841,7 +861,7 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
         geo.xb0 = (p.surf_lo[b] - Nb / 2 + 0.5) * dxb[b];
         geo.xc0 = (p.surf_lo[c] - Nc / 2 + 0.5) * dxb[c];
         geo.pref = (side == 0 ? 1.0 : -1.0) * dxb[b] * dxb[c] / (4 * kPi * Nb * Nc);
-        const int64_t nthr = ncell * kTerms;
+        const int64_t nthr = ncell * ((kTerms + kAdjP - 1) / kAdjP);
         const int64_t bx = (nthr + 127) / 128;
         const int splits = split_count(bx * 2, std::min<int64_t>((n_obs + kAdjObsChunk - 1) / kAdjObsChunk, 16));
         const int64_t per = (n_obs + splits - 1) / splits;
@@ -851,7 +871,7 @@ hipError_t project_adjoint(ProjectState** pst, const pstd_problem& p, const doub
             TRY(ensure(&s->part, &s->part_bytes, (size_t)splits * nq * sizeof(double2)));
             qdst = s->part;
         }
-        hipLaunchKernelGGL(near_adjoint_kernel, dim3((unsigned)bx, (unsigned)splits), dim3(128), 0, stream, obs, g,
+        hipLaunchKernelGGL(near_adjoint_kernel<kAdjP>, dim3((unsigned)bx, (unsigned)splits), dim3(128), 0, stream, obs, g,
                            n_obs, p.k0, geo, per, qdst);
         if (splits > 1)
             hipLaunchKernelGGL(add_splits_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, stream, s->part,
