@@ -263,11 +263,11 @@ void taper(const pstd_problem& p, int a, double dxb, int i, double* z, double* z
 pstd_status build_tables(pstd_solver* s) {
     const pstd_problem& p = s->prob;
     // per axis: kk[Nl] f, wloc[Nl] f, tw[Nl] f2, dlo[Nl] f2, dhi[Nl] f2 (local length Nl),
-    //           gam[N] f, zt[N] f2, dz[N] f2 (global length N)
+    //           gam[N] f, zt[N] f2, dz[N] f2, zd[N] f4 (global length N)
     size_t bytes = 0;
     for (int a = 0; a < 3; ++a)
         bytes += (size_t)local_len(p, a) * (2 * sizeof(float) + 3 * sizeof(float2)) +
-                 (size_t)p.n[a] * (sizeof(float) + 2 * sizeof(float2)) + 16 * 8;
+                 (size_t)p.n[a] * (sizeof(float) + 2 * sizeof(float2) + sizeof(float4)) + 16 * 9;
     HIP_TRY(s, hipMalloc(&s->tables, bytes));
     char* cur = (char*)s->tables;
     for (int a = 0; a < 3; ++a) {
@@ -353,14 +353,17 @@ pstd_status build_tables(pstd_solver* s) {
         float2* d_tw = place(tw);
         float2* d_zt = place(zt);
         float2* d_dz = place(dz);
+        std::vector<float4> zd(N);
+        for (int i = 0; i < N; ++i) zd[i] = make_float4(zt[i].x, zt[i].y, dz[i].x, dz[i].y);
+        float4* d_zd = place(zd);
         float2* d_dlo = place(dlo);
         float2* d_dhi = place(dhi);
         pstd_status st;
         if ((st = upload(s, d_kk, kk)) || (st = upload(s, d_wl, wl)) || (st = upload(s, d_gam, gam)) ||
             (st = upload(s, d_tw, tw)) || (st = upload(s, d_zt, zt)) || (st = upload(s, d_dz, dz)) ||
-            (st = upload(s, d_dlo, dlo)) || (st = upload(s, d_dhi, dhi)))
+            (st = upload(s, d_zd, zd)) || (st = upload(s, d_dlo, dlo)) || (st = upload(s, d_dhi, dhi)))
             return st;
-        s->ax[a] = pstd::AxisTables{d_kk, d_tw, d_gam, d_zt, d_dz, d_dlo, d_dhi};
+        s->ax[a] = pstd::AxisTables{d_kk, d_tw, d_gam, d_zt, d_dz, d_zd, d_dlo, d_dhi};
         s->wloc[a] = d_wl;
     }
     return PSTD_OK;

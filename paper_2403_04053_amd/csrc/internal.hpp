@@ -15,6 +15,7 @@ struct AxisTables {
     const float* gam;    // exp(-gamma(d) dtau), Eq. Gamma factor
     const float2* zt;    // zeta(i) exp(i khat_a x_a(i))
     const float2* dz;    // (zeta''(i) + 2 i khat_a zeta'(i)) exp(i khat_a x_a(i))
+    const float4* zd;    // zt and dz of index i side by side: one 16-byte load per cell
     const float2* dlo;   // spectral-derivative row for the low plane
     const float2* dhi;   // spectral-derivative row for the high plane
 };

@@ -108,6 +108,7 @@ struct Fields {
     int nx, ny, nz;
     GMEM const float *kk, *gam;
     GMEM const float2 *tw, *zt, *dz, *dlo, *dhi;
+    GMEM const float4* zd;
     GMEM const float2 *zt_x, *dz_x, *zt_y, *dz_y;
     GMEM const float *gam_x, *gam_y;
     GMEM const float2* sigma_tab;
@@ -151,6 +152,7 @@ __device__ __forceinline__ Fields fields(const PassArgs& a) {
     f.tw = gmem(a.ax[AXIS].tw);
     f.zt = gmem(a.ax[AXIS].zt);
     f.dz = gmem(a.ax[AXIS].dz);
+    f.zd = gmem(a.ax[AXIS].zd);
     f.dlo = gmem(a.ax[AXIS].dlo);
     f.dhi = gmem(a.ax[AXIS].dhi);
     f.zt_x = gmem(a.ax[0].zt);
@@ -588,8 +590,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                 });
             } else {
                 GMEM const float* __restrict__ t_gam = f.gam;
-                GMEM const float2* __restrict__ t_zt = f.zt;
-                GMEM const float2* __restrict__ t_dz = f.dz;
+                GMEM const float4* __restrict__ t_zd = f.zd;
                 const int px = geo.px, py = geo.py;
                 const float2 Zx = f.zt_x[px], Dx = f.dz_x[px];
                 const float2 Zy = f.zt_y[py], Dy = f.dz_y[py];
@@ -633,7 +634,8 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
                         float2 q = Lt;
                         if constexpr (!POTX) q = cadd(q, cscale(raw[n1], vv[n1]));
                         if constexpr (!ADJ) {
-                            const float2 s = cadd(cmul(SA, t_zt[z]), cmul(SB, t_dz[z]));
+                            const float4 zd = t_zd[z];
+                            const float2 s = cadd(cmul(SA, make_float2(zd.x, zd.y)), cmul(SB, make_float2(zd.z, zd.w)));
                             q = cadd(q, cmul(sigma, s));
                         }
                         const float g = gxy * t_gam[z];
