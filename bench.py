@@ -34,22 +34,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "779a9c0f0bded3e2a6560644bd81fc12f4d9d4989141155e7443c824a6bc7f36"
+TRAFFIC_SRC_SHA256 = "cf30ede662aa5f88fae1072bbd06381248d9fd091df0c275ba755c238a4f8101"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 8, 20, 16, 0, 0): (33266, 32001), (160, 8, 20, 16, 0, 1): (64167, 32000), (160, 8, 20, 16, 0, 2): (96285, 32000),
-    (160, 10, 16, 8, 0, 0): (33389, 32000), (160, 10, 16, 8, 0, 1): (64174, 32099), (160, 10, 16, 8, 0, 2): (96302, 32078),
-    (160, 10, 16, 16, 0, 0): (34407, 32000), (160, 10, 16, 16, 0, 1): (64170, 32000), (160, 10, 16, 16, 0, 2): (96277, 32000),
-    (160, 10, 16, 32, 0, 0): (34845, 32000), (160, 10, 16, 32, 0, 1): (64168, 32000), (160, 10, 16, 32, 0, 2): (96293, 32000),
-    (160, 16, 10, 16, 0, 0): (33500, 32000), (160, 16, 10, 16, 0, 1): (64186, 32000), (160, 16, 10, 16, 0, 2): (96320, 32000),
-    (160, 20, 8, 16, 0, 0): (32667, 32000), (160, 20, 8, 16, 0, 1): (64193, 32000), (160, 20, 8, 16, 0, 2): (96330, 32000),
-    (288, 12, 24, 8, 0, 0): (190121, 186625), (288, 12, 24, 8, 0, 1): (373549, 192555), (288, 12, 24, 8, 0, 2): (768964, 188401),
-    (288, 12, 24, 8, 4, 0): (190714, 186624), (288, 12, 24, 8, 4, 1): (374086, 193860), (288, 12, 24, 8, 4, 2): (765849, 188401),
-    (288, 12, 24, 16, 0, 0): (188167, 186624), (288, 12, 24, 16, 0, 1): (373485, 186624), (288, 12, 24, 16, 0, 2): (560240, 186624),
-    (288, 16, 18, 16, 0, 0): (187479, 186624), (288, 16, 18, 16, 0, 1): (373477, 186624), (288, 16, 18, 16, 0, 2): (560266, 186624),
-    (288, 16, 18, 32, 0, 0): (188586, 186642), (288, 16, 18, 32, 0, 1): (373557, 186624), (288, 16, 18, 32, 0, 2): (560283, 186624),
-    (288, 18, 16, 16, 0, 0): (187467, 186624), (288, 18, 16, 16, 0, 1): (373499, 186624), (288, 18, 16, 16, 0, 2): (560259, 186624),
-    (288, 24, 12, 8, 0, 0): (187438, 186624), (288, 24, 12, 8, 0, 1): (373514, 191183), (288, 24, 12, 8, 0, 2): (644172, 186637),
-    (288, 24, 12, 16, 0, 0): (187339, 186626), (288, 24, 12, 16, 0, 1): (373487, 186624), (288, 24, 12, 16, 0, 2): (560295, 186624),
+    (160, 8, 20, 16, 0, 0): (33380, 32000), (160, 8, 20, 16, 0, 1): (64170, 32000), (160, 8, 20, 16, 0, 2): (96271, 32000),
+    (160, 10, 16, 8, 0, 0): (33305, 32000), (160, 10, 16, 8, 0, 1): (64180, 32151), (160, 10, 16, 8, 0, 2): (96293, 32122),
+    (160, 10, 16, 16, 0, 0): (34432, 32000), (160, 10, 16, 16, 0, 1): (64167, 32000), (160, 10, 16, 16, 0, 2): (96287, 32000),
+    (160, 10, 16, 32, 0, 0): (34636, 32000), (160, 10, 16, 32, 0, 1): (64170, 32000), (160, 10, 16, 32, 0, 2): (96300, 32000),
+    (160, 16, 10, 16, 0, 0): (33623, 32000), (160, 16, 10, 16, 0, 1): (64183, 32000), (160, 16, 10, 16, 0, 2): (96326, 32000),
+    (160, 20, 8, 16, 0, 0): (32659, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96328, 32000),
+    (288, 12, 24, 8, 0, 0): (190315, 186625), (288, 12, 24, 8, 0, 1): (373549, 192389), (288, 12, 24, 8, 0, 2): (763735, 188121),
+    (288, 12, 24, 8, 4, 0): (190893, 186624), (288, 12, 24, 8, 4, 1): (374064, 193861), (288, 12, 24, 8, 4, 2): (759644, 188182),
+    (288, 12, 24, 16, 0, 0): (188492, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560243, 186624),
+    (288, 16, 18, 16, 0, 0): (187582, 186624), (288, 16, 18, 16, 0, 1): (373487, 186624), (288, 16, 18, 16, 0, 2): (560244, 186624),
+    (288, 16, 18, 32, 0, 0): (188903, 186644), (288, 16, 18, 32, 0, 1): (373543, 186624), (288, 16, 18, 32, 0, 2): (560275, 186624),
+    (288, 18, 16, 16, 0, 0): (187591, 186624), (288, 18, 16, 16, 0, 1): (373500, 186624), (288, 18, 16, 16, 0, 2): (560265, 186624),
+    (288, 24, 12, 8, 0, 0): (187548, 186624), (288, 24, 12, 8, 0, 1): (373513, 190759), (288, 24, 12, 8, 0, 2): (641564, 186635),
+    (288, 24, 12, 16, 0, 0): (187349, 186627), (288, 24, 12, 16, 0, 1): (373488, 186624), (288, 24, 12, 16, 0, 2): (560285, 186624),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053_amd/csrc/pass_variants.hpp",
                   "paper_2403_04053_amd/csrc/dft.hpp", "paper_2403_04053_amd/csrc/internal.hpp")
@@ -64,8 +64,8 @@ SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
 # the sources whose SHA-256 is FDTD_TRAFFIC_SRC_SHA256.
-FDTD_TRAFFIC_SRC_SHA256 = "50d9d8527c848b4a26a55a77004f61c05a952424927c6716e8ebe7941d2b111d"
-FDTD_TRAFFIC_KIB = {160: (105820, 32000)}
+FDTD_TRAFFIC_SRC_SHA256 = "d5187277b6240dcdf890cd190e5854694aa3d4825e1b2721c82b8d95b56c0c03"
+FDTD_TRAFFIC_KIB = {160: (105996, 32000)}
 FDTD_SOURCES = ("paper_2403_04053_amd/csrc/fdtd.hip", "paper_2403_04053_amd/csrc/dft.hpp",
                 "paper_2403_04053_amd/csrc/internal.hpp")
 
