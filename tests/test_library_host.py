@@ -151,3 +151,20 @@ def test_binding_argument_kinds_match_the_header():
         want = [kind_c(p) for p in decls[name]]
         got = [kind_py(t) for t in args]
         assert got == want, (name, got, want)
+
+
+def test_tile_variants_cover_every_workload_length():
+    """pstd_tile_variants (host only) lists (N1, N2, pencils, M1) for every
+    compiled length: N1 * N2 = N, a stage-B split M1 divides N2 with both M1
+    and N2 / M1 dividing N1, and the subdomain length has a segmented
+    instance; lengths without a compiled pass list nothing."""
+    for n in (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192, 256, 288):
+        shapes = lib_mod.pstd_tile_variants(n)
+        assert shapes, n
+        for n1, n2, pencils, m1 in shapes:
+            assert n1 * n2 == n and pencils in (8, 16, 32, 64), (n, n1, n2, pencils)
+            if m1:
+                assert n2 % m1 == 0 and n1 % m1 == 0 and n1 % (n2 // m1) == 0, (n, n1, n2, m1)
+    assert any(m1 for *_, m1 in lib_mod.pstd_tile_variants(288))
+    assert lib_mod.pstd_tile_variants(64, segmented=True)
+    assert lib_mod.pstd_tile_variants(72) == [] and lib_mod.pstd_tile_variants(290) == []
