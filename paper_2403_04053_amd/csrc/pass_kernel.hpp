@@ -333,7 +333,28 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         const TileGeo geo = tile_geo<N, P, AXIS, SEG>(f, tile, pA, activeA);
         float2 raw[N1];
         load_tile<N, N1, N2, SEG, NTL && AXIS == 2>(psi, geo, n2, raw);
+        // the y pass's epilogue operand (L from the x pass), the same elements
+        // the epilogue writes, read by the thread that writes them.  Issued
+        // once stage A is done, the field loads have the memory system to
+        // themselves and L's latency still hides behind stage B and the
+        // inverse stage A (issued with the field loads it cost 2-7 %); the
+        // short pencils of segmented passes take it with the field loads
+        // (the other way round there cost 2-3 %)
         float2 Lin[N1];
+        auto load_L = [&]() {
+            if constexpr (AXIS == 1) {
+                const int C = SEG ? f.seg_core : N;
+                const int H = SEG ? f.seg_halo : 0;
+                unroll<N1>([&](auto i) {
+                    constexpr int n1 = decltype(i)::value;
+                    const int e = n2 + N2 * n1;
+                    Lin[n1] = make_float2(0.f, 0.f);
+                    if (geo.valid && e < N && (!SEG || (e >= H && e < H + C)))
+                        Lin[n1] = f.L[geo.base + (int64_t)e * geo.estride];
+                });
+            }
+        };
+        if constexpr (SEG) load_L();
         GMEM const float* __restrict__ wloc = f.wloc;
         const int plane_lo = f.plane_lo, plane_hi = f.plane_hi;
         float2 v[N1];
@@ -380,23 +401,7 @@ __global__ __launch_bounds__(P * (N1 > N2 ? N1 : N2)) void pass_kernel(PassArgs 
         // in stage A (which skip the reload below) do not keep them alive
         // through stage B
         unroll<N1>([&](auto i) { v[decltype(i)::value] = make_float2(0.f, 0.f); });
-        // the y pass's epilogue operand (L from the x pass), issued once stage
-        // A is done: the field loads then have the memory system to
-        // themselves, and L's latency still hides behind stage B and the
-        // inverse stage A (issued with the field loads it cost 2-7 %); the
-        // same elements the epilogue writes, read by the thread that writes
-        // them
-        if constexpr (AXIS == 1) {
-            const int C = SEG ? f.seg_core : N;
-            const int H = SEG ? f.seg_halo : 0;
-            unroll<N1>([&](auto i) {
-                constexpr int n1 = decltype(i)::value;
-                const int e = n2 + N2 * n1;
-                Lin[n1] = make_float2(0.f, 0.f);
-                if (geo.valid && e < N && (!SEG || (e >= H && e < H + C)))
-                    Lin[n1] = f.L[geo.base + (int64_t)e * geo.estride];
-            });
-        }
+        if constexpr (!SEG) load_L();
 
         __syncthreads();
 
