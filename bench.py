@@ -34,22 +34,22 @@ STEP_BYTES = 28  # whole step: read psi^{n-1}, psi^n, V; write psi^{n+1}
 # FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources whose
 # SHA-256 is TRAFFIC_SRC_SHA256; otherwise traffic is reported as null.  Key:
 # (N, N1, N2, pencils per workgroup, stage-B split M1, axis).
-TRAFFIC_SRC_SHA256 = "cf30ede662aa5f88fae1072bbd06381248d9fd091df0c275ba755c238a4f8101"
+TRAFFIC_SRC_SHA256 = "078e2b9d4f8c41e42c9823dd5d69562aecef325df1aa1ad62c78b466b763c044"
 TRAFFIC_KIB = {  # (fetch, write) KiB per launch
-    (160, 8, 20, 16, 0, 0): (33380, 32000), (160, 8, 20, 16, 0, 1): (64170, 32000), (160, 8, 20, 16, 0, 2): (96271, 32000),
-    (160, 10, 16, 8, 0, 0): (33305, 32000), (160, 10, 16, 8, 0, 1): (64180, 32151), (160, 10, 16, 8, 0, 2): (96293, 32122),
-    (160, 10, 16, 16, 0, 0): (34432, 32000), (160, 10, 16, 16, 0, 1): (64167, 32000), (160, 10, 16, 16, 0, 2): (96287, 32000),
-    (160, 10, 16, 32, 0, 0): (34636, 32000), (160, 10, 16, 32, 0, 1): (64170, 32000), (160, 10, 16, 32, 0, 2): (96300, 32000),
-    (160, 16, 10, 16, 0, 0): (33623, 32000), (160, 16, 10, 16, 0, 1): (64183, 32000), (160, 16, 10, 16, 0, 2): (96326, 32000),
-    (160, 20, 8, 16, 0, 0): (32659, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96328, 32000),
-    (288, 12, 24, 8, 0, 0): (190315, 186625), (288, 12, 24, 8, 0, 1): (373549, 192389), (288, 12, 24, 8, 0, 2): (763735, 188121),
-    (288, 12, 24, 8, 4, 0): (190893, 186624), (288, 12, 24, 8, 4, 1): (374064, 193861), (288, 12, 24, 8, 4, 2): (759644, 188182),
-    (288, 12, 24, 16, 0, 0): (188492, 186624), (288, 12, 24, 16, 0, 1): (373486, 186624), (288, 12, 24, 16, 0, 2): (560243, 186624),
-    (288, 16, 18, 16, 0, 0): (187582, 186624), (288, 16, 18, 16, 0, 1): (373487, 186624), (288, 16, 18, 16, 0, 2): (560244, 186624),
-    (288, 16, 18, 32, 0, 0): (188903, 186644), (288, 16, 18, 32, 0, 1): (373543, 186624), (288, 16, 18, 32, 0, 2): (560275, 186624),
-    (288, 18, 16, 16, 0, 0): (187591, 186624), (288, 18, 16, 16, 0, 1): (373500, 186624), (288, 18, 16, 16, 0, 2): (560265, 186624),
-    (288, 24, 12, 8, 0, 0): (187548, 186624), (288, 24, 12, 8, 0, 1): (373513, 190759), (288, 24, 12, 8, 0, 2): (641564, 186635),
-    (288, 24, 12, 16, 0, 0): (187349, 186627), (288, 24, 12, 16, 0, 1): (373488, 186624), (288, 24, 12, 16, 0, 2): (560285, 186624),
+    (160, 8, 20, 16, 0, 0): (33260, 32001), (160, 8, 20, 16, 0, 1): (64168, 32000), (160, 8, 20, 16, 0, 2): (96273, 32000),
+    (160, 10, 16, 8, 0, 0): (33374, 32000), (160, 10, 16, 8, 0, 1): (64211, 32172), (160, 10, 16, 8, 0, 2): (96290, 32084),
+    (160, 10, 16, 16, 0, 0): (34391, 32000), (160, 10, 16, 16, 0, 1): (64167, 32000), (160, 10, 16, 16, 0, 2): (96287, 32000),
+    (160, 10, 16, 32, 0, 0): (34676, 32000), (160, 10, 16, 32, 0, 1): (64170, 32000), (160, 10, 16, 32, 0, 2): (96299, 32000),
+    (160, 16, 10, 16, 0, 0): (33638, 32000), (160, 16, 10, 16, 0, 1): (64183, 32000), (160, 16, 10, 16, 0, 2): (96319, 32000),
+    (160, 20, 8, 16, 0, 0): (32659, 32000), (160, 20, 8, 16, 0, 1): (64194, 32000), (160, 20, 8, 16, 0, 2): (96327, 32000),
+    (288, 12, 24, 8, 0, 0): (190064, 186625), (288, 12, 24, 8, 0, 1): (373548, 192534), (288, 12, 24, 8, 0, 2): (753359, 188168),
+    (288, 12, 24, 8, 4, 0): (190616, 186625), (288, 12, 24, 8, 4, 1): (374073, 194021), (288, 12, 24, 8, 4, 2): (751713, 188196),
+    (288, 12, 24, 16, 0, 0): (188175, 186624), (288, 12, 24, 16, 0, 1): (373482, 186624), (288, 12, 24, 16, 0, 2): (560241, 186624),
+    (288, 16, 18, 16, 0, 0): (187502, 186624), (288, 16, 18, 16, 0, 1): (373487, 186624), (288, 16, 18, 16, 0, 2): (560242, 186624),
+    (288, 16, 18, 32, 0, 0): (188611, 186641), (288, 16, 18, 32, 0, 1): (373545, 186624), (288, 16, 18, 32, 0, 2): (560284, 186624),
+    (288, 18, 16, 16, 0, 0): (187467, 186624), (288, 18, 16, 16, 0, 1): (373501, 186624), (288, 18, 16, 16, 0, 2): (560263, 186624),
+    (288, 24, 12, 8, 0, 0): (187454, 186624), (288, 24, 12, 8, 0, 1): (373513, 190755), (288, 24, 12, 8, 0, 2): (638001, 186635),
+    (288, 24, 12, 16, 0, 0): (187334, 186626), (288, 24, 12, 16, 0, 1): (373488, 186624), (288, 24, 12, 16, 0, 2): (560285, 186624),
 }
 KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053_amd/csrc/pass_variants.hpp",
                   "paper_2403_04053_amd/csrc/dft.hpp", "paper_2403_04053_amd/csrc/internal.hpp")
