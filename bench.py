@@ -58,8 +58,8 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053
 # The shell DFT of the spherical surface (r = 5, 64 x 128 nodes) on the same
 # workload, per launch of a pair of steps, valid for the sphere sources whose
 # SHA-256 is SHELL_TRAFFIC_SRC_SHA256.
-SHELL_TRAFFIC_SRC_SHA256 = "5a92eeda1d88c2f6d64b0f6a3a6ab22dd5923568c77e4abb8434aa4c81a7fa9f"
-SHELL_TRAFFIC_KIB = (18327, 10505)
+SHELL_TRAFFIC_SRC_SHA256 = "5e20221b4835ee069a7f36e935368b42bb286d7c009a32436967d83388de6960"
+SHELL_TRAFFIC_KIB = (13072, 5252)
 SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 
 # The same for the FDTD kernel on the 160^3 grid (key: grid edge), valid for
