@@ -58,7 +58,7 @@ KERNEL_SOURCES = ("paper_2403_04053_amd/csrc/pass_kernel.hpp", "paper_2403_04053
 # The shell DFT of the spherical surface (r = 5, 64 x 128 nodes) on the same
 # workload, per launch of a pair of steps, valid for the sphere sources whose
 # SHA-256 is SHELL_TRAFFIC_SRC_SHA256.
-SHELL_TRAFFIC_SRC_SHA256 = "5e20221b4835ee069a7f36e935368b42bb286d7c009a32436967d83388de6960"
+SHELL_TRAFFIC_SRC_SHA256 = "096c8ff0f16b3049b5c82c4e5df49a22cd4d03da7f60d8548781d006e4618a7f"
 SHELL_TRAFFIC_KIB = (13072, 5252)
 SHELL_SOURCES = ("paper_2403_04053_amd/csrc/sphere.hip",)
 

@@ -2,10 +2,9 @@
 // paper integrates over a box).  Nodes: Gauss-Legendre in cos(theta) times
 // uniform phi on a sphere centred at the origin.  Every window step
 // accumulates, in FP64, the DFT of psi (Eq. psiphasor) on the shell of grid
-// cells that the 8-point Lagrange stencils around the nodes touch (with a
-// compensation term in the staged sums of pulsed runs).  After the run the
-// node values and normal derivatives come from the separable Lagrange
-// interpolant of the scattered-field phasors (the incident
+// cells that the 8-point Lagrange stencils around the nodes touch.  After
+// the run the node values and normal derivatives come from the separable
+// Lagrange interpolant of the scattered-field phasors (the incident
 // part zeta exp(i khat . x) is removed exactly), and the Kirchhoff integral
 // with G = exp(ikR)/(4 pi R) is summed over the nodes, in FP64.
 #include <hip/hip_runtime.h>
@@ -35,8 +34,9 @@ struct SphereState {
     double2* inc = nullptr;       // zeta exp(i khat . x) per shell slot
     double inc_max = 0;           // largest |zeta| on the shell (0: scattered field only)
     int nk = 1;                   // wavenumbers with a phasor (more than one with a pulse)
-    double2* sum = nullptr;       // running DFT [wavenumber][slot], value and compensation
-    double2* comp = nullptr;
+    double2* sum = nullptr;       // running DFT [wavenumber][slot]
+    double2* comp = nullptr;      // same layout, all zero: the kernels keep plain FP64 sums (the node
+                                  // interpolation adds it, the saved state carries it)
     float2* stage = nullptr;      // [kStageSteps][slot]: psi of the steps of a launch group (pulsed runs)
     double2* phasor = nullptr;    // [2][node]: psi, d_n psi
 };
@@ -95,13 +95,6 @@ int lagrange(double u, double* L, double* dL) {
     return i0;
 }
 
-__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
-    const double t = s + x;
-    if (fabs(s) >= fabs(x)) c += (s - t) + x;
-    else c += (x - t) + s;
-    s = t;
-}
-
 // Eq. psiphasor on the shell cells for `count` (1 or 2) consecutive steps
 // ending at ctr[0] + koff, each with its own weight and window flag.  Run
 // before that step's z pass, when both psi^{n-1} and psi^n are in place, so
@@ -151,29 +144,34 @@ __global__ void shell_stage_kernel(const int64_t* __restrict__ ctr, int koff, co
 
 // Eq. psiphasor for the `count` staged steps ctr[0] .. ctr[0] + count - 1 of
 // a launch group at each of nk wavenumbers, added in step order: one
-// read-modify-write of the FP64 sums per group instead of per pair
+// read-modify-write of the FP64 sums per group instead of per pair.  The
+// group's staged values are read once, for every wavenumber; plain FP64
+// sums, as in shell_dft_kernel (the compensation array stays zero).
 __global__ void shell_flush_kernel(const int64_t* __restrict__ ctr, int count, const int* __restrict__ dft_tab,
                                    const double2* __restrict__ w_tab, int64_t wstride, int nk,
-                                   const float2* __restrict__ stage, int64_t n, double2* __restrict__ sum,
-                                   double2* __restrict__ comp) {
+                                   const float2* __restrict__ stage, int64_t n, double2* __restrict__ sum) {
     const int64_t first = ctr[0];
     bool any = false;
     for (int k = 0; k < count; ++k) any |= first + k < ctr[1] && dft_tab[first + k] != 0;
     if (!any) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    // slots k < count lie inside the ring; a slot whose step is past the run's
+    // end was not written this group and is skipped below
+    float2 v[kStageSteps];
+#pragma unroll
+    for (int k = 0; k < kStageSteps; ++k) v[k] = k < count ? stage[k * n + c] : make_float2(0.f, 0.f);
     for (int f = 0; f < nk; ++f) {
-        double2 s = sum[f * n + c], e = comp[f * n + c];
-        for (int k = 0; k < count; ++k) {
+        double2 s = sum[f * n + c];
+#pragma unroll
+        for (int k = 0; k < kStageSteps; ++k) {
             const int64_t m = first + k;
-            if (m >= ctr[1] || !dft_tab[m]) continue;
-            const float2 v = stage[k * n + c];
+            if (k >= count || m >= ctr[1] || !dft_tab[m]) continue;
             const double2 w = w_tab[f * wstride + m];
-            neumaier(s.x, e.x, w.x * v.x - w.y * v.y);
-            neumaier(s.y, e.y, w.x * v.y + w.y * v.x);
+            s.x += w.x * v[k].x - w.y * v[k].y;
+            s.y += w.x * v[k].y + w.y * v[k].x;
         }
         sum[f * n + c] = s;
-        comp[f * n + c] = e;
     }
 }
 
@@ -462,7 +460,7 @@ hipError_t sphere_launch_flush(const pstd_solver* s, int count, hipStream_t stre
     if (!sp || !sp->stage || sp->n_shell == 0) return hipSuccess;
     if (count < 1 || count > kStageSteps) return hipErrorInvalidValue;
     hipLaunchKernelGGL(shell_flush_kernel, dim3((unsigned)((sp->n_shell + 255) / 256)), dim3(256), 0, stream, s->ctr,
-                       count, s->dft_tab, s->w_tab, s->tab_cap, sp->nk, sp->stage, sp->n_shell, sp->sum, sp->comp);
+                       count, s->dft_tab, s->w_tab, s->tab_cap, sp->nk, sp->stage, sp->n_shell, sp->sum);
     return hipGetLastError();
 }
 
